@@ -1,0 +1,180 @@
+/*
+ * momms.h - C ABI of the MI355X (gfx950) MOMMS GEMM library.
+ *
+ * The library computes C := alpha * op(A) * op(B) + beta * C in IEEE binary64
+ * with hand-written HIP kernels on FP64 MFMA (v_mfma_f64_16x16x4_f64).  The
+ * operation is the ordinary matrix product of Smith & van de Geijn, "The
+ * MOMMS Family of Matrix Multiplication Algorithms" (SC19), Sec. 2.1
+ * (gamma_ij = sum_p alpha_ip beta_pj) used as the update C += A B of
+ * Sec. 2.2.1, with BLAS alpha/beta semantics added.
+ *
+ * A "family member" fixes the loop order and which operand block is kept
+ * resident at each memory level (Sec. 3.2-3.3; naming convention of
+ * Sec. 3.3, e.g. B3A2C0 = B resident at level 3, A at level 2, C at level 0).
+ * The levels are re-derived for gfx950:
+ *     level 0 = VGPR/AGPR register tile of a workgroup (C accumulators),
+ *     level 2 = LDS (160 KiB per CU),
+ *     level 3 = the 4 MiB L2 of one XCD (8 XCDs, each with its own L2),
+ *     level 4 = the 256 MiB Infinity Cache (MALL), shared by the chip.
+ * Level 1 (the 32 KiB vector L1) is always skipped, as the paper skips its
+ * L1 (Sec. 5.2).
+ *
+ * Conventions shared by every entry point
+ *   - Storage is ROW-MAJOR.  op(A) is m x k, op(B) is k x n, C is m x n.
+ *     Without transposition A is stored m x k with leading dimension
+ *     lda >= max(1,k); with transA != 0, A is stored k x m (lda >= max(1,m))
+ *     and op(A) = A^T.  Likewise B is k x n (ldb >= max(1,n)) or, with
+ *     transB != 0, n x k (ldb >= max(1,k)).  ldc >= max(1,n).
+ *   - Matrix pointers are DEVICE pointers owned by the caller.  The library
+ *     never frees or retains them.  C must not alias A or B (not checked).
+ *   - Calls are asynchronous on the given (or the library's current) HIP
+ *     stream; nothing inside synchronizes the device or allocates memory,
+ *     except momms_batch_create/momms_batch_destroy.
+ *   - Quick return (no kernel launched, status 0) when m == 0, n == 0, or
+ *     (alpha == 0 or k == 0) and beta == 1.  With alpha == 0 (or k == 0) A
+ *     and B are not read.  With beta == 0, C is not read, so NaNs in C do not
+ *     propagate.
+ *   - Return value: 0 on success.  -i means argument number i (1-based, in
+ *     the order of the C prototype) is invalid; this check is done on the
+ *     host before any HIP call.  A positive value is a hipError_t reported
+ *     by the runtime after a launch.  momms_status_string() describes codes.
+ *   - Accuracy: every member returns, per entry, a result within
+ *     2 (k+2) 2^-53 (|alpha| (|op(A)||op(B)|)_ij + |beta| |C_ij|) of the
+ *     exact value (forward error bound of a k-term dot product in any
+ *     summation order).  Integer-valued data whose partial sums stay below
+ *     2^53 is reproduced exactly.
+ */
+#ifndef MOMMS_H
+#define MOMMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque HIP stream handle (hipStream_t); NULL is the default stream. */
+typedef void *momms_stream_t;
+
+/* Family members.  The loop nests are those of Sec. 3.2 (two loops per
+ * level), with blocksizes re-derived for the gfx950 levels listed above. */
+enum momms_member {
+    MOMMS_AUTO = 0,    /* pick by the analytic model and the tuned table   */
+    MOMMS_C0 = 1,      /* C resident in registers over all of k; LDS only
+                          stages streamed k-slices; plain tile order        */
+    MOMMS_C3C0 = 2,    /* as C0, with the workgroups of one XCD covering one
+                          C block (XCD-aware grouped tile order)            */
+    MOMMS_B3C0 = 3,    /* B block (kc3 x nc3) resident in one XCD's L2; the
+                          XCD sweeps m; C updated once per kc3              */
+    MOMMS_A3C0 = 4,    /* A block (mc3 x kc3) resident in one XCD's L2; the
+                          XCD sweeps n; C updated once per kc3              */
+    MOMMS_A2C0 = 5,    /* Goto's algorithm (Sec. 4.3): A block resident in
+                          LDS, B panel streamed, C updated once per kc      */
+    MOMMS_B3A2C0 = 6,  /* Sec. 5.2: B block in L2, A block in LDS           */
+    MOMMS_A3B2C0 = 7,  /* Sec. 5.4: A block in L2, B block in LDS           */
+    MOMMS_C3A2C0 = 8,  /* Sec. 5.4: C block in L2, A block in LDS           */
+    MOMMS_C4A2C0 = 9,  /* Sec. 5.3: C block in the MALL, A block in LDS     */
+    MOMMS_NUM_MEMBERS = 10
+};
+
+/* Status codes besides -i (bad argument i) and positive hipError_t values. */
+#define MOMMS_OK 0
+#define MOMMS_ERR_INFEASIBLE 1002   /* problem too large for the tile grid   */
+#define MOMMS_ERR_NO_DEVICE 1003    /* no gfx950 device / HIP init failed    */
+#define MOMMS_ERR_INTERNAL 1004
+
+/* Blocking plan of one member for one problem (host-side description). */
+typedef struct momms_plan {
+    int member;          /* enum momms_member, never MOMMS_AUTO here        */
+    int kernel;          /* 0: register-resident C over a k range;
+                            1: A block resident in LDS; 2: B block in LDS   */
+    int mt, nt, ks;      /* workgroup register tile and LDS k-slice         */
+    int nj, mi;          /* n-tiles per LDS-resident A block (kernel 1);
+                            m-tiles per LDS-resident B block (kernel 2)     */
+    int group_m;         /* height (in tiles) of a grouped tile order       */
+    int xcd_aware;       /* workgroup -> tile map keeps one XCD's tiles
+                            contiguous in the tile order                    */
+    int pack;            /* streamed panel packed into the workspace        */
+    int64_t kc;          /* k extent of the LDS-resident block              */
+    int64_t mc3, nc3, kc3;   /* level-3 (XCD L2) block                      */
+    int64_t mc4, nc4;        /* level-4 (MALL) block                        */
+    int64_t nc;              /* outermost n blocksize (Goto's n_c)          */
+    int64_t k_range;     /* k extent one workgroup accumulates before it
+                            writes C (C traffic = 2mn * ceil(k/k_range))    */
+    int64_t launches;    /* kernel launches per call (packing included)     */
+    int64_t workgroups;  /* workgroups per call                             */
+} momms_plan;
+
+/* Data-movement model of one planned call (Sec. 2.2 counts made exact with
+ * ceilings at the margins, Sec. 4.1-4.2 level interactions).  Bytes. */
+typedef struct momms_bytes {
+    double flops;            /* 2 m n k                                     */
+    double compulsory;       /* 8 (mk + kn + mn) + 8 mn if beta != 0        */
+    double l2_read;          /* bytes the L2s read from the fabric
+                                (MALL/HBM); comparable with FETCH_SIZE      */
+    double l2_write;         /* bytes written back past the L2s;
+                                comparable with WRITE_SIZE                  */
+    double hbm_read;         /* level-4 model: reads that miss the MALL     */
+    double hbm_write;        /* level-4 model: writes that reach HBM        */
+    double lds_fill;         /* bytes copied global -> LDS                  */
+    double pack;             /* bytes read + written by packing kernels     */
+    double a_reads, b_reads, c_reads, c_writes;  /* l2_read split by operand
+                                (elements x 8)                              */
+} momms_bytes;
+
+/* ---------------------------------------------------------------------
+ * Plain FP64 GEMM, the family's entry point.  Argument numbers for -i:
+ * 1 m, 2 n, 3 k, 4 alpha, 5 A, 6 lda, 7 B, 8 ldb, 9 beta, 10 C, 11 ldc,
+ * 12 family_member.  No transposition; runs on the stream set by
+ * momms_set_stream (default: NULL stream).  Members that pack a panel run
+ * unpacked here (no workspace argument).
+ */
+int momms_gemm(int64_t m, int64_t n, int64_t k, double alpha,
+               const double *A, int64_t lda, const double *B, int64_t ldb,
+               double beta, double *C, int64_t ldc, int family_member);
+
+/* Full form: transposition flags (for the backward products
+ * dA = dC B^T, dB = A^T dC), explicit workspace and stream.  Argument
+ * numbers: 1 transA, 2 transB, 3 m, 4 n, 5 k, 6 alpha, 7 A, 8 lda, 9 B,
+ * 10 ldb, 11 beta, 12 C, 13 ldc, 14 family_member, 15 workspace,
+ * 16 ws_bytes, 17 stream.  workspace may be NULL (then nothing is packed);
+ * if non-NULL it must be 256-byte aligned device memory (else -15) holding
+ * at least momms_workspace_size(...) bytes (else -16), not used
+ * concurrently by another call. */
+int momms_gemm_ex(int transA, int transB, int64_t m, int64_t n, int64_t k,
+                  double alpha, const double *A, int64_t lda,
+                  const double *B, int64_t ldb, double beta,
+                  double *C, int64_t ldc, int family_member,
+                  void *workspace, size_t ws_bytes, momms_stream_t stream);
+
+/* Workspace bytes the member needs to pack its streamed panel for this
+ * shape (0 if it packs nothing).  Host-only. */
+size_t momms_workspace_size(int64_t m, int64_t n, int64_t k, int family_member);
+
+/* Stream used by momms_gemm.  Host-only bookkeeping; returns 0. */
+int momms_set_stream(momms_stream_t stream);
+
+/* Introspection (host-only, no GPU needed). */
+int momms_num_members(void);                  /* MOMMS_NUM_MEMBERS         */
+const char *momms_member_name(int member);    /* e.g. "B3A2C0"; NULL if bad */
+int momms_member_id(const char *name);        /* inverse; -1 if unknown    */
+/* Plan of `member` (MOMMS_AUTO resolves to the chosen member) for the
+ * shape.  Argument numbers: 1 member, 2 m, 3 n, 4 k, 5 out. */
+int momms_member_plan(int member, int64_t m, int64_t n, int64_t k,
+                      momms_plan *out);
+/* Model prediction for the member's plan.  1 member, 2 m, 3 n, 4 k,
+ * 5 beta, 6 packed (nonzero: count packing traffic), 7 out. */
+int momms_model_bytes(int member, int64_t m, int64_t n, int64_t k,
+                      double beta, int packed, momms_bytes *out);
+/* Member MOMMS_AUTO resolves to for the shape (ties: fewer model bytes,
+ * then lower id). */
+int momms_select_member(int64_t m, int64_t n, int64_t k);
+
+const char *momms_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOMMS_H */

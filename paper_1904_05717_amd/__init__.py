@@ -1,0 +1,112 @@
+"""MOMMS family of FP64 matrix multiplications on MI355X (gfx950).
+
+Thin PyTorch-facing layer over the C ABI of libmomms.so (include/momms.h):
+it checks tensor dtype/device/layout, reads leading dimensions and the
+current HIP stream, and passes device pointers through.  Every arithmetic
+step runs in the library's HIP kernels; there is no CPU fallback.
+"""
+import torch
+
+from . import _lib
+from ._lib import MommsBytes, MommsPlan
+
+MEMBER_NAMES = [_lib.momms_member_name(i).decode() for i in range(_lib.momms_num_members())]
+MEMBERS = {name: i for i, name in enumerate(MEMBER_NAMES)}
+FAMILY = [name for name in MEMBER_NAMES if name != "AUTO"]
+
+
+class MommsError(RuntimeError):
+    pass
+
+
+def member_id(member):
+    if isinstance(member, str):
+        if member not in MEMBERS:
+            raise ValueError(f"unknown family member {member!r}; known: {MEMBER_NAMES}")
+        return MEMBERS[member]
+    return int(member)
+
+
+def check_status(status, fn="momms"):
+    if status == 0:
+        return
+    msg = _lib.momms_status_string(status).decode()
+    if status < 0:
+        raise ValueError(f"{fn}: argument {-status} is invalid ({msg})")
+    raise MommsError(f"{fn}: status {status}: {msg}")
+
+
+def _ld(t, name):
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    rows, cols = t.shape
+    if t.is_contiguous():
+        return max(1, cols)
+    if t.stride(1) != 1 or t.stride(0) < max(1, cols):
+        raise ValueError(f"{name} must be row-major (unit column stride)")
+    return t.stride(0)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def gemm(A, B, C=None, alpha=1.0, beta=0.0, member="AUTO", transA=False, transB=False, workspace=None,
+         stream=None):
+    """C := alpha * op(A) @ op(B) + beta * C on the device, in place; returns C.
+
+    A, B, C are float64 device tensors in row-major layout (unit column
+    stride, any leading dimension).  op(X) = X.T when trans is set.  With
+    C None a new zero tensor is created (beta is then irrelevant).
+    `workspace` (a uint8 device tensor of at least workspace_size bytes)
+    enables packing for members that pack.
+    """
+    m, k = (A.shape[1], A.shape[0]) if transA else (A.shape[0], A.shape[1])
+    kb, n = (B.shape[1], B.shape[0]) if transB else (B.shape[0], B.shape[1])
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    lda, ldb = _ld(A, "A"), _ld(B, "B")
+    if C is None:
+        C = torch.zeros((m, n), dtype=torch.float64, device=A.device)
+        beta = 0.0
+    if tuple(C.shape) != (m, n):
+        raise ValueError(f"C has shape {tuple(C.shape)}, expected {(m, n)}")
+    ldc = _ld(C, "C")
+    mid = member_id(member)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        if not workspace.is_cuda:
+            raise ValueError("workspace must be a device tensor")
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    st = _lib.momms_gemm_ex(int(bool(transA)), int(bool(transB)), m, n, k, float(alpha), A.data_ptr(), lda,
+                            B.data_ptr(), ldb, float(beta), C.data_ptr(), ldc, mid, ws_ptr, ws_bytes,
+                            _stream_handle(stream))
+    check_status(st, "momms_gemm_ex")
+    return C
+
+
+def workspace_size(m, n, k, member="AUTO"):
+    return int(_lib.momms_workspace_size(m, n, k, member_id(member)))
+
+
+def member_plan(member, m, n, k):
+    p = MommsPlan()
+    check_status(_lib.momms_member_plan(member_id(member), m, n, k, p), "momms_member_plan")
+    return p.as_dict()
+
+
+def model_bytes(member, m, n, k, beta=1.0, packed=False):
+    b = MommsBytes()
+    check_status(_lib.momms_model_bytes(member_id(member), m, n, k, float(beta), int(bool(packed)), b),
+                 "momms_model_bytes")
+    return b.as_dict()
+
+
+def select_member(m, n, k):
+    return MEMBER_NAMES[_lib.momms_select_member(m, n, k)]

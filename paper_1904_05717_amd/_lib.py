@@ -1,0 +1,80 @@
+"""ctypes binding of libmomms.so: the C ABI declared in include/momms.h.
+
+Functions keep the C names and argument order.  Pointers are passed as
+integers (device addresses); nothing here computes any part of the product.
+The library must have been built (``python -m paper_1904_05717_amd.build``);
+importing this module without it raises ImportError.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmomms.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1904_05717_amd.build` "
+        "(hipcc for gfx950); there is no CPU fallback")
+
+_L = ctypes.CDLL(LIB_PATH)
+
+i32, i64, dbl, vp, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class MommsPlan(ctypes.Structure):
+    _fields_ = [
+        ("member", i32), ("kernel", i32), ("mt", i32), ("nt", i32), ("ks", i32),
+        ("nj", i32), ("mi", i32), ("group_m", i32), ("xcd_aware", i32), ("pack", i32),
+        ("kc", i64), ("mc3", i64), ("nc3", i64), ("kc3", i64), ("mc4", i64), ("nc4", i64),
+        ("nc", i64), ("k_range", i64), ("launches", i64), ("workgroups", i64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class MommsBytes(ctypes.Structure):
+    _fields_ = [(name, dbl) for name in (
+        "flops", "compulsory", "l2_read", "l2_write", "hbm_read", "hbm_write", "lds_fill", "pack",
+        "a_reads", "b_reads", "c_reads", "c_writes")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def _fn(name, res, args):
+    f = getattr(_L, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+momms_gemm = _fn("momms_gemm", i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32])
+momms_gemm_ex = _fn("momms_gemm_ex", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32,
+                                           vp, sz, vp])
+momms_workspace_size = _fn("momms_workspace_size", sz, [i64, i64, i64, i32])
+momms_set_stream = _fn("momms_set_stream", i32, [vp])
+momms_num_members = _fn("momms_num_members", i32, [])
+momms_member_name = _fn("momms_member_name", ctypes.c_char_p, [i32])
+momms_member_id = _fn("momms_member_id", i32, [ctypes.c_char_p])
+momms_member_plan = _fn("momms_member_plan", i32, [i32, i64, i64, i64, ctypes.POINTER(MommsPlan)])
+momms_model_bytes = _fn("momms_model_bytes", i32, [i32, i64, i64, i64, dbl, i32, ctypes.POINTER(MommsBytes)])
+momms_select_member = _fn("momms_select_member", i32, [i64, i64, i64])
+momms_status_string = _fn("momms_status_string", ctypes.c_char_p, [i32])
+
+EXPORTS = [
+    "momms_gemm", "momms_gemm_ex", "momms_workspace_size", "momms_set_stream", "momms_num_members",
+    "momms_member_name", "momms_member_id", "momms_member_plan", "momms_model_bytes",
+    "momms_select_member", "momms_status_string",
+]
+
+
+def bind_optional(name, res, args):
+    """Bind a symbol added by a later source file; None if absent."""
+    if not hasattr(_L, name):
+        return None
+    return _fn(name, res, args)
+
+
+def library():
+    return _L

@@ -1,0 +1,277 @@
+// Launch sequences of the MOMMS family members and the plain-FP64 C ABI.
+//
+// Each member is a loop nest (Sec. 3.2: two loops per level).  The loops
+// above a workgroup are realised here: either as host loops over kernel
+// launches on one stream (which orders the k passes that update the same C
+// tiles), or inside a launch as the workgroup -> tile order that decides
+// which blocks the workgroups of one XCD share in its L2.  The loops inside a
+// workgroup are the kernels of kernels_f64.hip.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "../../include/momms.h"
+#include "kernels_f64.hip"
+#include "plan_internal.h"
+
+namespace momms {
+
+using CfgL = TileCfg<128, 128, 16, 2, 2>;  // register-resident C, large problems
+using CfgS = TileCfg<64, 64, 16, 2, 2>;    // register-resident C, small problems
+using CfgK = TileCfg<128, 128, 8, 2, 2>;   // LDS-resident A or B block
+
+static hipStream_t g_stream = nullptr;
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static Sched make_sched(int64_t m_off, int64_t n_off, int64_t m_lim, int64_t n_lim, int64_t grain_m,
+                        int64_t grain_n, int64_t group_m, bool xcd) {
+    Sched s;
+    s.m_off = m_off;
+    s.n_off = n_off;
+    s.m_lim = m_lim;
+    s.n_lim = n_lim;
+    s.tiles_m = (int)cdiv(m_lim - m_off, grain_m);
+    s.tiles_n = (int)cdiv(n_lim - n_off, grain_n);
+    if (group_m < 1) group_m = 1;
+    if (group_m > s.tiles_m) group_m = s.tiles_m;
+    s.group_m = (int)group_m;
+    s.xcd = xcd ? kXcds : 1;
+    return s;
+}
+
+static inline int grid_of(const Sched& s) { return s.tiles_m * s.tiles_n; }
+
+struct Args {
+    bool ta, tb;
+    int64_t M, N, K;
+    double alpha;
+    const double* A;
+    int64_t lda;
+    const double* B;
+    int64_t ldb;
+    double beta;
+    double* C;
+    int64_t ldc;
+    hipStream_t st;
+};
+
+template <class CF, bool TA, bool TB>
+static void launch_regc_t(const Args& a, int64_t k0, int64_t k1, double beta, const Sched& s) {
+    hipLaunchKernelGGL((k_regc<CF, TA, TB>), dim3(grid_of(s)), dim3(CF::THREADS), 0, a.st, a.M, a.N, k0, k1, a.alpha,
+                       a.A, a.lda, a.B, a.ldb, beta, a.C, a.ldc, s);
+}
+
+template <class CF>
+static void launch_regc(const Args& a, int64_t k0, int64_t k1, double beta, const Sched& s) {
+    if (grid_of(s) <= 0) return;
+    if (!a.ta && !a.tb) launch_regc_t<CF, false, false>(a, k0, k1, beta, s);
+    else if (!a.ta && a.tb) launch_regc_t<CF, false, true>(a, k0, k1, beta, s);
+    else if (a.ta && !a.tb) launch_regc_t<CF, true, false>(a, k0, k1, beta, s);
+    else launch_regc_t<CF, true, true>(a, k0, k1, beta, s);
+}
+
+template <bool TA, bool TB, bool PK>
+static void launch_a2_t(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, const double* Bsrc,
+                        int64_t ldb, int64_t pk0, int64_t pn0) {
+    hipLaunchKernelGGL((k_a2<CfgK, kKC, TA, TB, PK>), dim3(grid_of(s)), dim3(CfgK::THREADS), 0, a.st, a.M, a.N, k0,
+                       k1, a.alpha, a.A, a.lda, Bsrc, ldb, a.beta, a.C, a.ldc, s, nj, pk0, pn0);
+}
+
+// beta is applied by the kernel to the pass whose k chunk starts at 0.
+static void launch_a2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, const double* packed,
+                      int64_t pk0, int64_t pn0) {
+    if (grid_of(s) <= 0) return;
+    if (packed) {
+        if (!a.ta) launch_a2_t<false, false, true>(a, k0, k1, s, nj, packed, CfgK::NT, pk0, pn0);
+        else launch_a2_t<true, false, true>(a, k0, k1, s, nj, packed, CfgK::NT, pk0, pn0);
+        return;
+    }
+    if (!a.ta && !a.tb) launch_a2_t<false, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
+    else if (!a.ta && a.tb) launch_a2_t<false, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
+    else if (a.ta && !a.tb) launch_a2_t<true, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
+    else launch_a2_t<true, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
+}
+
+template <bool TA, bool TB>
+static void launch_b2_t(const Args& a, int64_t k0, int64_t k1, const Sched& s, int mi) {
+    hipLaunchKernelGGL((k_b2<CfgK, kKC, TA, TB>), dim3(grid_of(s)), dim3(CfgK::THREADS), 0, a.st, a.M, a.N, k0, k1,
+                       a.alpha, a.A, a.lda, a.B, a.ldb, a.beta, a.C, a.ldc, s, mi);
+}
+
+static void launch_b2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int mi) {
+    if (grid_of(s) <= 0) return;
+    if (!a.ta && !a.tb) launch_b2_t<false, false>(a, k0, k1, s, mi);
+    else if (!a.ta && a.tb) launch_b2_t<false, true>(a, k0, k1, s, mi);
+    else if (a.ta && !a.tb) launch_b2_t<true, false>(a, k0, k1, s, mi);
+    else launch_b2_t<true, true>(a, k0, k1, s, mi);
+}
+
+static void launch_pack_b(const Args& a, int64_t pk0, int64_t pn0, int64_t ncw, double* P) {
+    const int ntiles = (int)cdiv(ncw, CfgK::NT);
+    const int64_t total = (int64_t)ntiles * kKC * CfgK::NT;
+    int grid = (int)cdiv(total, 256);
+    if (grid > 4 * kCUs * 8) grid = 4 * kCUs * 8;
+    if (a.tb)
+        hipLaunchKernelGGL((k_pack_b<CfgK::NT, true>), dim3(grid), dim3(256), 0, a.st, a.B, a.ldb, a.K, a.N, pk0, pn0,
+                           (int)kKC, ntiles, P);
+    else
+        hipLaunchKernelGGL((k_pack_b<CfgK::NT, false>), dim3(grid), dim3(256), 0, a.st, a.B, a.ldb, a.K, a.N, pk0,
+                           pn0, (int)kKC, ntiles, P);
+}
+
+// Runs the loop nest of plan p.  Returns 0 or a hipError_t.
+static int run_member(const momms_plan& p, const Args& a, void* ws) {
+    const int64_t M = a.M, N = a.N, K = a.K;
+    switch (p.member) {
+        case MOMMS_C0:
+        case MOMMS_C3C0: {
+            const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, p.group_m, p.xcd_aware != 0);
+            if (p.mt == 128) launch_regc<CfgL>(a, 0, K, a.beta, s);
+            else launch_regc<CfgS>(a, 0, K, a.beta, s);
+            break;
+        }
+        case MOMMS_B3C0:
+        case MOMMS_A3C0: {
+            // k by kc3 (host loop) -> tiles in column-major (B3) or row-major
+            // (A3) order, each XCD taking a contiguous run.
+            const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, p.group_m, true);
+            for (int64_t kb = 0; kb < K; kb += p.kc3) {
+                const int64_t ke = kb + p.kc3 < K ? kb + p.kc3 : K;
+                const double be = kb == 0 ? a.beta : 1.0;
+                if (p.mt == 128) launch_regc<CfgL>(a, kb, ke, be, s);
+                else launch_regc<CfgS>(a, kb, ke, be, s);
+            }
+            break;
+        }
+        case MOMMS_A2C0: {
+            // n by nc -> k by kc (pack the B panel) -> kernel: m by 128 (A
+            // block in LDS), n by 128 inside and across workgroups.
+            for (int64_t jc = 0; jc < N; jc += p.nc) {
+                const int64_t je = jc + p.nc < N ? jc + p.nc : N;
+                const Sched s = make_sched(0, jc, M, je, p.mt, (int64_t)p.nj * p.nt, 1, false);
+                for (int64_t pc = 0; pc < K; pc += p.kc) {
+                    const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
+                    if (ws) {
+                        double* P = static_cast<double*>(ws);
+                        launch_pack_b(a, pc, jc, je - jc, P);
+                        launch_a2(a, pc, pe, s, p.nj, P, pc, jc);
+                    } else {
+                        launch_a2(a, pc, pe, s, p.nj, nullptr, 0, 0);
+                    }
+                }
+            }
+            break;
+        }
+        case MOMMS_B3A2C0: {
+            // k by kc3 (host) -> granules of 128 rows x nc3 columns in
+            // column-major order (one XCD's run shares a kc3 x nc3 B block)
+            // -> kernel: k by kc inside, A block in LDS, n by 128.
+            const Sched s = make_sched(0, 0, M, N, p.mt, p.nc3, p.group_m, true);
+            for (int64_t kb = 0; kb < K; kb += p.kc3) {
+                const int64_t ke = kb + p.kc3 < K ? kb + p.kc3 : K;
+                launch_a2(a, kb, ke, s, p.nj, nullptr, 0, 0);
+            }
+            break;
+        }
+        case MOMMS_A3B2C0: {
+            const Sched s = make_sched(0, 0, M, N, p.mc3, p.nt, 1, true);
+            for (int64_t kb = 0; kb < K; kb += p.kc3) {
+                const int64_t ke = kb + p.kc3 < K ? kb + p.kc3 : K;
+                launch_b2(a, kb, ke, s, p.mi);
+            }
+            break;
+        }
+        case MOMMS_C3A2C0: {
+            const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, p.group_m, true);
+            launch_a2(a, 0, K, s, 1, nullptr, 0, 0);
+            break;
+        }
+        case MOMMS_C4A2C0: {
+            // m, n by the MALL-resident C block -> k by kc (host) -> kernel.
+            for (int64_t ib = 0; ib < M; ib += p.mc4) {
+                const int64_t ie = ib + p.mc4 < M ? ib + p.mc4 : M;
+                for (int64_t jb = 0; jb < N; jb += p.nc4) {
+                    const int64_t je = jb + p.nc4 < N ? jb + p.nc4 : N;
+                    const Sched s = make_sched(ib, jb, ie, je, p.mt, (int64_t)p.nj * p.nt, 1, false);
+                    for (int64_t pc = 0; pc < K; pc += p.kc) {
+                        const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
+                        launch_a2(a, pc, pe, s, p.nj, nullptr, 0, 0);
+                    }
+                }
+            }
+            break;
+        }
+        default:
+            return MOMMS_ERR_INTERNAL;
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+// Largest grid any member launches for this plan must fit the int tile
+// arithmetic of decode_tile.
+static bool grid_fits(int64_t M, int64_t N) {
+    const int64_t t = cdiv(M, 64) * cdiv(N, 64);
+    return t < (int64_t)INT_MAX / 2;
+}
+
+}  // namespace momms
+
+extern "C" {
+
+int momms_set_stream(momms_stream_t stream) {
+    momms::g_stream = static_cast<hipStream_t>(stream);
+    return 0;
+}
+
+int momms_gemm_ex(int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                  int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int family_member,
+                  void* workspace, size_t ws_bytes, momms_stream_t stream) {
+    using namespace momms;
+    const bool ta = transA != 0, tb = transB != 0;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const bool reads_ab = (alpha != 0.0) && k > 0 && m > 0 && n > 0;
+    if (reads_ab && A == nullptr) return -7;
+    if (lda < (ta ? (m > 1 ? m : 1) : (k > 1 ? k : 1))) return -8;
+    if (reads_ab && B == nullptr) return -9;
+    if (ldb < (tb ? (k > 1 ? k : 1) : (n > 1 ? n : 1))) return -10;
+    if (m > 0 && n > 0 && C == nullptr) return -12;
+    if (ldc < (n > 1 ? n : 1)) return -13;
+    if (family_member < 0 || family_member >= MOMMS_NUM_MEMBERS) return -14;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return -15;
+    if (!grid_fits(m, n)) return MOMMS_ERR_INFEASIBLE;
+
+    int member = family_member == MOMMS_AUTO ? select_member(m, n, k) : family_member;
+    const size_t need = workspace_bytes(member, m, n, k);
+    if (workspace && need > 0 && ws_bytes < need) return -16;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (m == 0 || n == 0) return 0;
+    if ((alpha == 0.0 || k == 0) && beta == 1.0) return 0;
+    if (alpha == 0.0 || k == 0) {
+        int64_t total = m * n;
+        int grid = (int)cdiv(total, 256);
+        if (grid > 8 * kCUs * 8) grid = 8 * kCUs * 8;
+        hipLaunchKernelGGL(k_scale_c, dim3(grid), dim3(256), 0, st, m, n, beta, C, ldc);
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? 0 : (int)e;
+    }
+    momms_plan p;
+    if (plan_member(member, m, n, k, &p) != 0) return MOMMS_ERR_INTERNAL;
+    Args a{ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, st};
+    return run_member(p, a, need > 0 ? workspace : nullptr);
+}
+
+int momms_gemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda, const double* B,
+               int64_t ldb, double beta, double* C, int64_t ldc, int family_member) {
+    const int r = momms_gemm_ex(0, 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, family_member, nullptr, 0,
+                                momms::g_stream);
+    // momms_gemm_ex numbers m as argument 3; momms_gemm numbers it 1.
+    return r < 0 ? r + 2 : r;
+}
+
+}  // extern "C"

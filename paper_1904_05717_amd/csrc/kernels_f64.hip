@@ -1,0 +1,388 @@
+// FP64 MFMA kernels of the MOMMS family on gfx950 (CDNA4).
+//
+// Every member is assembled from three workgroup-level kernels that share one
+// register micro-kernel (the paper's "inner kernel", Sec. 5.2: all members
+// call the same micro-kernel):
+//
+//   k_regc : C tile resident in registers (level 0) while the workgroup runs
+//            over a k range; A and B k-slices are streamed through a
+//            double-buffered LDS stage (LDS holds no resident block).
+//   k_a2   : an A block (MT x KC) resident in LDS (level 2), reused across
+//            NJ n-tiles; B slices streamed; C updated once per KC.
+//   k_b2   : a B block (KC x NT) resident in LDS, reused across MI m-tiles;
+//            A slices streamed; C updated once per KC.
+//
+// The loops above the workgroup (levels 3 and 4: the per-XCD L2 and the
+// MALL) are realised by the host loops in gemm_f64.hip and by the
+// workgroup -> tile map `decode_tile` below.
+//
+// MFMA lane layout of v_mfma_f64_16x16x4_f64 on gfx950 (measured on the
+// device): lane l supplies A[l % 16][l / 16] of the 16x4 A block and
+// B[l / 16][l % 16] of the 4x16 B block, and holds D[l / 16 + 4 r][l % 16]
+// in accumulator element r of the 16x16 result.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace momms {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kXcds = 8;  // XCDs on MI355X; workgroup b is dispatched to XCD b % 8
+
+// Workgroup tile: MT x NT of C per workgroup, KS = LDS k-slice depth,
+// WM x WN waves of 64 lanes, each owning a (MT/WM) x (NT/WN) sub-tile.
+template <int MT_, int NT_, int KS_, int WM_, int WN_>
+struct TileCfg {
+    static constexpr int MT = MT_, NT = NT_, KS = KS_, WM = WM_, WN = WN_;
+    static constexpr int THREADS = 64 * WM * WN;
+    static constexpr int WTM = MT / WM, WTN = NT / WN;
+    static constexpr int BM = WTM / 16, BN = WTN / 16;
+    // LDS row pitches (doubles): A slices are stored [m][k], B slices [k][n].
+    static constexpr int A_LD = KS + 1;
+    static constexpr int B_LD = NT + 2;
+    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be a multiple of 16");
+    static_assert(KS % 4 == 0, "k-slice must be a multiple of the MFMA depth 4");
+};
+
+// Region of C covered by one launch and the order in which workgroups visit
+// its granules.  A granule is the C area one workgroup owns.
+struct Sched {
+    int64_t m_off, n_off;  // region origin (elements)
+    int64_t m_lim, n_lim;  // region end, exclusive, already clipped to (m, n)
+    int tiles_m, tiles_n;  // granules in the region
+    int group_m;           // grouped order: group_m granule rows are swept
+                           // column by column; 1 = row-major, tiles_m = column-major
+    int xcd;               // 1: plain order; 8: each XCD takes a contiguous run of the order
+};
+
+// Workgroup b -> granule (tm, tn).  With xcd == 8 the run of the tile order
+// handed to XCD x is [x*q + min(x, r), ...) where q, r = T / 8, T % 8, so the
+// workgroups that share one L2 work on neighbouring granules.
+__device__ __forceinline__ void decode_tile(const Sched& s, int b, int& tm, int& tn) {
+    const int T = s.tiles_m * s.tiles_n;
+    int t = b;
+    if (s.xcd > 1) {
+        const int x = b % s.xcd, slot = b / s.xcd;
+        const int q = T / s.xcd, r = T % s.xcd;
+        t = x * q + (x < r ? x : r) + slot;
+    }
+    const int per_group = s.group_m * s.tiles_n;
+    const int g = t / per_group;
+    const int first_m = g * s.group_m;
+    const int rows = (s.tiles_m - first_m) < s.group_m ? (s.tiles_m - first_m) : s.group_m;
+    const int local = t - g * per_group;
+    tm = first_m + local % rows;
+    tn = local / rows;
+}
+
+// Register staging of an R x S tile of a logical operand X, where
+// X(r, s) = P[(r0 + r) * ld + s0 + s] if !TRANS, P[(s0 + s) * ld + r0 + r] if TRANS.
+// Consecutive threads walk the contiguous index, so global loads coalesce.
+// Entries outside [0, rlim) x [0, slim) are zero.
+template <int R, int S, int THREADS, bool TRANS>
+struct Stage {
+    static_assert((R * S) % THREADS == 0, "stage must divide evenly over the threads");
+    static constexpr int N = (R * S) / THREADS;
+    double v[N];
+
+    __device__ __forceinline__ static void coord(int e, int& r, int& s) {
+        if (TRANS) { s = e / R; r = e - s * R; }
+        else       { r = e / S; s = e - r * S; }
+    }
+    __device__ __forceinline__ void load(const double* __restrict__ P, int64_t ld, int64_t r0, int64_t s0,
+                                         int64_t rlim, int64_t slim, int tid) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            int r, s;
+            coord(tid + i * THREADS, r, s);
+            const int64_t gr = r0 + r, gs = s0 + s;
+            v[i] = (gr < rlim && gs < slim) ? (TRANS ? P[gs * ld + gr] : P[gr * ld + gs]) : 0.0;
+        }
+    }
+    __device__ __forceinline__ void store(double* __restrict__ L, int lld, int tid) const {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            int r, s;
+            coord(tid + i * THREADS, r, s);
+            L[r * lld + s] = v[i];
+        }
+    }
+};
+
+// Micro-kernel: acc += A(:, a_k0 : a_k0 + 4*ksteps) * B(b_k0 : ..., :) from LDS.
+// A is read from As[m][k] (pitch a_ld), B from Bs[k][n] (pitch b_ld).
+template <class CF, int KSTEPS>
+__device__ __forceinline__ void mma_lds(const double* __restrict__ As, int a_ld, int a_k0,
+                                        const double* __restrict__ Bs, int b_ld, int b_k0,
+                                        d4 (&acc)[CF::BM][CF::BN], int wm, int wn, int lane) {
+    const int li = lane & 15, lk = lane >> 4;
+    const double* ap = As + (wm * CF::WTM + li) * a_ld + a_k0 + lk;
+    const double* bp = Bs + (b_k0 + lk) * b_ld + wn * CF::WTN + li;
+#pragma unroll
+    for (int kk = 0; kk < KSTEPS; ++kk) {
+        double a[CF::BM], b[CF::BN];
+#pragma unroll
+        for (int i = 0; i < CF::BM; ++i) a[i] = ap[i * 16 * a_ld + kk * 4];
+#pragma unroll
+        for (int j = 0; j < CF::BN; ++j) b[j] = bp[kk * 4 * b_ld + j * 16];
+#pragma unroll
+        for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::BN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+template <class CF>
+__device__ __forceinline__ void zero_acc(d4 (&acc)[CF::BM][CF::BN]) {
+#pragma unroll
+    for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::BN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Epilogue: C = alpha * acc + beta * C on the workgroup tile at (m0, n0);
+// beta == 0 does not read C.  Sixteen consecutive lanes write one 128-byte row
+// segment.
+template <class CF>
+__device__ __forceinline__ void store_c(const d4 (&acc)[CF::BM][CF::BN], double alpha, double beta,
+                                        double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0,
+                                        int64_t M, int64_t N, int wm, int wn, int lane) {
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::BN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm * CF::WTM + i * 16 + lk + 4 * r;
+                const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
+                if (row < M && col < N) {
+                    double* p = C + row * ldc + col;
+                    double v = alpha * acc[i][j][r];
+                    if (beta != 0.0) v += beta * (*p);
+                    *p = v;
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// k_regc: one C granule (MT x NT) per workgroup, accumulated in registers over
+// k in [k_begin, k_end); C = alpha*acc + beta*C at the end.
+template <class CF, bool TA, bool TB>
+__global__ __launch_bounds__(CF::THREADS) void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
+                                                      double alpha, const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ B, int64_t ldb, double beta,
+                                                      double* __restrict__ C, int64_t ldc, Sched s) {
+    __shared__ double As[2][CF::MT * CF::A_LD];
+    __shared__ double Bs[2][CF::KS * CF::B_LD];
+    int tm, tn;
+    decode_tile(s, blockIdx.x, tm, tn);
+    const int64_t m0 = s.m_off + (int64_t)tm * CF::MT;
+    const int64_t n0 = s.n_off + (int64_t)tn * CF::NT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / CF::WN, wn = wave % CF::WN;
+
+    d4 acc[CF::BM][CF::BN];
+    zero_acc<CF>(acc);
+    Stage<CF::MT, CF::KS, CF::THREADS, TA> sa;
+    Stage<CF::KS, CF::NT, CF::THREADS, TB> sb;
+    const int64_t nsl = (k_end - k_begin + CF::KS - 1) / CF::KS;
+    if (nsl > 0) {
+        sa.load(A, lda, m0, k_begin, M, k_end, tid);
+        sb.load(B, ldb, k_begin, n0, k_end, N, tid);
+        sa.store(As[0], CF::A_LD, tid);
+        sb.store(Bs[0], CF::B_LD, tid);
+        __syncthreads();
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            const int cur = (int)(sl & 1);
+            const bool more = sl + 1 < nsl;
+            if (more) {
+                const int64_t kn = k_begin + (sl + 1) * CF::KS;
+                sa.load(A, lda, m0, kn, M, k_end, tid);
+                sb.load(B, ldb, kn, n0, k_end, N, tid);
+            }
+            mma_lds<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs[cur], CF::B_LD, 0, acc, wm, wn, lane);
+            if (more) {
+                sa.store(As[cur ^ 1], CF::A_LD, tid);
+                sb.store(Bs[cur ^ 1], CF::B_LD, tid);
+            }
+            __syncthreads();
+        }
+    }
+    store_c<CF>(acc, alpha, beta, C, ldc, m0, n0, M, N, wm, wn, lane);
+}
+
+// ---------------------------------------------------------------------------
+// k_a2: granule = MT rows x (nj * NT) columns.  For each KC chunk of
+// [k_begin, k_end) the A block (MT x KC) is loaded into LDS once and reused for
+// every n-tile of the granule; B slices stream through two LDS buffers.  C is
+// read-modified-written once per chunk: beta applies to the chunk starting at
+// k = 0, later chunks accumulate.  With PACKED, B comes from a packed panel
+// laid out [n-tile][k][NT] (rows of NT doubles, zero-padded), whose origin is
+// (pk0, pn0) in B's coordinates; n-tiles are numbered from pn0.
+template <class CF, int KC, bool TA, bool TB, bool PACKED>
+__global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
+                                                    double alpha, const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb, double beta,
+                                                    double* __restrict__ C, int64_t ldc, Sched s, int nj,
+                                                    int64_t pk0, int64_t pn0) {
+    static_assert(KC % CF::KS == 0, "KC must be a multiple of the slice depth");
+    constexpr int AB_LD = KC + 1;
+    __shared__ double As[CF::MT * AB_LD];
+    __shared__ double Bs[2][CF::KS * CF::B_LD];
+    int tm, tn;
+    decode_tile(s, blockIdx.x, tm, tn);
+    const int64_t m0 = s.m_off + (int64_t)tm * CF::MT;
+    const int64_t nbeg = s.n_off + (int64_t)tn * nj * CF::NT;
+    const int64_t nend = (nbeg + (int64_t)nj * CF::NT) < s.n_lim ? (nbeg + (int64_t)nj * CF::NT) : s.n_lim;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / CF::WN, wn = wave % CF::WN;
+    const int ntiles = (int)((nend - nbeg + CF::NT - 1) / CF::NT);
+
+    Stage<CF::MT, CF::KS, CF::THREADS, TA> sa;
+    Stage<CF::KS, CF::NT, CF::THREADS, PACKED ? false : TB> sb;
+    d4 acc[CF::BM][CF::BN];
+
+    for (int64_t kb = k_begin; kb < k_end; kb += KC) {
+        const int64_t kbe = (kb + KC) < k_end ? (kb + KC) : k_end;
+        const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
+        const int total = ntiles * nsl;
+        __syncthreads();  // previous chunk's readers of As / Bs are done
+#pragma unroll 1
+        for (int c = 0; c < nsl; ++c) {
+            sa.load(A, lda, m0, kb + c * CF::KS, M, kbe, tid);
+            sa.store(As + c * CF::KS, AB_LD, tid);
+        }
+        auto load_b = [&](int t) {
+            const int j = t / nsl, sl = t - (t / nsl) * nsl;
+            if (PACKED) {
+                // panel row (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j)
+                const int64_t jt = (nbeg - pn0) / CF::NT + j;
+                const double* P = B + jt * (int64_t)KC * CF::NT;
+                sb.load(P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, INT64_MAX, CF::NT, tid);
+            } else {
+                sb.load(B, ldb, kb + (int64_t)sl * CF::KS, nbeg + (int64_t)j * CF::NT, kbe, nend, tid);
+            }
+        };
+        if (total > 0) {
+            load_b(0);
+            sb.store(Bs[0], CF::B_LD, tid);
+        }
+        __syncthreads();
+        zero_acc<CF>(acc);
+        const double beta_eff = (kb == 0) ? beta : 1.0;
+#pragma unroll 1
+        for (int t = 0; t < total; ++t) {
+            const int cur = t & 1;
+            const int j = t / nsl, sl = t - j * nsl;
+            const bool more = t + 1 < total;
+            if (more) load_b(t + 1);
+            mma_lds<CF, CF::KS / 4>(As, AB_LD, sl * CF::KS, Bs[cur], CF::B_LD, 0, acc, wm, wn, lane);
+            if (more) sb.store(Bs[cur ^ 1], CF::B_LD, tid);
+            if (sl == nsl - 1) {
+                store_c<CF>(acc, alpha, beta_eff, C, ldc, m0, nbeg + (int64_t)j * CF::NT, M, nend, wm, wn, lane);
+                zero_acc<CF>(acc);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_b2: mirror of k_a2.  Granule = (mi * MT) rows x NT columns; for each KC
+// chunk the B block (KC x NT) is resident in LDS and reused for every m-tile;
+// A slices stream through two LDS buffers.
+template <class CF, int KC, bool TA, bool TB>
+__global__ __launch_bounds__(CF::THREADS) void k_b2(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
+                                                    double alpha, const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb, double beta,
+                                                    double* __restrict__ C, int64_t ldc, Sched s, int mi) {
+    static_assert(KC % CF::KS == 0, "KC must be a multiple of the slice depth");
+    __shared__ double Bs[KC * CF::B_LD];
+    __shared__ double As[2][CF::MT * CF::A_LD];
+    int tm, tn;
+    decode_tile(s, blockIdx.x, tm, tn);
+    const int64_t mbeg = s.m_off + (int64_t)tm * mi * CF::MT;
+    const int64_t mend = (mbeg + (int64_t)mi * CF::MT) < s.m_lim ? (mbeg + (int64_t)mi * CF::MT) : s.m_lim;
+    const int64_t n0 = s.n_off + (int64_t)tn * CF::NT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / CF::WN, wn = wave % CF::WN;
+    const int mtiles = (int)((mend - mbeg + CF::MT - 1) / CF::MT);
+
+    Stage<CF::MT, CF::KS, CF::THREADS, TA> sa;
+    Stage<CF::KS, CF::NT, CF::THREADS, TB> sb;
+    d4 acc[CF::BM][CF::BN];
+
+    for (int64_t kb = k_begin; kb < k_end; kb += KC) {
+        const int64_t kbe = (kb + KC) < k_end ? (kb + KC) : k_end;
+        const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
+        const int total = mtiles * nsl;
+        __syncthreads();
+#pragma unroll 1
+        for (int c = 0; c < nsl; ++c) {
+            sb.load(B, ldb, kb + c * CF::KS, n0, kbe, N, tid);
+            sb.store(Bs + c * CF::KS * CF::B_LD, CF::B_LD, tid);
+        }
+        if (total > 0) {
+            sa.load(A, lda, mbeg, kb, mend, kbe, tid);
+            sa.store(As[0], CF::A_LD, tid);
+        }
+        __syncthreads();
+        zero_acc<CF>(acc);
+        const double beta_eff = (kb == 0) ? beta : 1.0;
+#pragma unroll 1
+        for (int t = 0; t < total; ++t) {
+            const int cur = t & 1;
+            const int i = t / nsl, sl = t - i * nsl;
+            const bool more = t + 1 < total;
+            if (more) {
+                const int i2 = (t + 1) / nsl, sl2 = (t + 1) - ((t + 1) / nsl) * nsl;
+                sa.load(A, lda, mbeg + (int64_t)i2 * CF::MT, kb + (int64_t)sl2 * CF::KS, mend, kbe, tid);
+            }
+            mma_lds<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs, CF::B_LD, sl * CF::KS, acc, wm, wn, lane);
+            if (more) sa.store(As[cur ^ 1], CF::A_LD, tid);
+            if (sl == nsl - 1) {
+                store_c<CF>(acc, alpha, beta_eff, C, ldc, mbeg + (int64_t)i * CF::MT, n0, mend, N, wm, wn, lane);
+                zero_acc<CF>(acc);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Packing (Sec. 5.2-5.3: a block is copied into a contiguous buffer when it
+// first becomes resident or guest).  Packs the B panel rows [pk0, pk0+kc),
+// columns [pn0, pn0+nc) into P laid out [n-tile j][k row p][NT], zero-padded
+// past k and n.  One thread per packed element; writes are contiguous, reads
+// contiguous along n (or along k when TB).
+template <int NT, bool TB>
+__global__ __launch_bounds__(256) void k_pack_b(const double* __restrict__ B, int64_t ldb, int64_t K, int64_t N,
+                                                int64_t pk0, int64_t pn0, int kc, int ntiles,
+                                                double* __restrict__ P) {
+    const int64_t total = (int64_t)ntiles * kc * NT;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / ((int64_t)kc * NT);
+        const int64_t rem = e - j * kc * NT;
+        const int64_t p = rem / NT, q = rem - (rem / NT) * NT;
+        const int64_t gk = pk0 + p, gn = pn0 + j * NT + q;
+        P[e] = (gk < K && gn < N) ? (TB ? B[gn * ldb + gk] : B[gk * ldb + gn]) : 0.0;
+    }
+}
+
+// C = beta * C over an m x n matrix (beta == 0 writes zeros without reading).
+__global__ __launch_bounds__(256) void k_scale_c(int64_t M, int64_t N, double beta, double* __restrict__ C,
+                                                 int64_t ldc) {
+    const int64_t total = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / N, j = e - (e / N) * N;
+        double* p = C + i * ldc + j;
+        *p = (beta == 0.0) ? 0.0 : beta * (*p);
+    }
+}
+
+}  // namespace momms

@@ -1,0 +1,423 @@
+// Host-side planner and data-movement model of the MOMMS family on gfx950.
+// No HIP calls: everything here runs (and is tested) without a GPU.
+//
+// Blocksizes are derived from the gfx950 capacities, not from the paper's
+// CPU numbers:
+//   level 0: a workgroup's register tile of C.  128 x 128 fp64 = 128 KiB held
+//            by 4 waves (64 doubles per lane), i.e. sqrt(M0) ~ 128 - the same
+//            order as the paper's LDS-class block, because the register file
+//            (512 KiB/CU) is larger than the LDS (160 KiB/CU).
+//   level 2: LDS.  A resident block of 128 x 128 fp64 (128 KiB) leaves room
+//            for two 8 x 128 streamed slices (Sec. 4.1: resident block plus
+//            guest panel must fit).
+//   level 3: one XCD's 4 MiB L2.  A 512 x 512 resident block (2 MiB) leaves
+//            half the L2 for the guest and streamed panels (Sec. 4.1).
+//   level 4: the 256 MiB MALL.  A 4096 x 4096 C block (128 MiB) leaves half.
+#include <cmath>
+#include <cstring>
+
+#include "../../include/momms.h"
+#include "plan_internal.h"
+
+namespace momms {
+
+static const char* const kNames[MOMMS_NUM_MEMBERS] = {
+    "AUTO", "C0", "C3C0", "B3C0", "A3C0", "A2C0", "B3A2C0", "A3B2C0", "C3A2C0", "C4A2C0"};
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Tile of the register-resident kernel: 128 x 128 when there are enough
+// tiles to give every CU work twice over, else 64 x 64.
+static inline int regc_tile(int64_t m, int64_t n) {
+    return (cdiv(m, 128) * cdiv(n, 128) >= 2 * kCUs) ? 128 : 64;
+}
+
+int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
+    std::memset(p, 0, sizeof(*p));
+    p->member = member;
+    p->ks = 16;
+    p->xcd_aware = 0;
+    p->group_m = 1;
+    p->k_range = k;
+    p->launches = 1;
+    switch (member) {
+        case MOMMS_C0:
+        case MOMMS_C3C0:
+        case MOMMS_B3C0:
+        case MOMMS_A3C0: {
+            const int t = regc_tile(m, n);
+            p->kernel = 0;
+            p->mt = p->nt = t;
+            const int64_t tm = cdiv(m, t), tn = cdiv(n, t);
+            p->workgroups = tm * tn;
+            if (member == MOMMS_C3C0) {
+                // The workgroups resident on one XCD at a time (32 CUs, two
+                // workgroups each for the 128-tile) cover an 8 x 8 tile block.
+                p->xcd_aware = 1;
+                p->group_m = (int)(tm < 8 ? tm : 8);
+                p->mc3 = (int64_t)p->group_m * t;
+                p->nc3 = (int64_t)8 * t;
+            } else if (member == MOMMS_B3C0 || member == MOMMS_A3C0) {
+                p->xcd_aware = 1;
+                p->kc3 = 512;
+                p->k_range = p->kc3 < k ? p->kc3 : k;
+                p->launches = k > 0 ? cdiv(k, p->kc3) : 1;
+                p->workgroups *= p->launches;
+                // Column-major order (B3): one XCD's run of tiles shares
+                // columns, i.e. a B block; row-major (A3): shares an A block.
+                p->group_m = (member == MOMMS_B3C0) ? (int)tm : 1;
+                if (member == MOMMS_B3C0) { p->nc3 = t; p->mc3 = m; }
+                else { p->mc3 = t; p->nc3 = n; }
+            }
+            break;
+        }
+        case MOMMS_A2C0: {
+            // Goto: n by nc -> k by kc (pack B panel) -> m by 128 (A block
+            // in LDS) -> n by 128 across workgroups (the parallel 2nd loop).
+            p->kernel = 1;
+            p->mt = p->nt = 128;
+            p->ks = 8;
+            p->kc = kKC;
+            p->nc = 4096;
+            p->nj = 4;
+            p->k_range = p->kc < k ? p->kc : k;
+            p->pack = 1;
+            const int64_t jcs = cdiv(n, p->nc), pcs = k > 0 ? cdiv(k, p->kc) : 1;
+            const int64_t ncw = n < p->nc ? n : p->nc;
+            p->launches = jcs * pcs * 2;  // pack + compute
+            p->workgroups = jcs * pcs * cdiv(m, p->mt) * cdiv(ncw, (int64_t)p->nj * p->nt);
+            break;
+        }
+        case MOMMS_B3A2C0: {
+            // n by nc3 -> k by kc3 (B block in one XCD's L2) -> m by 128 (A
+            // block in LDS) -> k by kc -> n by 128.
+            p->kernel = 1;
+            p->mt = p->nt = 128;
+            p->ks = 8;
+            p->kc = kKC;
+            p->kc3 = 512;
+            p->nc3 = 512;
+            p->nj = (int)(p->nc3 / p->nt);
+            p->xcd_aware = 1;
+            p->group_m = (int)cdiv(m, p->mt);
+            p->k_range = p->kc < k ? p->kc : k;
+            p->launches = k > 0 ? cdiv(k, p->kc3) : 1;
+            p->workgroups = p->launches * cdiv(m, p->mt) * cdiv(n, p->nc3);
+            break;
+        }
+        case MOMMS_A3B2C0: {
+            // m by mc3 -> k by kc3 (A block in one XCD's L2) -> n by 128 (B
+            // block in LDS) -> k by kc -> m by 128.
+            p->kernel = 2;
+            p->mt = p->nt = 128;
+            p->ks = 8;
+            p->kc = kKC;
+            p->kc3 = 512;
+            p->mc3 = 512;
+            p->mi = (int)(p->mc3 / p->mt);
+            p->xcd_aware = 1;
+            p->group_m = 1;
+            p->k_range = p->kc < k ? p->kc : k;
+            p->launches = k > 0 ? cdiv(k, p->kc3) : 1;
+            p->workgroups = p->launches * cdiv(m, p->mc3) * cdiv(n, p->nt);
+            break;
+        }
+        case MOMMS_C3A2C0: {
+            // n, m by a C block per XCD -> k by kc -> m by 128 (A block in
+            // LDS) -> n by 128; one launch, every workgroup walks all of k.
+            p->kernel = 1;
+            p->mt = p->nt = 128;
+            p->ks = 8;
+            p->kc = kKC;
+            p->nj = 1;
+            p->xcd_aware = 1;
+            p->group_m = (int)(cdiv(m, 128) < 4 ? cdiv(m, 128) : 4);
+            p->mc3 = (int64_t)p->group_m * 128;
+            p->nc3 = 8 * 128;
+            p->k_range = p->kc < k ? p->kc : k;
+            p->workgroups = cdiv(m, p->mt) * cdiv(n, p->nt);
+            break;
+        }
+        case MOMMS_C4A2C0: {
+            // m, n by a 4096 x 4096 C block (MALL) -> k by kc -> m by 128 (A
+            // block in LDS) -> n by 128 across workgroups.
+            p->kernel = 1;
+            p->mt = p->nt = 128;
+            p->ks = 8;
+            p->kc = kKC;
+            p->mc4 = p->nc4 = 4096;
+            p->nj = 4;
+            p->k_range = p->kc < k ? p->kc : k;
+            const int64_t blocks = cdiv(m, p->mc4) * cdiv(n, p->nc4);
+            const int64_t pcs = k > 0 ? cdiv(k, p->kc) : 1;
+            p->launches = blocks * pcs;
+            const int64_t mw = m < p->mc4 ? m : p->mc4, nw = n < p->nc4 ? n : p->nc4;
+            p->workgroups = p->launches * cdiv(mw, p->mt) * cdiv(nw, (int64_t)p->nj * p->nt);
+            break;
+        }
+        default:
+            return -1;
+    }
+    return 0;
+}
+
+size_t workspace_bytes(int member, int64_t m, int64_t n, int64_t k) {
+    (void)m;
+    (void)k;
+    if (member != MOMMS_A2C0) return 0;
+    const int64_t nc = n < 4096 ? n : 4096;
+    return (size_t)(kKC * cdiv(nc, 128) * 128) * sizeof(double);
+}
+
+// ---------------------------------------------------------------------------
+// Data-movement model.  Element counts of Sec. 2.2 with the ceilings the
+// paper keeps at the margins, applied to the loop nest of each member:
+//   an operand block that is resident at a level is read once per pass of the
+//   loop that makes it resident; a streamed operand is read once per
+//   iteration of the loops around it that do not index it; C is read and
+//   written once per pass over its k range (read skipped when beta == 0 on
+//   the first pass).
+// "L2" figures count what crosses the boundary between the per-XCD L2s and
+// the fabric, under ideal residency (Sec. 4.1: the block plus its guest
+// panel fit).  For the L2 level the unit that shares a block is "the
+// workgroups resident on one XCD at a time" (kWGsPerXcd of them).
+static double c_traffic(int64_t m, int64_t n, int64_t k, int64_t k_range, double beta, double* rd, double* wr) {
+    const double passes = (k > 0 && k_range > 0) ? (double)cdiv(k, k_range) : 1.0;
+    const double mn = (double)m * (double)n;
+    *rd = mn * (passes - 1.0 + (beta != 0.0 ? 1.0 : 0.0));
+    *wr = mn * passes;
+    return *rd + *wr;
+}
+
+int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int packed, momms_bytes* o) {
+    momms_plan p;
+    if (plan_member(member, m, n, k, &p) != 0) return -1;
+    std::memset(o, 0, sizeof(*o));
+    const double M = (double)m, N = (double)n, K = (double)k;
+    o->flops = 2.0 * M * N * K;
+    o->compulsory = 8.0 * (M * K + K * N + M * N + (beta != 0.0 ? M * N : 0.0));
+    double a = 0, b = 0, cr = 0, cw = 0;
+    c_traffic(m, n, k, p.k_range, beta, &cr, &cw);
+    const double t = (double)p.mt;
+    const double tm = (double)cdiv(m, p.mt), tn = (double)cdiv(n, p.nt);
+    const int per_xcd = (p.mt >= 128) ? kWGsPerXcd128 : kWGsPerXcd64;
+    switch (member) {
+        case MOMMS_C0: {
+            // Plain order: XCD x holds tiles x, x+8, ...; the tiles one XCD
+            // runs together span rows R = ceil(per_xcd*8 / tn) of the tile
+            // grid and columns C = min(tn, per_xcd*8) / 8 (every 8th).
+            const double run = (double)per_xcd * kXcdsH;  // consecutive tiles in flight chip-wide
+            const double rows = std::ceil(run / tn) < tm ? std::ceil(run / tn) : tm;
+            const double cols = std::ceil((tn < run ? tn : run) / kXcdsH);
+            const double tiles_per_round = (double)per_xcd;
+            const double rounds = (tm * tn) / (tiles_per_round * kXcdsH);
+            // per XCD round: `rows` A panels and `cols` B panels of depth k
+            a = rounds * kXcdsH * rows * t * K;
+            b = rounds * kXcdsH * cols * t * K;
+            if (a > M * K * tn) a = M * K * tn;
+            if (b > K * N * tm) b = K * N * tm;
+            break;
+        }
+        case MOMMS_C3C0: {
+            // One XCD's resident tiles form a group_m x (per_xcd/group_m)
+            // block: each round reads group_m A panels and per_xcd/group_m B
+            // panels of depth k.
+            const double gm = (double)p.group_m;
+            const double gn = std::ceil((double)per_xcd / gm);
+            const double rounds = (tm * tn) / (double)per_xcd;
+            a = rounds * gm * t * K;
+            b = rounds * gn * t * K;
+            if (a > M * K * tn) a = M * K * tn;
+            if (b > K * N * tm) b = K * N * tm;
+            break;
+        }
+        case MOMMS_B3C0: {
+            // Per kc3 pass, XCD runs walk down tile columns: a B block
+            // (kc3 x t) is read once per column; A panels once per tile.
+            a = M * K * tn;
+            b = K * N;
+            break;
+        }
+        case MOMMS_A3C0: {
+            a = M * K;
+            b = K * N * tm;
+            break;
+        }
+        case MOMMS_A2C0: {
+            // A block (128 x kc) read once per (jc, pc, ic); B panel once per
+            // (jc, pc) per workgroup row group... B slices stream from L2 for
+            // every m-block: kn * ceil(m/128) at the LDS boundary, but the
+            // panel (kc x nc, <= 4 MiB) is the guest that the skipped L3 may
+            // keep: count it once per (jc, pc) from the fabric.
+            const double jcs = (double)cdiv(n, p.nc);
+            a = M * K * jcs * (double)cdiv(p.nc < n ? p.nc : n, (int64_t)p.nj * p.nt);
+            b = K * N;
+            break;
+        }
+        case MOMMS_B3A2C0: {
+            // B block kc3 x nc3 resident in L2: B read once.  A block read
+            // once per (jc3, pc3) per m-block.
+            a = M * K * (double)cdiv(n, p.nc3);
+            b = K * N;
+            break;
+        }
+        case MOMMS_A3B2C0: {
+            a = M * K;
+            b = K * N * (double)cdiv(m, p.mc3);
+            break;
+        }
+        case MOMMS_C3A2C0: {
+            // C block (group_m x 8 tiles) per XCD round; A panels once per
+            // tile column of the block, B panels shared by the block rows.
+            const double gm = (double)p.group_m;
+            const double gn = std::ceil((double)kWGsPerXcdLds / gm);
+            const double rounds = (tm * tn) / (gm * gn);
+            a = rounds * gm * t * K;
+            b = rounds * gn * t * K;
+            // C is updated per kc but stays in L2: fabric sees it once.
+            c_traffic(m, n, k, k, beta, &cr, &cw);
+            break;
+        }
+        case MOMMS_C4A2C0: {
+            const double bm = (double)cdiv(m, p.mc4), bn = (double)cdiv(n, p.nc4);
+            const double nw = (double)(n < p.nc4 ? n : p.nc4);
+            a = M * K * bn * std::ceil(nw / ((double)p.nj * p.nt));
+            b = K * N * bm;
+            break;
+        }
+        default:
+            return -1;
+    }
+    o->a_reads = 8.0 * a;
+    o->b_reads = 8.0 * b;
+    o->c_reads = 8.0 * cr;
+    o->c_writes = 8.0 * cw;
+    o->l2_read = o->a_reads + o->b_reads + o->c_reads;
+    o->l2_write = o->c_writes;
+    // Level-4 (MALL, 256 MiB) model: operands that fit the MALL together are
+    // read from HBM once; C updates of k-split members hit the MALL when the
+    // C region one pass touches fits (C4 block), else go to HBM.
+    const double mall = 256.0 * 1024 * 1024;
+    const double total_in = 8.0 * (M * K + K * N);
+    const double cbytes = 8.0 * M * N;
+    if (total_in + cbytes <= mall * 0.75) {
+        o->hbm_read = total_in + (beta != 0.0 ? cbytes : 0.0);
+        o->hbm_write = cbytes;
+    } else {
+        o->hbm_read = o->a_reads + o->b_reads;
+        if (member == MOMMS_C4A2C0 || member == MOMMS_C3A2C0 || p.k_range >= k) {
+            o->hbm_read += (beta != 0.0 ? cbytes : 0.0);
+            o->hbm_write = cbytes;
+        } else {
+            o->hbm_read += o->c_reads;
+            o->hbm_write = o->c_writes;
+        }
+        if (o->hbm_read < total_in) o->hbm_read = total_in;
+    }
+    // LDS fills: every streamed or resident element copied global -> LDS.
+    if (p.kernel == 0) {
+        o->lds_fill = 8.0 * (M * K * tn + K * N * tm);
+    } else if (p.kernel == 1) {
+        o->lds_fill = 8.0 * (M * K * (double)cdiv(n, (int64_t)p.nj * p.nt) + K * N * tm);
+    } else {
+        o->lds_fill = 8.0 * (M * K * tn + K * N * (double)cdiv(m, (int64_t)p.mi * p.mt));
+    }
+    if (packed && p.pack) {
+        // the packed panel is read once from B and written once (padded)
+        const double jcs = (double)cdiv(n, p.nc), pcs = (double)cdiv(k, p.kc);
+        const double ncp = (double)(cdiv(p.nc < n ? p.nc : n, 128) * 128);
+        o->pack = 8.0 * (K * N + jcs * pcs * (double)p.kc * ncp);
+    }
+    return 0;
+}
+
+int select_member(int64_t m, int64_t n, int64_t k) {
+    // Analytic prior (Sec. 2.3: resident C needs k large, resident B needs m
+    // large, resident A needs n large), then fewest model bytes, then lowest
+    // id.  Only members that keep C in registers over all of k are
+    // candidates: on gfx950 they dominate the LDS-resident members for every
+    // shape the model was evaluated on (C traffic 2mn instead of
+    // 2mn * ceil(k/128)).
+    int best = MOMMS_C3C0;
+    double best_bytes = -1.0;
+    const int cand[] = {MOMMS_C3C0, MOMMS_C0, MOMMS_B3C0, MOMMS_A3C0};
+    for (int c : cand) {
+        momms_bytes b;
+        if (model_bytes(c, m, n, k, 1.0, 0, &b) != 0) continue;
+        const double tot = b.l2_read + b.l2_write;
+        if (best_bytes < 0 || tot < best_bytes * (1.0 - 1e-9)) {
+            best = c;
+            best_bytes = tot;
+        }
+    }
+    return best;
+}
+
+const char* member_name(int member) {
+    if (member < 0 || member >= MOMMS_NUM_MEMBERS) return nullptr;
+    return kNames[member];
+}
+
+int member_id(const char* name) {
+    if (!name) return -1;
+    for (int i = 0; i < MOMMS_NUM_MEMBERS; ++i)
+        if (std::strcmp(name, kNames[i]) == 0) return i;
+    return -1;
+}
+
+}  // namespace momms
+
+// ---------------------------------------------------------------------------
+// C ABI: host-only introspection.
+extern "C" {
+
+int momms_num_members(void) { return MOMMS_NUM_MEMBERS; }
+
+const char* momms_member_name(int member) { return momms::member_name(member); }
+
+int momms_member_id(const char* name) { return momms::member_id(name); }
+
+int momms_select_member(int64_t m, int64_t n, int64_t k) {
+    if (m < 0 || n < 0 || k < 0) return -1;
+    return momms::select_member(m, n, k);
+}
+
+int momms_member_plan(int member, int64_t m, int64_t n, int64_t k, momms_plan* out) {
+    if (member < 0 || member >= MOMMS_NUM_MEMBERS) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (k < 0) return -4;
+    if (!out) return -5;
+    if (member == MOMMS_AUTO) member = momms::select_member(m, n, k);
+    return momms::plan_member(member, m, n, k, out) == 0 ? 0 : MOMMS_ERR_INTERNAL;
+}
+
+int momms_model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int packed, momms_bytes* out) {
+    if (member < 0 || member >= MOMMS_NUM_MEMBERS) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (k < 0) return -4;
+    if (!std::isfinite(beta)) return -5;
+    if (!out) return -7;
+    if (member == MOMMS_AUTO) member = momms::select_member(m, n, k);
+    return momms::model_bytes(member, m, n, k, beta, packed, out) == 0 ? 0 : MOMMS_ERR_INTERNAL;
+}
+
+size_t momms_workspace_size(int64_t m, int64_t n, int64_t k, int member) {
+    if (m < 0 || n < 0 || k < 0 || member < 0 || member >= MOMMS_NUM_MEMBERS) return 0;
+    if (member == MOMMS_AUTO) member = momms::select_member(m, n, k);
+    return momms::workspace_bytes(member, m, n, k);
+}
+
+const char* momms_status_string(int status) {
+    if (status == 0) return "success";
+    if (status < 0) return "invalid argument (-status is its 1-based position)";
+    switch (status) {
+        case MOMMS_ERR_INFEASIBLE: return "problem too large for the tile grid";
+        case MOMMS_ERR_NO_DEVICE: return "no usable gfx950 device";
+        case MOMMS_ERR_INTERNAL: return "internal error";
+        default: return "HIP runtime error (status is the hipError_t value)";
+    }
+}
+
+}  // extern "C"

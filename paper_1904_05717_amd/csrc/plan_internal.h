@@ -1,0 +1,24 @@
+// Internal planner interface shared by plan.cpp and the launch code.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/momms.h"
+
+namespace momms {
+
+constexpr int kCUs = 256;              // MI355X: 8 XCDs x 32 CUs
+constexpr double kXcdsH = 8.0;         // XCD count as a double for the model
+constexpr int64_t kKC = 128;           // k depth of an LDS-resident block
+constexpr int kWGsPerXcd128 = 64;      // 128x128 register tile: 2 workgroups per CU
+constexpr int kWGsPerXcd64 = 128;      // 64x64 register tile: 4 workgroups per CU (LDS-bound)
+constexpr int kWGsPerXcdLds = 32;      // LDS-resident kernels: 1 workgroup per CU
+
+int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p);
+size_t workspace_bytes(int member, int64_t m, int64_t n, int64_t k);
+int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int packed, momms_bytes* o);
+int select_member(int64_t m, int64_t n, int64_t k);
+const char* member_name(int member);
+int member_id(const char* name);
+
+}  // namespace momms

@@ -1,0 +1,96 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+declared in include/momms.h, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1904_05717_amd as mm
+from paper_1904_05717_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(momms_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "momms_gemm" in names and "momms_gemm_ex" in names
+    lib = _lib.library()
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_member_names_round_trip():
+    assert mm.MEMBER_NAMES[0] == "AUTO"
+    for i, name in enumerate(mm.MEMBER_NAMES):
+        assert _lib.momms_member_id(name.encode()) == i
+    assert _lib.momms_member_id(b"X9Y9") == -1
+    assert _lib.momms_member_name(99) is None
+    assert {"C0", "A2C0", "B3A2C0", "A3B2C0", "C3A2C0", "C4A2C0"} <= set(mm.FAMILY)
+
+
+NULL = None
+BIG = 1 << 20  # a fake non-null device address; never dereferenced on these paths
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, 1), -1),
+    ((4, -1, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, 1), -2),
+    ((4, 4, -1, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, 1), -3),
+    ((4, 4, 4, 1.0, NULL, 4, BIG, 4, 0.0, BIG, 4, 1), -5),
+    ((4, 4, 8, 1.0, BIG, 7, BIG, 4, 0.0, BIG, 4, 1), -6),
+    ((4, 4, 4, 1.0, BIG, 4, NULL, 4, 0.0, BIG, 4, 1), -7),
+    ((4, 6, 4, 1.0, BIG, 4, BIG, 5, 0.0, BIG, 6, 1), -8),
+    ((4, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, NULL, 4, 1), -10),
+    ((4, 6, 4, 1.0, BIG, 4, BIG, 6, 0.0, BIG, 5, 1), -11),
+    ((4, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, 10), -12),
+    ((4, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, -1), -12),
+])
+def test_argument_errors_reported_before_launch(args, code):
+    assert _lib.momms_gemm(*args) == code
+
+
+def test_ex_argument_errors():
+    f = _lib.momms_gemm_ex
+    # transA: A stored k x m, lda >= m
+    assert f(1, 0, 8, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, 1, None, 0, None) == -8
+    # transB: B stored n x k, ldb >= k
+    assert f(0, 1, 4, 4, 8, 1.0, BIG, 8, BIG, 4, 0.0, BIG, 4, 1, None, 0, None) == -10
+    # misaligned workspace
+    assert f(0, 0, 4, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, 5, BIG + 8, 1 << 30, None) == -15
+    # workspace too small for a packing member
+    need = _lib.momms_workspace_size(64, 64, 64, mm.MEMBERS["A2C0"])
+    assert need > 0
+    assert f(0, 0, 64, 64, 64, 1.0, BIG, 64, BIG, 64, 0.0, BIG, 64, mm.MEMBERS["A2C0"], BIG, need - 8,
+             None) == -16
+
+
+def test_quick_returns_do_not_touch_the_device():
+    # m == 0, n == 0, or (alpha == 0 or k == 0) with beta == 1: nothing is launched
+    assert _lib.momms_gemm(0, 4, 4, 1.0, NULL, 4, NULL, 4, 0.0, NULL, 4, 1) == 0
+    assert _lib.momms_gemm(4, 0, 4, 1.0, NULL, 4, NULL, 1, 0.0, NULL, 1, 1) == 0
+    assert _lib.momms_gemm(4, 4, 4, 0.0, NULL, 4, NULL, 4, 1.0, BIG, 4, 1) == 0
+    assert _lib.momms_gemm(4, 4, 0, 1.0, NULL, 1, NULL, 4, 1.0, BIG, 4, 1) == 0
+
+
+def test_plans_are_consistent():
+    for name in mm.FAMILY:
+        p = mm.member_plan(name, 8192, 8192, 8192)
+        assert p["member"] == mm.MEMBERS[name]
+        assert p["mt"] in (64, 128) and p["nt"] in (64, 128)
+        assert p["launches"] >= 1 and p["workgroups"] >= 1
+        assert 1 <= p["k_range"] <= 8192
+    assert mm.member_plan("AUTO", 8192, 8192, 8192)["member"] == mm.MEMBERS[mm.select_member(8192, 8192, 8192)]
+    assert _lib.momms_member_plan(1, -1, 4, 4, mm.MommsPlan()) == -2
+    assert _lib.momms_member_plan(1, 4, 4, 4, None) == -5

@@ -1,0 +1,165 @@
+"""Parity of every FP64 family member with the CPU oracle, through the C ABI.
+
+Bar: per entry |C_gpu - C_oracle| <= T_ij = 2 (k+2) 2^-53 (|alpha| (|A||B|)_ij
++ |beta| |C_ij|) for uniform data (the forward error bound of a k-term dot
+product in any order; the oracle's own error is below 2^-53 |C_ij|, inside
+the +2 margin), and bit-exact equality on integer data whose partial sums are
+exact in every order.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+mm = pytest.importorskip("paper_1904_05717_amd")
+FAMILY = mm.FAMILY
+DEV = "cuda:0"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def run(A, B, C, alpha, beta, member, transA=False, transB=False, workspace=None):
+    Cd = dev(C.copy()) if C is not None else None
+    out = mm.gemm(dev(A), dev(B), Cd, alpha=alpha, beta=beta, member=member, transA=transA, transB=transB,
+                  workspace=workspace)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_within_bound(got, want, A, B, C, alpha, beta, what=""):
+    k = A.shape[1]
+    tol = oracle.error_bound(A, B, C, alpha, beta, k=k)
+    err = np.abs(got - want)
+    bad = err > tol
+    assert not bad.any(), (f"{what}: {bad.sum()} entries over bound; worst err {err.max():.3e}, "
+                           f"at {np.unravel_index(np.argmax(err - tol), err.shape)}")
+
+
+@pytest.mark.parametrize("member", FAMILY + ["AUTO"])
+def test_config1_uniform(member):
+    m = n = k = 256
+    A, B, _ = workloads.gemm_operands(m, n, k)
+    C = np.zeros((m, n))
+    want = oracle.gemm(A, B, C, 1.0, 1.0)
+    got = run(A, B, C, 1.0, 1.0, member)
+    assert_within_bound(got, want, A, B, C, 1.0, 1.0, member)
+
+
+@pytest.mark.parametrize("member", FAMILY)
+def test_config1_integer_bit_exact(member):
+    m = n = k = 256
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="int")
+    C = np.zeros((m, n))
+    want = oracle.gemm(A, B, C, 1.0, 1.0)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, member), want)
+
+
+@pytest.mark.parametrize("member", FAMILY)
+@pytest.mark.parametrize("shape", [(300, 280, 260), (129, 257, 131)])
+def test_ragged_alpha_beta(member, shape):
+    m, n, k = shape
+    A, B, C = workloads.gemm_operands(m, n, k)
+    want = oracle.gemm(A, B, C, 1.5, -0.5)
+    got = run(A, B, C, 1.5, -0.5, member)
+    assert_within_bound(got, want, A, B, C, 1.5, -0.5, f"{member} {shape}")
+
+
+@pytest.mark.parametrize("member", ["C0", "C3C0", "A2C0"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (15, 17, 3), (33, 65, 129), (64, 64, 64), (2, 300, 5)])
+def test_small_shapes(member, shape):
+    m, n, k = shape
+    A, B, C = workloads.gemm_operands(m, n, k)
+    want = oracle.gemm(A, B, C, 1.0, 1.0)
+    assert_within_bound(run(A, B, C, 1.0, 1.0, member), want, A, B, C, 1.0, 1.0, f"{member} {shape}")
+
+
+@pytest.mark.parametrize("member", FAMILY)
+@pytest.mark.parametrize("ta,tb", [(False, True), (True, False), (True, True)])
+def test_transposed_operands(member, ta, tb):
+    m, n, k = 200, 150, 170
+    A, B, C = workloads.gemm_operands(m, n, k)
+    want = oracle.gemm(A, B, C, 1.0, 1.0)
+    As = A.T.copy() if ta else A
+    Bs = B.T.copy() if tb else B
+    got = run(As, Bs, C, 1.0, 1.0, member, transA=ta, transB=tb)
+    assert_within_bound(got, want, A, B, C, 1.0, 1.0, f"{member} ta={ta} tb={tb}")
+
+
+@pytest.mark.parametrize("member", ["C0", "C3C0", "B3C0", "A2C0", "A3B2C0"])
+def test_leading_dimensions(member):
+    m, n, k = 130, 140, 150
+    A, B, C = workloads.gemm_operands(m, n, k)
+    want = oracle.gemm(A, B, C, 2.0, 0.5)
+    Abig = torch.full((m, k + 7), float("nan"), dtype=torch.float64, device=DEV)
+    Bbig = torch.full((k, n + 3), float("nan"), dtype=torch.float64, device=DEV)
+    Cbig = torch.full((m, n + 5), float("nan"), dtype=torch.float64, device=DEV)
+    Abig[:, :k] = dev(A)
+    Bbig[:, :n] = dev(B)
+    Cbig[:, :n] = dev(C)
+    mm.gemm(Abig[:, :k], Bbig[:, :n], Cbig[:, :n], alpha=2.0, beta=0.5, member=member)
+    torch.cuda.synchronize()
+    got = Cbig.cpu().numpy()
+    assert_within_bound(got[:, :n], want, A, B, C, 2.0, 0.5, member)
+    assert np.isnan(got[:, n:]).all(), "wrote outside the leading-dimension gap"
+
+
+def test_alpha_zero_k_zero_beta_zero():
+    m, n, k = 70, 90, 40
+    A, B, C = workloads.gemm_operands(m, n, k)
+    np.testing.assert_array_equal(run(A, B, C, 0.0, 0.5, "C0"), 0.5 * C)
+    np.testing.assert_array_equal(run(A, B, C, 0.0, 0.0, "C0"), np.zeros_like(C))
+    Ak, Bk = np.zeros((m, 0)), np.zeros((0, n))
+    np.testing.assert_array_equal(run(Ak, Bk, C, 1.0, -2.0, "C3C0"), -2.0 * C)
+    Cn = np.full((m, n), np.nan)
+    for member in FAMILY:
+        got = run(A, B, Cn, 1.0, 0.0, member)
+        assert np.isfinite(got).all(), member
+        assert_within_bound(got, oracle.gemm(A, B), A, B, None, 1.0, 0.0, member)
+
+
+def test_packed_goto_with_workspace():
+    # n spans two n_c = 4096 panels; k spans three kc = 128 passes.
+    m, n, k = 160, 4200, 300
+    A, B, C = workloads.gemm_operands(m, n, k)
+    ws = torch.empty(mm.workspace_size(m, n, k, "A2C0"), dtype=torch.uint8, device=DEV)
+    got = run(A, B, C, 1.0, 1.0, "A2C0", workspace=ws)
+    assert_within_bound(got, oracle.gemm(A, B, C, 1.0, 1.0), A, B, C, 1.0, 1.0, "A2C0 packed")
+    Bt = B.T.copy()
+    got = run(A, Bt, C, 1.0, 1.0, "A2C0", transB=True, workspace=ws)
+    assert_within_bound(got, oracle.gemm(A, B, C, 1.0, 1.0), A, B, C, 1.0, 1.0, "A2C0 packed transB")
+
+
+def sampled_check(m, n, k, member, npts=1500, alpha=1.0, beta=1.0, seed=0):
+    A, B, C = workloads.gemm_operands(m, n, k)
+    got = run(A, B, C, alpha, beta, member)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows = rng.integers(0, m, npts)
+    cols = rng.integers(0, n, npts)
+    # every tile boundary row/column (multiples of 64 and their predecessors) plus the last ones
+    edges_r = np.unique(np.clip(np.concatenate([np.arange(0, m, 64), np.arange(63, m, 64), [m - 1]]), 0, m - 1))
+    edges_c = np.unique(np.clip(np.concatenate([np.arange(0, n, 64), np.arange(63, n, 64), [n - 1]]), 0, n - 1))
+    rows = np.concatenate([rows, edges_r, rng.integers(0, m, edges_c.size)])
+    cols = np.concatenate([cols, rng.integers(0, n, edges_r.size), edges_c])
+    want = oracle.gemm_entries(A, B, rows, cols, C, alpha, beta)
+    absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
+    tol = 2.0 * (k + 2) * 2.0 ** -53 * (abs(alpha) * absab + abs(beta) * np.abs(C[rows, cols]))
+    err = np.abs(got[rows, cols] - want)
+    assert (err <= tol).all(), f"{member} {m}x{n}x{k}: {(err > tol).sum()} sampled entries over bound"
+    return got
+
+
+@pytest.mark.parametrize("member", ["C0", "C3C0", "B3C0", "A3C0"])
+def test_large_register_tile_sampled(member):
+    # 128 x 128 register tiles are used once there are >= 512 tiles.
+    sampled_check(3000, 2900, 384, member)
+
+
+def test_bench_size_sampled():
+    m = n = k = 8192
+    sampled_check(m, n, k, "AUTO", npts=1024)
