@@ -110,6 +110,43 @@ struct Stage {
     }
 };
 
+// Unchecked staging for tiles that lie wholly inside the operand.  Thread tid
+// loads elements e = tid + i*THREADS; because THREADS is a multiple of the
+// contiguous extent, element i sits at a fixed offset i*step from element 0,
+// so one pointer per thread plus a wave-uniform step address every load.
+template <int R, int S, int THREADS, bool TRANS>
+struct FastStage {
+    static constexpr int N = (R * S) / THREADS;
+    static constexpr int CONT = TRANS ? R : S;       // contiguous extent
+    static_assert(THREADS % CONT == 0, "threads must cover whole contiguous rows");
+    static constexpr int ROWS_PER_PASS = THREADS / CONT;
+    double v[N];
+    const double* p;   // this thread's element 0 for the current slice
+    int64_t step;      // distance between consecutive elements i (elements)
+
+    // X(r, s) as in Stage; (r0, s0) is the tile origin.
+    __device__ __forceinline__ void init(const double* __restrict__ P, int64_t ld, int64_t r0, int64_t s0, int tid) {
+        const int c = tid % CONT, q = tid / CONT;
+        if (TRANS) p = P + (s0 + q) * ld + r0 + c;
+        else       p = P + (r0 + q) * ld + s0 + c;
+        step = (int64_t)ROWS_PER_PASS * ld;
+    }
+    __device__ __forceinline__ void advance(int64_t delta) { p += delta; }
+    __device__ __forceinline__ void load() {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = p[i * step];
+    }
+    __device__ __forceinline__ void store(double* __restrict__ L, int lld, int tid) const {
+        const int c = tid % CONT, q = tid / CONT;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int rr = q + i * ROWS_PER_PASS;  // index along the strided extent
+            if (TRANS) L[c * lld + rr] = v[i];
+            else       L[rr * lld + c] = v[i];
+        }
+    }
+};
+
 // Micro-kernel: acc += A(:, a_k0 : a_k0 + 4*ksteps) * B(b_k0 : ..., :) from LDS.
 // A is read from As[m][k] (pitch a_ld), B from Bs[k][n] (pitch b_ld).
 template <class CF, int KSTEPS>
@@ -171,7 +208,8 @@ __device__ __forceinline__ void store_c(const d4 (&acc)[CF::BM][CF::BN], double 
 // k_regc: one C granule (MT x NT) per workgroup, accumulated in registers over
 // k in [k_begin, k_end); C = alpha*acc + beta*C at the end.
 template <class CF, bool TA, bool TB>
-__global__ __launch_bounds__(CF::THREADS) void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
+__global__ __launch_bounds__(CF::THREADS) __attribute__((amdgpu_waves_per_eu(CF::MT >= 128 ? 2 : 1)))
+void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
                                                       double alpha, const double* __restrict__ A, int64_t lda,
                                                       const double* __restrict__ B, int64_t ldb, double beta,
                                                       double* __restrict__ C, int64_t ldc, Sched s) {
@@ -186,9 +224,42 @@ __global__ __launch_bounds__(CF::THREADS) void k_regc(int64_t M, int64_t N, int6
 
     d4 acc[CF::BM][CF::BN];
     zero_acc<CF>(acc);
+    const int64_t nsl = (k_end - k_begin + CF::KS - 1) / CF::KS;
+    const bool interior = (m0 + CF::MT <= M) && (n0 + CF::NT <= N) && ((k_end - k_begin) % CF::KS == 0);
+    if (interior) {
+        // Whole tile inside the matrices: no bounds checks, pointer stepping.
+        FastStage<CF::MT, CF::KS, CF::THREADS, TA> fa;
+        FastStage<CF::KS, CF::NT, CF::THREADS, TB> fb;
+        fa.init(A, lda, m0, k_begin, tid);
+        fb.init(B, ldb, k_begin, n0, tid);
+        const int64_t da = TA ? (int64_t)CF::KS * lda : CF::KS;   // A advances along k
+        const int64_t db = TB ? CF::KS : (int64_t)CF::KS * ldb;   // B advances along k
+        fa.load();
+        fb.load();
+        fa.store(As[0], CF::A_LD, tid);
+        fb.store(Bs[0], CF::B_LD, tid);
+        __syncthreads();
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            const int cur = (int)(sl & 1);
+            const bool more = sl + 1 < nsl;
+            if (more) {
+                fa.advance(da);
+                fb.advance(db);
+                fa.load();
+                fb.load();
+            }
+            mma_lds<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs[cur], CF::B_LD, 0, acc, wm, wn, lane);
+            if (more) {
+                fa.store(As[cur ^ 1], CF::A_LD, tid);
+                fb.store(Bs[cur ^ 1], CF::B_LD, tid);
+            }
+            __syncthreads();
+        }
+        store_c<CF>(acc, alpha, beta, C, ldc, m0, n0, M, N, wm, wn, lane);
+        return;
+    }
     Stage<CF::MT, CF::KS, CF::THREADS, TA> sa;
     Stage<CF::KS, CF::NT, CF::THREADS, TB> sb;
-    const int64_t nsl = (k_end - k_begin + CF::KS - 1) / CF::KS;
     if (nsl > 0) {
         sa.load(A, lda, m0, k_begin, M, k_end, tid);
         sb.load(B, ldb, k_begin, n0, k_end, N, tid);
