@@ -33,7 +33,59 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_f64_8192.json"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (3 times): the reference for HBM byte counters")
+    ap.add_argument("--profile-members", action="store_true",
+                    help="run every family member once at --size, separated by marker fills (for rocprofv3)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 2**27 doubles (1 GiB) three times.
+
+    Under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE its dispatches must read
+    and write 1 GiB each; the ratio counter/known is the scale applied to the
+    GEMM kernels' counters.
+    """
+    import torch
+
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 8 * n, "bytes_written": 8 * n, "repeats": 3}}),
+          flush=True)
+
+
+def profile_members(size):
+    """Each member once (after one warm-up) with a 1-element fill between members."""
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    m = n = k = size
+    A, B, C = workloads.gemm_operands(m, n, k)
+    Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
+    del A, B, C
+    marker = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    order = []
+    for member in mm.FAMILY:
+        wsb = mm.workspace_size(m, n, k, member)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda:0") if wsb else None
+        mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
+        marker.fill_(1.0)
+        t0 = time.perf_counter()
+        mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
+        marker.fill_(2.0)
+        torch.cuda.synchronize()
+        order.append({"member": member, "launches": mm.member_plan(member, m, n, k)["launches"],
+                      "packed": ws is not None, "s": round(time.perf_counter() - t0, 4)})
+        print(json.dumps({"profiled": order[-1]}), flush=True)
+    print(json.dumps({"profile_members": order, "size": size}), flush=True)
 
 
 def cpu_baseline(m, n, k, target_s):
@@ -67,7 +119,12 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.profile_members:
+        profile_members(args.size)
+        return
     import torch
 
     import paper_1904_05717_amd as mm

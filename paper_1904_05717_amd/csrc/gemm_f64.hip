@@ -125,11 +125,23 @@ static void launch_pack_b(const Args& a, int64_t pk0, int64_t pn0, int64_t ncw, 
 static int run_member(const momms_plan& p, const Args& a, void* ws) {
     const int64_t M = a.M, N = a.N, K = a.K;
     switch (p.member) {
-        case MOMMS_C0:
-        case MOMMS_C3C0: {
-            const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, p.group_m, p.xcd_aware != 0);
+        case MOMMS_C0: {
+            const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, 1, false);
             if (p.mt == 128) launch_regc<CfgL>(a, 0, K, a.beta, s);
             else launch_regc<CfgS>(a, 0, K, a.beta, s);
+            break;
+        }
+        case MOMMS_C3C0: {
+            // m, n by the level-4 region (host) -> XCD-aware grouped tiles.
+            for (int64_t ib = 0; ib < M; ib += p.mc4) {
+                const int64_t ie = ib + p.mc4 < M ? ib + p.mc4 : M;
+                for (int64_t jb = 0; jb < N; jb += p.nc4) {
+                    const int64_t je = jb + p.nc4 < N ? jb + p.nc4 : N;
+                    const Sched s = make_sched(ib, jb, ie, je, p.mt, p.nt, p.group_m, true);
+                    if (p.mt == 128) launch_regc<CfgL>(a, 0, K, a.beta, s);
+                    else launch_regc<CfgS>(a, 0, K, a.beta, s);
+                }
+            }
             break;
         }
         case MOMMS_B3C0:

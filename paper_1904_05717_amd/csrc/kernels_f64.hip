@@ -228,10 +228,14 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
     const bool interior = (m0 + CF::MT <= M) && (n0 + CF::NT <= N) && ((k_end - k_begin) % CF::KS == 0);
     if (interior) {
         // Whole tile inside the matrices: no bounds checks, pointer stepping.
+        // Tiles that share an A row panel (same tm) or a B column panel (same
+        // tn) start their k loops a few slices apart and wrap around, so the
+        // workgroups of one XCD do not all miss on the same lines at once.
+        const int64_t s0 = (int64_t)((tm + tn) & 7) % nsl;
         FastStage<CF::MT, CF::KS, CF::THREADS, TA> fa;
         FastStage<CF::KS, CF::NT, CF::THREADS, TB> fb;
-        fa.init(A, lda, m0, k_begin, tid);
-        fb.init(B, ldb, k_begin, n0, tid);
+        fa.init(A, lda, m0, k_begin + s0 * CF::KS, tid);
+        fb.init(B, ldb, k_begin + s0 * CF::KS, n0, tid);
         const int64_t da = TA ? (int64_t)CF::KS * lda : CF::KS;   // A advances along k
         const int64_t db = TB ? CF::KS : (int64_t)CF::KS * ldb;   // B advances along k
         fa.load();
@@ -243,8 +247,10 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
             const int cur = (int)(sl & 1);
             const bool more = sl + 1 < nsl;
             if (more) {
-                fa.advance(da);
-                fb.advance(db);
+                // next slice index (s0 + sl + 1) mod nsl: wrap back to k_begin
+                const bool wrap = (s0 + sl + 1) == nsl;
+                fa.advance(wrap ? da * (1 - nsl) : da);
+                fb.advance(wrap ? db * (1 - nsl) : db);
                 fa.load();
                 fb.load();
             }

@@ -51,12 +51,20 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             const int64_t tm = cdiv(m, t), tn = cdiv(n, t);
             p->workgroups = tm * tn;
             if (member == MOMMS_C3C0) {
-                // The workgroups resident on one XCD at a time (32 CUs, two
-                // workgroups each for the 128-tile) cover an 8 x 8 tile block.
+                // Level 3: the workgroups resident on one XCD at a time cover
+                // one C block of group_m x (per_xcd / group_m) tiles.  Level
+                // 4: one launch covers the C region all 8 XCDs hold at once
+                // (2 x 4 such blocks), so every launch starts its workgroups
+                // together and their k loops stay in step; the host loops
+                // over these regions.
+                const int per_xcd = (t >= 128) ? kWGsPerXcd128 : kWGsPerXcd64;
                 p->xcd_aware = 1;
-                p->group_m = (int)(tm < 8 ? tm : 8);
-                p->mc3 = (int64_t)p->group_m * t;
-                p->nc3 = (int64_t)8 * t;
+                p->group_m = 8;
+                p->mc3 = (int64_t)8 * t;
+                p->nc3 = (int64_t)(per_xcd / 8) * t;
+                p->mc4 = 2 * p->mc3;
+                p->nc4 = 4 * p->nc3;
+                p->launches = cdiv(m, p->mc4) * cdiv(n, p->nc4);
             } else if (member == MOMMS_B3C0 || member == MOMMS_A3C0) {
                 p->xcd_aware = 1;
                 p->kc3 = 512;
@@ -219,16 +227,13 @@ int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int pa
             break;
         }
         case MOMMS_C3C0: {
-            // One XCD's resident tiles form a group_m x (per_xcd/group_m)
-            // block: each round reads group_m A panels and per_xcd/group_m B
-            // panels of depth k.
-            const double gm = (double)p.group_m;
-            const double gn = std::ceil((double)per_xcd / gm);
-            const double rounds = (tm * tn) / (double)per_xcd;
-            a = rounds * gm * t * K;
-            b = rounds * gn * t * K;
-            if (a > M * K * tn) a = M * K * tn;
-            if (b > K * N * tm) b = K * N * tm;
+            // Each launch covers one level-4 region; inside it every XCD
+            // holds one level-3 C block (mc3 x nc3) whose workgroups read
+            // each A row panel and B column panel of the block once.
+            // Summed over blocks: A is read once per block column, B once
+            // per block row (ceilings at the margins).
+            a = M * K * (double)cdiv(n, p.nc3);
+            b = K * N * (double)cdiv(m, p.mc3);
             break;
         }
         case MOMMS_B3C0: {
