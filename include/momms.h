@@ -173,6 +173,39 @@ int momms_select_member(int64_t m, int64_t n, int64_t k);
 
 const char *momms_status_string(int status);
 
+/* ---------------------------------------------------------------------
+ * Split-precision FP64-accurate product (Ozaki-style error-free splitting;
+ * Ozaki, Ogita, Oishi & Rump, Numer. Algorithms 59, 2012 - the paper itself
+ * has no such method).  op(A) and op(B) are split per row / per column into
+ * `slices` integer slices of 8 (first) and 9 (further) bits, exact in BF16;
+ * the slice pairs s + t <= slices-1 are multiplied on BF16 MFMA with exact
+ * FP32 accumulation over chunks of at most 256 products, summed exactly in
+ * FP64 per diagonal s + t, and recombined smallest diagonal first in FP64:
+ *   C := fl(fl(alpha * 2^(e_i+f_j) V_ij) + fl(beta * C_ij)).
+ * The result is deterministic (bit-reproducible).  Its error against the
+ * exact product is at most about (slices+2) * k * 2^(e_i+f_j) * 2^-(9*slices)
+ * + (slices+2) u (|A||B|)_ij, where 2^e_i > max_p |op(A)_ip| and
+ * 2^f_j > max_p |op(B)_pj|; 7 slices give FP64-level accuracy for data
+ * spanning 16 decades.  Inputs must be finite.
+ * Argument numbers: 1 transA, 2 transB, 3 m, 4 n, 5 k, 6 alpha, 7 A, 8 lda,
+ * 9 B, 10 ldb, 11 beta, 12 C, 13 ldc, 14 slices (1..8), 15 slice_type
+ * (MOMMS_SLICE_BF16), 16 family_member (MOMMS_AUTO, MOMMS_C0 or
+ * MOMMS_C3C0: tile order of the slice products), 17 workspace (device,
+ * 256-byte aligned), 18 ws_bytes (>= momms_split_workspace_size), 19 stream.
+ * The workspace holds the exponents, the slices and the FP64 partial sums;
+ * it must not be used concurrently by another call.
+ */
+enum momms_slice_type { MOMMS_SLICE_BF16 = 0, MOMMS_SLICE_FP8 = 1 };
+
+size_t momms_split_workspace_size(int64_t m, int64_t n, int64_t k, int slices, int slice_type);
+
+int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k,
+                     double alpha, const double *A, int64_t lda,
+                     const double *B, int64_t ldb, double beta,
+                     double *C, int64_t ldc, int slices, int slice_type,
+                     int family_member, void *workspace, size_t ws_bytes,
+                     momms_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

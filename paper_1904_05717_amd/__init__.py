@@ -110,3 +110,41 @@ def model_bytes(member, m, n, k, beta=1.0, packed=False):
 
 def select_member(m, n, k):
     return MEMBER_NAMES[_lib.momms_select_member(m, n, k)]
+
+
+SLICE_TYPES = {"bf16": 0, "fp8": 1}
+
+
+def split_workspace_size(m, n, k, slices, slice_type="bf16"):
+    return int(_lib.momms_split_workspace_size(m, n, k, slices, SLICE_TYPES[slice_type]))
+
+
+def gemm_split(A, B, C=None, alpha=1.0, beta=0.0, slices=7, slice_type="bf16", member="AUTO", transA=False,
+               transB=False, workspace=None, stream=None):
+    """FP64-accurate C := alpha op(A) op(B) + beta C from BF16 slice products.
+
+    Same conventions as gemm().  `workspace` (uint8 device tensor of at
+    least split_workspace_size bytes) is allocated through torch when None.
+    """
+    m, k = (A.shape[1], A.shape[0]) if transA else (A.shape[0], A.shape[1])
+    kb, n = (B.shape[1], B.shape[0]) if transB else (B.shape[0], B.shape[1])
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    lda, ldb = _ld(A, "A"), _ld(B, "B")
+    if C is None:
+        C = torch.zeros((m, n), dtype=torch.float64, device=A.device)
+        beta = 0.0
+    if tuple(C.shape) != (m, n):
+        raise ValueError(f"C has shape {tuple(C.shape)}, expected {(m, n)}")
+    ldc = _ld(C, "C")
+    if slice_type not in SLICE_TYPES:
+        raise ValueError(f"unknown slice type {slice_type!r}")
+    need = split_workspace_size(m, n, k, slices, slice_type)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    st = _lib.momms_gemm_split(int(bool(transA)), int(bool(transB)), m, n, k, float(alpha), A.data_ptr(), lda,
+                               B.data_ptr(), ldb, float(beta), C.data_ptr(), ldc, int(slices),
+                               SLICE_TYPES[slice_type], member_id(member), workspace.data_ptr(),
+                               workspace.numel() * workspace.element_size(), _stream_handle(stream))
+    check_status(st, "momms_gemm_split")
+    return C

@@ -61,11 +61,14 @@ momms_member_plan = _fn("momms_member_plan", i32, [i32, i64, i64, i64, ctypes.PO
 momms_model_bytes = _fn("momms_model_bytes", i32, [i32, i64, i64, i64, dbl, i32, ctypes.POINTER(MommsBytes)])
 momms_select_member = _fn("momms_select_member", i32, [i64, i64, i64])
 momms_status_string = _fn("momms_status_string", ctypes.c_char_p, [i32])
+momms_split_workspace_size = _fn("momms_split_workspace_size", sz, [i64, i64, i64, i32, i32])
+momms_gemm_split = _fn("momms_gemm_split", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64,
+                                                 i32, i32, i32, vp, sz, vp])
 
 EXPORTS = [
     "momms_gemm", "momms_gemm_ex", "momms_workspace_size", "momms_set_stream", "momms_num_members",
     "momms_member_name", "momms_member_id", "momms_member_plan", "momms_model_bytes",
-    "momms_select_member", "momms_status_string",
+    "momms_select_member", "momms_status_string", "momms_split_workspace_size", "momms_gemm_split",
 ]
 
 

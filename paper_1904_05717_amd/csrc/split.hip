@@ -1,0 +1,406 @@
+// Split-precision FP64-accurate product on BF16 MFMA (Ozaki-style splitting,
+// Ozaki, Ogita, Oishi & Rump, Numer. Algorithms 59 (2012)).  The paper has no
+// such method; this is the precision extension of the MOMMS family: the
+// slice products run on the register-resident-C loop nest (member C3C0 order)
+// with BF16 operands.
+//
+//   s1 exponent scan : e_i = frexp exponent of max_p |op(A)_ip| (so the row
+//                      maximum is < 2^e_i), f_j likewise per column of op(B).
+//   s2 slicing       : d_0 = rint(a' 2^w_0), d_s = rint(r_s 2^w_s),
+//                      r_{s+1} = r_s - d_s 2^-w_s, a' = a 2^-e_i,
+//                      w_s = 8 + 9 s.  |d_0| <= 256, |d_s| <= 256: exact BF16.
+//   s3 slice products: for each diagonal d = s + t <= S-1 one launch computes
+//                      Q_d = sum_s D^A_s D^B_{d-s} with v_mfma_f32_16x16x32_bf16.
+//                      Products are <= 2^16, so FP32 sums of at most 256 of
+//                      them are exact integers below 2^24; every 256 products
+//                      they are added into FP64 (exact: |Q_d| < 2^53).
+//   s4 recombination : V = sum_{d = S-1 .. 0} Q_d 2^-(16 + 9 d) in that order
+//                      (each launch adds its term to V), then
+//                      C = fl(fl(alpha * V 2^(e_i + f_j)) + fl(beta * C)).
+// Steps s1-s3 are exact and s4 has a fixed order, so the result is
+// reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "../../include/momms.h"
+#include "plan_internal.h"
+#include "sched.h"
+
+namespace momms {
+namespace split {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kB0 = 8;       // bits of the first BF16 slice
+constexpr int kB = 9;        // bits of every further slice
+constexpr int kMT = 128;     // workgroup tile of the slice-product kernel
+constexpr int kKS = 64;      // k-slice staged in LDS (bf16 elements)
+constexpr int kKPad = 64;    // k padded to a multiple of this
+constexpr int kLdsPitch = kKS + 8;  // 144-byte rows: conflict-free 16-byte fragment reads
+constexpr int kExpNone = INT_MIN;   // exponent of an all-zero row/column
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+__device__ __forceinline__ int exp_or_zero(int e) { return e == kExpNone ? 0 : e; }
+
+__global__ __launch_bounds__(256) void k_fill_int(int* __restrict__ p, int64_t n, int v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// frexp exponent of |x| for x != 0 (|x| < 2^e); zero contributes nothing.
+__device__ __forceinline__ int exp_of(double x) {
+    int e;
+    (void)frexp(x, &e);
+    return e;
+}
+
+// Per stored row r of P (rows x cols, pitch ld): out[r] = max exponent.  One
+// wave per (row, column chunk); lanes read consecutive columns.
+__global__ __launch_bounds__(256) void k_rowmax_exp(const double* __restrict__ P, int64_t ld, int64_t rows,
+                                                    int64_t cols, int64_t chunk, int* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const int64_t c0 = (int64_t)blockIdx.y * chunk;
+    const int64_t c1 = c0 + chunk < cols ? c0 + chunk : cols;
+    double mx = 0.0;
+    for (int64_t c = c0 + lane; c < c1; c += 64) mx = fmax(mx, fabs(P[r * ld + c]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0 && mx != 0.0) atomicMax(out + r, exp_of(mx));
+}
+
+// Per stored column c: out[c] = max exponent over a chunk of rows; threads
+// walk consecutive columns.
+__global__ __launch_bounds__(256) void k_colmax_exp(const double* __restrict__ P, int64_t ld, int64_t rows,
+                                                    int64_t cols, int64_t chunk, int* __restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= cols) return;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk;
+    const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
+    double mx = 0.0;
+    for (int64_t r = r0; r < r1; ++r) mx = fmax(mx, fabs(P[r * ld + c]));
+    if (mx != 0.0) atomicMax(out + c, exp_of(mx));
+}
+
+// Slices of the logical R x Cc matrix X, X(r, c) = P[r*ld + c] (TRANSPOSED =
+// false) or P[c*ld + r] (true), scaled per row by 2^-e[r].  Writes
+// out[s][r][c] (pitch Cp, slice stride Rp*Cp) as BF16 bit patterns for all
+// r < Rp, c < Cp (zero outside X).  64 x 64 tiles go through LDS so that
+// global reads and writes are both contiguous.
+template <bool TRANSPOSED>
+__global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int64_t ld, int64_t R, int64_t Cc,
+                                               const int* __restrict__ e, int S, uint16_t* __restrict__ out,
+                                               int64_t Rp, int64_t Cp) {
+    __shared__ double tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int idx = tid + 256 * i;
+        int rr, cc;
+        if (TRANSPOSED) { cc = idx >> 6; rr = idx & 63; }
+        else            { rr = idx >> 6; cc = idx & 63; }
+        const int64_t gr = r0 + rr, gc = c0 + cc;
+        double v = 0.0;
+        if (gr < R && gc < Cc) v = TRANSPOSED ? P[gc * ld + gr] : P[gr * ld + gc];
+        tile[rr][cc] = v;
+    }
+    __syncthreads();
+    const int64_t slice = Rp * Cp;
+#pragma unroll 2
+    for (int i = 0; i < 16; ++i) {
+        const int idx = tid + 256 * i;
+        const int rr = idx >> 6, cc = idx & 63;
+        const int64_t gr = r0 + rr, gc = c0 + cc;
+        if (gr >= Rp || gc >= Cp) continue;
+        const int ee = gr < R ? exp_or_zero(e[gr]) : 0;
+        double rem = ldexp(tile[rr][cc], -ee);
+        uint16_t* o = out + gr * Cp + gc;
+        for (int s = 0; s < S; ++s) {
+            const int w = kB0 + s * kB;
+            const double d = rint(ldexp(rem, w));
+            o[s * slice] = (uint16_t)(__float_as_uint((float)d) >> 16);  // exact: |d| <= 256
+            rem = rem - ldexp(d, -w);
+        }
+    }
+}
+
+// One diagonal d of the slice products for the 128 x 128 C tile of this
+// workgroup: Q = sum_{s=0..d} D^A_s D^B_{d-s} over the padded k range, then
+// the recombination step of s4.  SA is [S][mp][kp], SB is [S][np][kp] (B
+// stored column by column), both BF16, zero-padded.
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(512) void k_split_diag(int64_t M, int64_t N, int64_t kp, int d,
+                                                    const uint16_t* __restrict__ SA,
+                                                    const uint16_t* __restrict__ SB, int64_t sa_stride,
+                                                    int64_t sb_stride, int shift, const int* __restrict__ ea,
+                                                    const int* __restrict__ eb, double* __restrict__ V,
+                                                    int64_t ldv, double alpha, double beta,
+                                                    double* __restrict__ C, int64_t ldc, Sched sc) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][kMT * kLdsPitch];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kMT * kLdsPitch];
+    int tm, tn;
+    decode_tile(sc, blockIdx.x, tm, tn);
+    const int64_t m0 = sc.m_off + (int64_t)tm * kMT, n0 = sc.n_off + (int64_t)tn * kMT;
+    // 8 waves as 2 (m) x 4 (n); each wave owns a 64 x 32 sub-tile: 4 x 2
+    // blocks of 16 x 16.
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
+    const int li = lane & 15, lk = lane >> 4;
+
+    f4 acc[4][2];
+    double q[4][2][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) q[i][j][r] = 0.0;
+        }
+
+    // staging: each thread moves 2 x 16 bytes of A and of B per k-slice;
+    // chunk c = tid + 512 i covers row c / 8, bytes 16 (c % 8) of the row.
+    uint4 ra0, ra1, rb0, rb1;
+    const int nks = (int)(kp / kKS);
+    const int total = (d + 1) * nks;
+    const int row0 = tid >> 3, row1 = (tid + 512) >> 3, chb = (tid & 7) * 8;
+#define MOMMS_SPLIT_GLOAD(t_)                                                                       \
+    do {                                                                                          \
+        const int s_ = (t_) / nks;                                                                \
+        const int64_t kk_ = (int64_t)((t_) - s_ * nks) * kKS;                                     \
+        const uint16_t* pa_ = SA + (int64_t)s_ * sa_stride + m0 * kp + kk_ + chb;                 \
+        const uint16_t* pb_ = SB + (int64_t)(d - s_) * sb_stride + n0 * kp + kk_ + chb;           \
+        ra0 = *reinterpret_cast<const uint4*>(pa_ + (int64_t)row0 * kp);                          \
+        ra1 = *reinterpret_cast<const uint4*>(pa_ + (int64_t)row1 * kp);                          \
+        rb0 = *reinterpret_cast<const uint4*>(pb_ + (int64_t)row0 * kp);                          \
+        rb1 = *reinterpret_cast<const uint4*>(pb_ + (int64_t)row1 * kp);                          \
+    } while (0)
+#define MOMMS_SPLIT_LSTORE(buf_)                                                                  \
+    do {                                                                                          \
+        *reinterpret_cast<uint4*>(&As[buf_][row0 * kLdsPitch + chb]) = ra0;                       \
+        *reinterpret_cast<uint4*>(&As[buf_][row1 * kLdsPitch + chb]) = ra1;                       \
+        *reinterpret_cast<uint4*>(&Bs[buf_][row0 * kLdsPitch + chb]) = rb0;                       \
+        *reinterpret_cast<uint4*>(&Bs[buf_][row1 * kLdsPitch + chb]) = rb1;                       \
+    } while (0)
+
+    MOMMS_SPLIT_GLOAD(0);
+    MOMMS_SPLIT_LSTORE(0);
+    __syncthreads();
+    for (int t = 0; t < total; ++t) {
+        const int cur = t & 1;
+        const bool more = t + 1 < total;
+        if (more) MOMMS_SPLIT_GLOAD(t + 1);
+#pragma unroll
+        for (int ks = 0; ks < kKS / 32; ++ks) {
+            bf16x8 a[4], b[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][(wm * 64 + i * 16 + li) * kLdsPitch + ks * 32 + 8 * lk]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(wn * 32 + j * 16 + li) * kLdsPitch + ks * 32 + 8 * lk]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) MOMMS_SPLIT_LSTORE(cur ^ 1);
+        // 4 k-slices = 256 products per accumulator: fold the exact FP32
+        // integers into FP64 before they could reach 2^24.
+        if ((t & 3) == 3 || !more) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) q[i][j][r] += (double)acc[i][j][r];
+                    acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+        __syncthreads();
+    }
+
+#undef MOMMS_SPLIT_GLOAD
+#undef MOMMS_SPLIT_LSTORE
+    // s4: lane (li, lk) holds rows 4 lk + r, column li of each 16 x 16 block.
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm * 64 + i * 16 + 4 * lk + r;
+                const int64_t col = n0 + wn * 32 + j * 16 + li;
+                if (row >= M || col >= N) continue;
+                const double term = ldexp(q[i][j][r], -shift);
+                const double v = FIRST ? term : __dadd_rn(V[row * ldv + col], term);
+                if (LAST) {
+                    const double T = ldexp(v, exp_or_zero(ea[row]) + exp_or_zero(eb[col]));
+                    double o = __dmul_rn(alpha, T);
+                    if (beta != 0.0) o = __dadd_rn(o, __dmul_rn(beta, C[row * ldc + col]));
+                    C[row * ldc + col] = o;
+                } else {
+                    V[row * ldv + col] = v;
+                }
+            }
+}
+
+// C = beta * C (beta == 0 writes zeros).
+__global__ __launch_bounds__(256) void k_scale(int64_t M, int64_t N, double beta, double* __restrict__ C,
+                                               int64_t ldc) {
+    const int64_t total = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / N, j = e - (e / N) * N;
+        C[i * ldc + j] = beta == 0.0 ? 0.0 : beta * C[i * ldc + j];
+    }
+}
+
+struct Layout {
+    int64_t mp, np, kp;
+    size_t off_ea, off_eb, off_sa, off_sb, off_v, total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Layout layout(int64_t m, int64_t n, int64_t k, int S) {
+    Layout L;
+    L.mp = rup(m > 0 ? m : 1, kMT);
+    L.np = rup(n > 0 ? n : 1, kMT);
+    L.kp = rup(k > 0 ? k : 1, kKPad);
+    size_t o = 0;
+    L.off_ea = o; o = align256(o + sizeof(int) * (size_t)m);
+    L.off_eb = o; o = align256(o + sizeof(int) * (size_t)n);
+    L.off_sa = o; o = align256(o + sizeof(uint16_t) * (size_t)S * L.mp * L.kp);
+    L.off_sb = o; o = align256(o + sizeof(uint16_t) * (size_t)S * L.np * L.kp);
+    L.off_v = o;  o = align256(o + (S > 1 ? sizeof(double) * (size_t)m * n : 0));
+    L.total = o;
+    return L;
+}
+
+template <bool F, bool L>
+static void launch_diag(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t kp, int d, const uint16_t* SA,
+                        const uint16_t* SB, int64_t sas, int64_t sbs, int shift, const int* ea, const int* eb,
+                        double* V, int64_t ldv, double alpha, double beta, double* C, int64_t ldc, Sched s) {
+    hipLaunchKernelGGL((k_split_diag<F, L>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs, shift, ea, eb, V,
+                       ldv, alpha, beta, C, ldc, s);
+}
+
+}  // namespace split
+}  // namespace momms
+
+extern "C" {
+
+size_t momms_split_workspace_size(int64_t m, int64_t n, int64_t k, int slices, int slice_type) {
+    if (m < 0 || n < 0 || k < 0 || slices < 1 || slices > 8 || slice_type != MOMMS_SLICE_BF16) return 0;
+    return momms::split::layout(m, n, k, slices).total;
+}
+
+int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                     int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int slices,
+                     int slice_type, int family_member, void* workspace, size_t ws_bytes,
+                     momms_stream_t stream) {
+    using namespace momms;
+    using namespace momms::split;
+    const bool ta = transA != 0, tb = transB != 0;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const bool reads_ab = (alpha != 0.0) && k > 0 && m > 0 && n > 0;
+    if (reads_ab && A == nullptr) return -7;
+    if (lda < (ta ? (m > 1 ? m : 1) : (k > 1 ? k : 1))) return -8;
+    if (reads_ab && B == nullptr) return -9;
+    if (ldb < (tb ? (k > 1 ? k : 1) : (n > 1 ? n : 1))) return -10;
+    if (m > 0 && n > 0 && C == nullptr) return -12;
+    if (ldc < (n > 1 ? n : 1)) return -13;
+    if (slices < 1 || slices > 8) return -14;
+    if (slice_type != MOMMS_SLICE_BF16) return -15;
+    if (family_member != MOMMS_AUTO && family_member != MOMMS_C0 && family_member != MOMMS_C3C0) return -16;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return -17;
+    const Layout L = layout(m, n, k, slices);
+    if (reads_ab && (workspace == nullptr || ws_bytes < L.total)) return -18;
+    if (cdiv(m, kMT) * cdiv(n, kMT) >= (int64_t)INT_MAX / 2) return MOMMS_ERR_INFEASIBLE;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (m == 0 || n == 0) return 0;
+    if ((alpha == 0.0 || k == 0) && beta == 1.0) return 0;
+    if (alpha == 0.0 || k == 0) {
+        int grid = (int)cdiv(m * n, 256);
+        if (grid > 16384) grid = 16384;
+        hipLaunchKernelGGL(k_scale, dim3(grid), dim3(256), 0, st, m, n, beta, C, ldc);
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? 0 : (int)e;
+    }
+    char* ws = static_cast<char*>(workspace);
+    int* ea = reinterpret_cast<int*>(ws + L.off_ea);
+    int* eb = reinterpret_cast<int*>(ws + L.off_eb);
+    uint16_t* SA = reinterpret_cast<uint16_t*>(ws + L.off_sa);
+    uint16_t* SB = reinterpret_cast<uint16_t*>(ws + L.off_sb);
+    double* V = reinterpret_cast<double*>(ws + L.off_v);
+
+    // s1: exponents of the rows of op(A) and the columns of op(B)
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, ea, m, kExpNone);
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, eb, n, kExpNone);
+    const int64_t chunk = 1024;
+    if (!ta)  // rows of A
+        hipLaunchKernelGGL(k_rowmax_exp, dim3((unsigned)cdiv(m, 4), (unsigned)cdiv(k, chunk)), dim3(256), 0, st, A,
+                           lda, m, k, chunk, ea);
+    else      // A stored k x m: columns
+        hipLaunchKernelGGL(k_colmax_exp, dim3((unsigned)cdiv(m, 256), (unsigned)cdiv(k, chunk)), dim3(256), 0, st,
+                           A, lda, k, m, chunk, ea);
+    if (!tb)  // B stored k x n: columns
+        hipLaunchKernelGGL(k_colmax_exp, dim3((unsigned)cdiv(n, 256), (unsigned)cdiv(k, chunk)), dim3(256), 0, st,
+                           B, ldb, k, n, chunk, eb);
+    else      // B stored n x k: rows
+        hipLaunchKernelGGL(k_rowmax_exp, dim3((unsigned)cdiv(n, 4), (unsigned)cdiv(k, chunk)), dim3(256), 0, st, B,
+                           ldb, n, k, chunk, eb);
+    // s2: slices.  A side X = op(A) (m x k); B side X = op(B)^T (n x k).
+    {
+        const dim3 ga((unsigned)cdiv(L.kp, 64), (unsigned)cdiv(L.mp, 64));
+        if (!ta) hipLaunchKernelGGL((k_slice<false>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
+        else     hipLaunchKernelGGL((k_slice<true>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
+        const dim3 gb((unsigned)cdiv(L.kp, 64), (unsigned)cdiv(L.np, 64));
+        if (!tb) hipLaunchKernelGGL((k_slice<true>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
+        else     hipLaunchKernelGGL((k_slice<false>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
+    }
+    // s3 + s4: one launch per diagonal, smallest first.
+    Sched s;
+    s.m_off = 0;
+    s.n_off = 0;
+    s.m_lim = m;
+    s.n_lim = n;
+    s.tiles_m = (int)cdiv(m, kMT);
+    s.tiles_n = (int)cdiv(n, kMT);
+    const bool grouped = family_member != MOMMS_C0;
+    s.group_m = grouped ? (s.tiles_m < 8 ? s.tiles_m : 8) : 1;
+    s.xcd = grouped ? kXcds : 1;
+    const dim3 grid((unsigned)(s.tiles_m * s.tiles_n));
+    const int64_t sas = L.mp * L.kp, sbs = L.np * L.kp;
+    for (int d = slices - 1; d >= 0; --d) {
+        const int shift = 2 * kB0 + d * kB;
+        const bool first = d == slices - 1, last = d == 0;
+        if (first && last)
+            launch_diag<true, true>(grid, st, m, n, L.kp, d, SA, SB, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
+                                    ldc, s);
+        else if (first)
+            launch_diag<true, false>(grid, st, m, n, L.kp, d, SA, SB, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
+                                     ldc, s);
+        else if (last)
+            launch_diag<false, true>(grid, st, m, n, L.kp, d, SA, SB, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
+                                     ldc, s);
+        else
+            launch_diag<false, false>(grid, st, m, n, L.kp, d, SA, SB, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
+                                      ldc, s);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+}  // extern "C"

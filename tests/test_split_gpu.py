@@ -1,0 +1,112 @@
+"""Parity of the split-precision GPU path with its CPU emulation (bit for bit:
+every step but the fixed-order recombination is exact) and with the FP64
+oracle (per-entry error bound; 1e-13 of |A||B| at seven slices)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from oracle import split_emul as se
+
+pytestmark = pytest.mark.gpu
+mm = pytest.importorskip("paper_1904_05717_amd")
+DEV = "cuda:0"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def run(A, B, C, alpha, beta, S, member="AUTO", ta=False, tb=False):
+    Cd = dev(C.copy()) if C is not None else None
+    out = mm.gemm_split(dev(A), dev(B), Cd, alpha=alpha, beta=beta, slices=S, member=member, transA=ta, transB=tb)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("S", [1, 2, 3, 5, 7, 8])
+@pytest.mark.parametrize("kind", ["uniform", "loguniform"])
+def test_bit_exact_against_emulation(S, kind):
+    m = n = k = 256
+    A, B, C = workloads.gemm_operands(m, n, k, kind=kind)
+    want = se.split_gemm(A, B, S, "bf16", C, 1.0, 1.0)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, S), want)
+
+
+@pytest.mark.parametrize("shape", [(300, 280, 260), (1, 1, 1), (129, 7, 65), (17, 200, 3)])
+@pytest.mark.parametrize("member", ["AUTO", "C0"])
+def test_ragged_shapes_bit_exact(shape, member):
+    m, n, k = shape
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = se.split_gemm(A, B, 6, "bf16", C, -1.5, 0.25)
+    np.testing.assert_array_equal(run(A, B, C, -1.5, 0.25, 6, member), want)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, True), (True, False), (True, True)])
+def test_transposed_operands_bit_exact(ta, tb):
+    m, n, k = 200, 150, 170
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = se.split_gemm(A, B, 5, "bf16", C, 1.0, 1.0)
+    got = run(A.T.copy() if ta else A, B.T.copy() if tb else B, C, 1.0, 1.0, 5, ta=ta, tb=tb)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_integers_exact():
+    m, n, k = 160, 144, 300
+    A, B, C = workloads.gemm_operands(m, n, k, kind="int")
+    want = (A.astype(np.int64) @ B.astype(np.int64) + C.astype(np.int64)).astype(np.float64)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, 1), want)
+
+
+def test_zero_rows_columns_and_beta_zero_nan():
+    m, n, k = 130, 120, 90
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform")
+    A[5] = 0.0
+    B[:, 7] = 0.0
+    Cn = np.full((m, n), np.nan)
+    got = run(A, B, Cn, 1.0, 0.0, 4)
+    np.testing.assert_array_equal(got, se.split_gemm(A, B, 4, "bf16"))
+    assert (got[5] == 0).all() and (got[:, 7] == 0).all()
+
+
+def test_error_against_fp64_oracle():
+    m, n, k = 192, 160, 512
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = oracle.gemm(A, B)
+    absab = np.abs(A) @ np.abs(B)
+    got7 = run(A, B, None, 1.0, 0.0, 7)
+    assert np.max(np.abs(got7 - want) / absab) <= 1e-13
+    e = se.exponents(A, 1)
+    f = se.exponents(B, 0)
+    for S in (3, 6):
+        got = run(A, B, None, 1.0, 0.0, S)
+        tau = 2.0 ** -(8 + (S - 1) * 9 + 1)
+        bound = (S + 2) * 1.01 * tau * k * np.ldexp(1.0, e[:, None] + f[None, :]) + (S + 2) * 2.0 ** -53 * absab
+        assert np.all(np.abs(got - want) <= bound), S
+
+
+def test_argument_errors():
+    f = mm._lib.momms_gemm_split
+    big = 1 << 20
+    assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 0, 0, 0, big, 1 << 30, None) == -14
+    assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 9, 0, 0, big, 1 << 30, None) == -14
+    assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 3, 7, 0, big, 1 << 30, None) == -15
+    assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 3, 0, 5, big, 1 << 30, None) == -16
+    assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 3, 0, 0, big + 8, 1 << 30, None) == -17
+    assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 3, 0, 0, big, 16, None) == -18
+
+
+def test_config3_sampled_8192():
+    # m = n = k = 8192, signed log-uniform over [1e-8, 1e8], seven BF16 slices.
+    m = n = k = 8192
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform", with_c=False)
+    got = run(A, B, None, 1.0, 0.0, 7)
+    rng = np.random.Generator(np.random.PCG64(3))
+    rows = np.concatenate([rng.integers(0, m, 300), [0, m - 1, 127, 128]])
+    cols = np.concatenate([rng.integers(0, n, 300), [n - 1, 0, 128, 127]])
+    emu = se.split_gemm_entries(A, B, rows, cols, 7, "bf16")
+    np.testing.assert_array_equal(got[rows, cols], emu)
+    exact = oracle.gemm_entries(A, B, rows, cols)
+    absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
+    assert np.max(np.abs(got[rows, cols] - exact) / absab) <= 1e-13
