@@ -206,6 +206,40 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k,
                      int family_member, void *workspace, size_t ws_bytes,
                      momms_stream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Batched uneven FP64 GEMMs.  momms_batch_create builds a plan for `count`
+ * independent problems C_i := alpha_i A_i B_i + beta_i C_i (row-major, no
+ * transposition; all pointer arrays are HOST arrays holding DEVICE
+ * pointers): it picks each problem's register tile (`tile` may be NULL or
+ * hold 0 = choose by the analytic prior, 64, or 128 per problem), uploads a
+ * descriptor table and a work queue of (problem, tile) items ordered by
+ * decreasing work, and captures a hipGraph of one persistent kernel launch
+ * (plus the kernel that resets the queue counter).  The plan owns that
+ * device memory (allocated here, freed by momms_batch_destroy) and keeps the
+ * caller's matrix pointers: they must stay valid while the plan is used.
+ * Argument numbers: 1 out, 2 count, 3 m, 4 n, 5 k, 6 A, 7 lda, 8 B, 9 ldb,
+ * 10 C, 11 ldc, 12 alpha, 13 beta, 14 tile.  A per-problem argument error
+ * returns the number of that array.  Synchronous (copies the tables).
+ */
+typedef struct momms_batch momms_batch;
+
+int momms_batch_create(momms_batch **out, int count, const int64_t *m, const int64_t *n,
+                       const int64_t *k, const double *const *A, const int64_t *lda,
+                       const double *const *B, const int64_t *ldb, double *const *C,
+                       const int64_t *ldc, const double *alpha, const double *beta,
+                       const int *tile);
+/* Replays the captured graph on `stream` (asynchronous).  Runs of one plan
+ * must not overlap (they share the queue counter).  1 plan, 2 stream. */
+int momms_batch_run(momms_batch *plan, momms_stream_t stream);
+/* Plan facts: queue items, persistent workgroups, total 2mnk flops, and the
+ * register tile chosen per problem (`tiles` holds count entries).  Any
+ * output pointer may be NULL. */
+int momms_batch_info(const momms_batch *plan, int64_t *items, int64_t *workgroups,
+                     double *flops, int *tiles);
+int momms_batch_destroy(momms_batch *plan);
+/* The analytic prior's register tile (64 or 128) for one problem. */
+int momms_batch_select_tile(int64_t m, int64_t n, int64_t k);
+
 #ifdef __cplusplus
 }
 #endif

@@ -148,3 +148,67 @@ def gemm_split(A, B, C=None, alpha=1.0, beta=0.0, slices=7, slice_type="bf16", m
                                workspace.numel() * workspace.element_size(), _stream_handle(stream))
     check_status(st, "momms_gemm_split")
     return C
+
+
+class BatchPlan:
+    """Batched uneven GEMMs C_i := alpha_i A_i B_i + beta_i C_i (C ABI momms_batch_*).
+
+    `problems` is a list of (A, B, C, alpha, beta) with float64 row-major
+    device tensors.  `tiles` optionally fixes each problem's register tile
+    (64 or 128; 0 = the library's analytic prior).  The plan keeps references
+    to the tensors so their memory stays valid while it exists.
+    """
+
+    def __init__(self, problems, tiles=None):
+        import ctypes
+        self._keep = list(problems)
+        n = len(problems)
+        I64 = ctypes.c_int64 * n
+        P = ctypes.c_void_p * n
+        D = ctypes.c_double * n
+        ms, ns, ks, lda, ldb, ldc = [], [], [], [], [], []
+        pa, pb, pc, al, be = [], [], [], [], []
+        for (A, B, C, alpha, beta) in problems:
+            m, k = A.shape
+            k2, nn = B.shape
+            if k != k2 or tuple(C.shape) != (m, nn):
+                raise ValueError("batch problem shapes do not match")
+            ms.append(m); ns.append(nn); ks.append(k)
+            lda.append(_ld(A, "A")); ldb.append(_ld(B, "B")); ldc.append(_ld(C, "C"))
+            pa.append(A.data_ptr()); pb.append(B.data_ptr()); pc.append(C.data_ptr())
+            al.append(float(alpha)); be.append(float(beta))
+        tl = None
+        if tiles is not None:
+            tl = (ctypes.c_int * n)(*[int(t) for t in tiles])
+        self.count = n
+        self._h = ctypes.c_void_p()
+        st = _lib.momms_batch_create(ctypes.byref(self._h), n, I64(*ms), I64(*ns), I64(*ks), P(*pa), I64(*lda),
+                                     P(*pb), I64(*ldb), P(*pc), I64(*ldc), D(*al), D(*be), tl)
+        check_status(st, "momms_batch_create")
+
+    def run(self, stream=None):
+        check_status(_lib.momms_batch_run(self._h, _stream_handle(stream)), "momms_batch_run")
+
+    def info(self):
+        import ctypes
+        items, wgs, flops = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        tiles = (ctypes.c_int * max(self.count, 1))()
+        check_status(_lib.momms_batch_info(self._h, ctypes.byref(items), ctypes.byref(wgs), ctypes.byref(flops),
+                                           tiles), "momms_batch_info")
+        return {"items": items.value, "workgroups": wgs.value, "flops": flops.value,
+                "tiles": list(tiles)[:self.count]}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.momms_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_select_tile(m, n, k):
+    return int(_lib.momms_batch_select_tile(m, n, k))

@@ -65,10 +65,22 @@ momms_split_workspace_size = _fn("momms_split_workspace_size", sz, [i64, i64, i6
 momms_gemm_split = _fn("momms_gemm_split", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64,
                                                  i32, i32, i32, vp, sz, vp])
 
+_pp = ctypes.POINTER(ctypes.c_void_p)
+_pi64 = ctypes.POINTER(i64)
+_pdbl = ctypes.POINTER(dbl)
+_pi32 = ctypes.POINTER(i32)
+momms_batch_create = _fn("momms_batch_create", i32, [_pp, i32, _pi64, _pi64, _pi64, _pp, _pi64, _pp, _pi64, _pp,
+                                                     _pi64, _pdbl, _pdbl, _pi32])
+momms_batch_run = _fn("momms_batch_run", i32, [vp, vp])
+momms_batch_info = _fn("momms_batch_info", i32, [vp, _pi64, _pi64, _pdbl, _pi32])
+momms_batch_destroy = _fn("momms_batch_destroy", i32, [vp])
+momms_batch_select_tile = _fn("momms_batch_select_tile", i32, [i64, i64, i64])
+
 EXPORTS = [
     "momms_gemm", "momms_gemm_ex", "momms_workspace_size", "momms_set_stream", "momms_num_members",
     "momms_member_name", "momms_member_id", "momms_member_plan", "momms_model_bytes",
     "momms_select_member", "momms_status_string", "momms_split_workspace_size", "momms_gemm_split",
+    "momms_batch_create", "momms_batch_run", "momms_batch_info", "momms_batch_destroy", "momms_batch_select_tile",
 ]
 
 

@@ -17,6 +17,18 @@
 
 namespace momms {
 
+// C = beta * C over an m x n matrix (beta == 0 writes zeros without reading).
+__global__ __launch_bounds__(256) void k_scale_c(int64_t M, int64_t N, double beta, double* __restrict__ C,
+                                                 int64_t ldc) {
+    const int64_t total = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / N, j = e - (e / N) * N;
+        double* p = C + i * ldc + j;
+        *p = (beta == 0.0) ? 0.0 : beta * (*p);
+    }
+}
+
 using CfgL = TileCfg<128, 128, 16, 2, 2>;  // register-resident C, large problems
 using CfgS = TileCfg<64, 64, 16, 2, 2>;    // register-resident C, small problems
 using CfgK = TileCfg<128, 128, 8, 2, 2>;   // LDS-resident A or B block

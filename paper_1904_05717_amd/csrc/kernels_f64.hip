@@ -101,6 +101,44 @@ struct FastStage {
     }
 };
 
+// Predicated staging for any tile: like FastStage (one pointer per thread,
+// wave-uniform stride), but each thread knows how many of its N elements lie
+// inside the operand (nv) and whether its contiguous coordinate does; the
+// others read as zero.  For an interior tile every element is valid.
+template <int R, int S, int THREADS, bool TRANS>
+struct PStage {
+    static constexpr int N = (R * S) / THREADS;
+    static constexpr int CONT = TRANS ? R : S;       // contiguous extent
+    static_assert(THREADS % CONT == 0, "threads must cover whole contiguous rows");
+    static constexpr int RPP = THREADS / CONT;       // strided positions per pass
+    double v[N];
+
+    // X(r, s) = P[(r0 + r) * ld + s0 + s] (!TRANS) or P[(s0 + s) * ld + r0 + r]
+    // (TRANS); valid where r0 + r < rlim and s0 + s < slim.
+    __device__ __forceinline__ void load(const double* __restrict__ P, int64_t ld, int64_t r0, int64_t s0,
+                                         int64_t rlim, int64_t slim, int tid) {
+        const int c = tid % CONT, q = tid / CONT;
+        const int64_t gc = (TRANS ? r0 : s0) + c, lim_c = TRANS ? rlim : slim;
+        const int64_t gq = (TRANS ? s0 : r0) + q, lim_q = TRANS ? slim : rlim;
+        const int64_t rem = lim_q - gq;
+        int nv = rem <= 0 ? 0 : (int)((rem + RPP - 1) / RPP);
+        if (nv > N || gc >= lim_c) nv = gc >= lim_c ? 0 : N;
+        const double* p = P + gq * ld + gc;
+        const int64_t step = (int64_t)RPP * ld;
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = (i < nv) ? p[i * step] : 0.0;
+    }
+    __device__ __forceinline__ void store(double* __restrict__ L, int lld, int tid) const {
+        const int c = tid % CONT, q = tid / CONT;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int rr = q + i * RPP;
+            if (TRANS) L[c * lld + rr] = v[i];
+            else       L[rr * lld + c] = v[i];
+        }
+    }
+};
+
 // Micro-kernel: acc += A(:, a_k0 : a_k0 + 4*ksteps) * B(b_k0 : ..., :) from LDS.
 // A is read from As[m][k] (pitch a_ld), B from Bs[k][n] (pitch b_ld).
 template <class CF, int KSTEPS>
@@ -159,33 +197,31 @@ __device__ __forceinline__ void store_c(const d4 (&acc)[CF::BM][CF::BN], double 
 }
 
 // ---------------------------------------------------------------------------
-// k_regc: one C granule (MT x NT) per workgroup, accumulated in registers over
-// k in [k_begin, k_end); C = alpha*acc + beta*C at the end.
-template <class CF, bool TA, bool TB>
-__global__ __launch_bounds__(CF::THREADS) __attribute__((amdgpu_waves_per_eu(CF::MT >= 128 ? 2 : 1)))
-void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
-                                                      double alpha, const double* __restrict__ A, int64_t lda,
-                                                      const double* __restrict__ B, int64_t ldb, double beta,
-                                                      double* __restrict__ C, int64_t ldc, Sched s) {
-    __shared__ double As[2][CF::MT * CF::A_LD];
-    __shared__ double Bs[2][CF::KS * CF::B_LD];
-    int tm, tn;
-    decode_tile(s, blockIdx.x, tm, tn);
-    const int64_t m0 = s.m_off + (int64_t)tm * CF::MT;
-    const int64_t n0 = s.n_off + (int64_t)tn * CF::NT;
+// Register-resident C tile at (m0, n0): accumulate over k in [k_begin,
+// k_end) through the double-buffered LDS stage, then C = alpha*acc + beta*C.
+// (tm, tn) only staggers the k start (see below).  Shared by k_regc and the
+// persistent batched kernel.
+template <class CF, bool TA, bool TB, bool FAST_INTERIOR = true>
+__device__ __forceinline__ void regc_tile(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha,
+                                          const double* __restrict__ A, int64_t lda,
+                                          const double* __restrict__ B, int64_t ldb, double beta,
+                                          double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0, int tm,
+                                          int tn, double (*As)[CF::MT * CF::A_LD],
+                                          double (*Bs)[CF::KS * CF::B_LD]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / CF::WN, wn = wave % CF::WN;
 
     d4 acc[CF::BM][CF::BN];
     zero_acc<CF>(acc);
     const int64_t nsl = (k_end - k_begin + CF::KS - 1) / CF::KS;
-    const bool interior = (m0 + CF::MT <= M) && (n0 + CF::NT <= N) && ((k_end - k_begin) % CF::KS == 0);
+    // Tiles that share an A row panel (same tm) or a B column panel (same tn)
+    // start their k loops a few slices apart and wrap around, so the
+    // workgroups of one XCD do not all miss on the same lines at once.
+    const int64_t s0 = nsl > 0 ? (int64_t)((tm + tn) & 7) % nsl : 0;
+    const bool interior = FAST_INTERIOR && nsl > 0 && (m0 + CF::MT <= M) && (n0 + CF::NT <= N) &&
+                          ((k_end - k_begin) % CF::KS == 0);
     if (interior) {
-        // Whole tile inside the matrices: no bounds checks, pointer stepping.
-        // Tiles that share an A row panel (same tm) or a B column panel (same
-        // tn) start their k loops a few slices apart and wrap around, so the
-        // workgroups of one XCD do not all miss on the same lines at once.
-        const int64_t s0 = (int64_t)((tm + tn) & 7) % nsl;
+        // Whole tile inside the matrices: no predicates, pointer stepping.
         FastStage<CF::MT, CF::KS, CF::THREADS, TA> fa;
         FastStage<CF::KS, CF::NT, CF::THREADS, TB> fb;
         fa.init(A, lda, m0, k_begin + s0 * CF::KS, tid);
@@ -201,8 +237,7 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
             const int cur = (int)(sl & 1);
             const bool more = sl + 1 < nsl;
             if (more) {
-                // next slice index (s0 + sl + 1) mod nsl: wrap back to k_begin
-                const bool wrap = (s0 + sl + 1) == nsl;
+                const bool wrap = (s0 + sl + 1) == nsl;  // next slice index wraps to k_begin
                 fa.advance(wrap ? da * (1 - nsl) : da);
                 fb.advance(wrap ? db * (1 - nsl) : db);
                 fa.load();
@@ -215,14 +250,12 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
             }
             __syncthreads();
         }
-        store_c<CF>(acc, alpha, beta, C, ldc, m0, n0, M, N, wm, wn, lane);
-        return;
-    }
-    Stage<CF::MT, CF::KS, CF::THREADS, TA> sa;
-    Stage<CF::KS, CF::NT, CF::THREADS, TB> sb;
-    if (nsl > 0) {
-        sa.load(A, lda, m0, k_begin, M, k_end, tid);
-        sb.load(B, ldb, k_begin, n0, k_end, N, tid);
+    } else if (nsl > 0) {
+        PStage<CF::MT, CF::KS, CF::THREADS, TA> sa;
+        PStage<CF::KS, CF::NT, CF::THREADS, TB> sb;
+        int64_t kb = k_begin + s0 * CF::KS;
+        sa.load(A, lda, m0, kb, M, k_end, tid);
+        sb.load(B, ldb, kb, n0, k_end, N, tid);
         sa.store(As[0], CF::A_LD, tid);
         sb.store(Bs[0], CF::B_LD, tid);
         __syncthreads();
@@ -230,9 +263,11 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
             const int cur = (int)(sl & 1);
             const bool more = sl + 1 < nsl;
             if (more) {
-                const int64_t kn = k_begin + (sl + 1) * CF::KS;
-                sa.load(A, lda, m0, kn, M, k_end, tid);
-                sb.load(B, ldb, kn, n0, k_end, N, tid);
+                int64_t nx = s0 + sl + 1;
+                if (nx >= nsl) nx -= nsl;
+                kb = k_begin + nx * CF::KS;
+                sa.load(A, lda, m0, kb, M, k_end, tid);
+                sb.load(B, ldb, kb, n0, k_end, N, tid);
             }
             mma_lds<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs[cur], CF::B_LD, 0, acc, wm, wn, lane);
             if (more) {
@@ -243,6 +278,22 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
         }
     }
     store_c<CF>(acc, alpha, beta, C, ldc, m0, n0, M, N, wm, wn, lane);
+}
+
+// k_regc: one C granule (MT x NT) per workgroup, accumulated in registers over
+// k in [k_begin, k_end); C = alpha*acc + beta*C at the end.
+template <class CF, bool TA, bool TB>
+__global__ __launch_bounds__(CF::THREADS) __attribute__((amdgpu_waves_per_eu(CF::MT >= 128 ? 2 : 1)))
+void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha, const double* __restrict__ A,
+            int64_t lda, const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C,
+            int64_t ldc, Sched s) {
+    __shared__ double As[2][CF::MT * CF::A_LD];
+    __shared__ double Bs[2][CF::KS * CF::B_LD];
+    int tm, tn;
+    decode_tile(s, blockIdx.x, tm, tn);
+    const int64_t m0 = s.m_off + (int64_t)tm * CF::MT;
+    const int64_t n0 = s.n_off + (int64_t)tn * CF::NT;
+    regc_tile<CF, TA, TB>(M, N, k_begin, k_end, alpha, A, lda, B, ldb, beta, C, ldc, m0, n0, tm, tn, As, Bs);
 }
 
 // ---------------------------------------------------------------------------
@@ -401,18 +452,6 @@ __global__ __launch_bounds__(256) void k_pack_b(const double* __restrict__ B, in
         const int64_t p = rem / NT, q = rem - (rem / NT) * NT;
         const int64_t gk = pk0 + p, gn = pn0 + j * NT + q;
         P[e] = (gk < K && gn < N) ? (TB ? B[gn * ldb + gk] : B[gk * ldb + gn]) : 0.0;
-    }
-}
-
-// C = beta * C over an m x n matrix (beta == 0 writes zeros without reading).
-__global__ __launch_bounds__(256) void k_scale_c(int64_t M, int64_t N, double beta, double* __restrict__ C,
-                                                 int64_t ldc) {
-    const int64_t total = M * N;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / N, j = e - (e / N) * N;
-        double* p = C + i * ldc + j;
-        *p = (beta == 0.0) ? 0.0 : beta * (*p);
     }
 }
 
