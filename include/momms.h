@@ -173,6 +173,20 @@ int momms_select_member(int64_t m, int64_t n, int64_t k);
 
 const char *momms_status_string(int status);
 
+/* Element transfers of the resident algorithms of the paper (Sec. 2.2:
+ * Resident C with an mc x nc block, Resident A with mc x kc, Resident B with
+ * kc x nc), with ceilings at the margins, between a slow and a fast memory.
+ * resident is 'A', 'B' or 'C'; (b1, b2) is (mc, nc), (mc, kc) or (kc, nc)
+ * respectively.  counts[4] receives {A reads, B reads, C reads, C writes}
+ * (elements; beta == 0 skips the first read of C).  Host-only.  Argument
+ * numbers: 1 resident, 2 m, 3 n, 4 k, 5 b1, 6 b2, 7 beta, 8 counts. */
+int momms_model_resident(int resident, int64_t m, int64_t n, int64_t k, int64_t b1, int64_t b2,
+                         double beta, double *counts);
+/* Cost-balanced Resident A block for a fast memory of M elements when a B
+ * element costs beta_b and a C element beta_c (Sec. 2.4):
+ * mc = sqrt(beta_b/beta_c M), kc = sqrt(beta_c/beta_b M).  Host-only. */
+int momms_balanced_block(double M, double beta_b, double beta_c, double *mc, double *kc);
+
 /* ---------------------------------------------------------------------
  * Split-precision FP64-accurate product (Ozaki-style error-free splitting;
  * Ozaki, Ogita, Oishi & Rump, Numer. Algorithms 59, 2012 - the paper itself

@@ -212,3 +212,20 @@ class BatchPlan:
 
 def batch_select_tile(m, n, k):
     return int(_lib.momms_batch_select_tile(m, n, k))
+
+
+def model_resident(resident, m, n, k, b1, b2, beta=1.0):
+    """Sec. 2.2 transfer counts: {a_reads, b_reads, c_reads, c_writes} in elements."""
+    import ctypes
+    out = (ctypes.c_double * 4)()
+    check_status(_lib.momms_model_resident(ord(resident), m, n, k, b1, b2, float(beta), out),
+                 "momms_model_resident")
+    return {"a_reads": out[0], "b_reads": out[1], "c_reads": out[2], "c_writes": out[3]}
+
+
+def balanced_block(M, beta_b, beta_c):
+    import ctypes
+    mc, kc = ctypes.c_double(), ctypes.c_double()
+    check_status(_lib.momms_balanced_block(float(M), float(beta_b), float(beta_c), ctypes.byref(mc),
+                                           ctypes.byref(kc)), "momms_balanced_block")
+    return mc.value, kc.value

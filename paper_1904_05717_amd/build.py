@@ -1,6 +1,8 @@
 """Compile the HIP library libmomms.so for gfx950 in-tree.
 
-    python -m paper_1904_05717_amd.build
+    python paper_1904_05717_amd/build.py     (or __graft_entry__.build())
+
+Run it as a file: importing the package loads the library this builds.
 
 Every HIP source is compiled with hipcc for gfx950 only, with packed-FP32
 instructions disabled, into paper_1904_05717_amd/libmomms.so.

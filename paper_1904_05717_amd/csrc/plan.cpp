@@ -177,6 +177,39 @@ size_t workspace_bytes(int member, int64_t m, int64_t n, int64_t k) {
     return (size_t)(kKC * cdiv(nc, 128) * 128) * sizeof(double);
 }
 
+// Element transfers of the resident algorithms of Sec. 2.2 between a slow
+// and a fast memory, with the ceilings kept at the margins:
+//   Resident C (b1 x b2 = mc x nc): A read ceil(n/nc) times, B ceil(m/mc)
+//     times, C read and written once.
+//   Resident A (b1 x b2 = mc x kc): A read once, B ceil(m/mc) times, C read
+//     and written once per kc block of k.
+//   Resident B (b1 x b2 = kc x nc): B read once, A ceil(n/nc) times, C read
+//     and written once per kc block of k.
+// With beta == 0 the first read of each C entry is skipped.  counts = {A
+// reads, B reads, C reads, C writes} in elements.
+void resident_counts(int resident, int64_t m, int64_t n, int64_t k, int64_t b1, int64_t b2, double beta,
+                     double* counts) {
+    const double M = (double)m, N = (double)n, K = (double)k;
+    double a, b, passes;
+    if (resident == 'C') {
+        a = M * K * (double)cdiv(n, b2);
+        b = K * N * (double)cdiv(m, b1);
+        passes = 1.0;
+    } else if (resident == 'A') {
+        a = M * K;
+        b = K * N * (double)cdiv(m, b1);
+        passes = k > 0 ? (double)cdiv(k, b2) : 1.0;
+    } else {
+        a = M * K * (double)cdiv(n, b2);
+        b = K * N;
+        passes = k > 0 ? (double)cdiv(k, b1) : 1.0;
+    }
+    counts[0] = a;
+    counts[1] = b;
+    counts[2] = M * N * (passes - 1.0 + (beta != 0.0 ? 1.0 : 0.0));
+    counts[3] = M * N * passes;
+}
+
 // ---------------------------------------------------------------------------
 // Data-movement model.  Element counts of Sec. 2.2 with the ceilings the
 // paper keeps at the margins, applied to the loop nest of each member:
@@ -412,6 +445,34 @@ size_t momms_workspace_size(int64_t m, int64_t n, int64_t k, int member) {
     if (m < 0 || n < 0 || k < 0 || member < 0 || member >= MOMMS_NUM_MEMBERS) return 0;
     if (member == MOMMS_AUTO) member = momms::select_member(m, n, k);
     return momms::workspace_bytes(member, m, n, k);
+}
+
+int momms_model_resident(int resident, int64_t m, int64_t n, int64_t k, int64_t b1, int64_t b2, double beta,
+                         double* counts) {
+    if (resident != 'A' && resident != 'B' && resident != 'C') return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (k < 0) return -4;
+    if (b1 < 1) return -5;
+    if (b2 < 1) return -6;
+    if (!counts) return -8;
+    momms::resident_counts(resident, m, n, k, b1, b2, beta, counts);
+    return 0;
+}
+
+int momms_balanced_block(double M, double beta_b, double beta_c, double* mc, double* kc) {
+    if (!(M > 0)) return -1;
+    if (!(beta_b > 0)) return -2;
+    if (!(beta_c > 0)) return -3;
+    if (!mc) return -4;
+    if (!kc) return -5;
+    // Resident A with streamed B (cost beta_b per element) and C (beta_c):
+    // flops per unit cost 2 mc / beta_b + 2 kc / beta_c is largest, with
+    // mc kc = M, at mc = sqrt(beta_b / beta_c * M), kc = sqrt(beta_c / beta_b * M)
+    // (Sec. 2.4).
+    *mc = std::sqrt(beta_b / beta_c * M);
+    *kc = std::sqrt(beta_c / beta_b * M);
+    return 0;
 }
 
 const char* momms_status_string(int status) {

@@ -1,0 +1,106 @@
+"""Pins of the data-movement model (library, host-only) against an
+independent brute-force simulation and the paper's printed numbers.
+
+* The resident algorithms of Sec. 2.2 are run element by element through an
+  LRU fast memory that holds the resident block plus two streamed rows and
+  columns (Sec. 4.1: under LRU the panels a loop exposes must fit beside the
+  block): when the blocks divide the matrices the simulated transfers equal
+  the model's counts exactly; with ragged margins the spare room can only
+  save transfers.
+* Belady's optimal replacement never needs more than the model and never
+  fewer than the I/O lower bound of Sec. 2.1, 2mnk/sqrt(M) - 2M reads.
+* The paper's analysed intensities (Sec. 5.2): Goto's algorithm with
+  k_c = 192, n_c = 3000 reaches 23.26 flop/byte and B3A2C0 with a 768 x 768
+  block 64 flop/byte; the balanced blocksizes of Sec. 2.4.
+"""
+import math
+
+import pytest
+
+import paper_1904_05717_amd as mm
+from oracle import cache_sim as cs
+
+CASES = [("C", (3, 2)), ("A", (3, 4)), ("B", (4, 2)), ("C", (4, 4)), ("A", (4, 3)), ("B", (2, 5))]
+
+
+def model(res, shape, b, beta):
+    return {k: int(v) for k, v in mm.model_resident(res, *shape, *b, beta).items()}
+
+
+@pytest.mark.parametrize("res,b", CASES)
+@pytest.mark.parametrize("beta", [1.0, 0.0])
+def test_lru_equals_model_when_blocks_divide(res, b, beta):
+    # shapes that are multiples of every block dimension involved
+    b1, b2 = b
+    if res == "C":
+        shape = (2 * b1, 3 * b2, 5)
+    elif res == "A":
+        shape = (3 * b1, 4, 2 * b2)
+    else:
+        shape = (4, 3 * b2, 2 * b1)
+    assert cs.simulate_lru(res, *shape, b1, b2, beta) == model(res, shape, b, beta)
+
+
+@pytest.mark.parametrize("res,b", CASES)
+@pytest.mark.parametrize("shape", [(7, 5, 6), (6, 4, 8), (12, 10, 9)])
+def test_ragged_margins_never_exceed_model(res, b, shape):
+    for beta in (1.0, 0.0):
+        sim = cs.simulate_lru(res, *shape, *b, beta)
+        mod = model(res, shape, b, beta)
+        assert all(sim[x] <= mod[x] for x in sim), (sim, mod)
+
+
+@pytest.mark.parametrize("res,b", CASES)
+def test_optimal_replacement_between_lower_bound_and_model(res, b):
+    shape = (12, 10, 9)
+    sim = cs.simulate(res, *shape, *b, 1.0)
+    mod = model(res, shape, b, 1.0)
+    assert all(sim[x] <= mod[x] for x in sim)
+    m, n, k = shape
+    M = b[0] * b[1] + b[0] + b[1]
+    reads = sim["a_reads"] + sim["b_reads"] + sim["c_reads"]
+    assert reads >= 2 * m * n * k / math.sqrt(M) - 2 * M
+
+
+def intensity(res, b1, b2, scale=200):
+    # flops per byte of the model at large sizes (the paper counts 8-byte
+    # elements; C read and written)
+    if res == "B":
+        m, n, k = 10 ** 7, b2 * scale, b1 * scale
+    elif res == "C":
+        m, n, k = b1 * scale, b2 * scale, 10 ** 7
+    else:
+        m, n, k = b1 * scale, 10 ** 7, b2 * scale
+    c = mm.model_resident(res, m, n, k, b1, b2, 1.0)
+    return 2.0 * m * n * k / (8.0 * sum(c.values()))
+
+
+def test_paper_intensities():
+    # Goto: the B panel k_c x n_c sits in L3 and the rest streams -> Resident B
+    assert intensity("B", 192, 3000) == pytest.approx(23.26, abs=0.01)
+    # B3A2C0: 768 x 768 block of B in L3
+    assert intensity("B", 768, 768) == pytest.approx(64.0, rel=2e-3)
+    # derived the same way: C3A2C0 (624 x 624 block of C) and C4A2C0 (3600)
+    assert intensity("C", 624, 624) == pytest.approx(78.0, rel=2e-3)
+    assert intensity("C", 3600, 3600) == pytest.approx(450.0, rel=2e-3)
+
+
+def test_balanced_blocks():
+    M = 120 * 192
+    mc, kc = mm.balanced_block(M, 1.0, 1.0)
+    assert mc == pytest.approx(math.sqrt(M)) and kc == pytest.approx(math.sqrt(M))
+    mc, kc = mm.balanced_block(M, 1.0, 2.0)   # C costs twice (read and written)
+    assert mc / kc == pytest.approx(0.5) and mc * kc == pytest.approx(M)
+
+
+def test_member_models_follow_resident_counts():
+    # The level-3 models of the gfx950 members are resident counts with the
+    # member's block sizes at the L2 boundary.
+    m = n = k = 8192
+    for name, res, b in [("B3C0", "B", (512, 128)), ("A3C0", "A", (128, 512)), ("C3C0", "C", (1024, 1024)),
+                         ("A2C0", "B", (128, 512))]:
+        got = mm.model_bytes(name, m, n, k, beta=1.0)
+        want = mm.model_resident(res, m, n, k, *b, 1.0)
+        assert got["a_reads"] == 8 * want["a_reads"], name
+        assert got["b_reads"] == 8 * want["b_reads"], name
+        assert got["c_reads"] == 8 * want["c_reads"] and got["c_writes"] == 8 * want["c_writes"], name
