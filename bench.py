@@ -1,13 +1,19 @@
 """Benchmark of the MOMMS FP64 GEMM family on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--member NAME] [--size N]
+                    [--only fp64|split|batch|backward|members]
 
 A step is one C := A B + C product in FP64 at m = n = k = 8192 (uniform
 [-1, 1] entries, beta = 1 with random C) by the selected family member
-(default: the autotuned pick), with inputs resident in HBM.  The JSON line
-reports whole-job TFLOP/s, the dominant kernel's roofline position against
-the FP64 MFMA peak, the model's byte prediction, and the CPU oracle timed on
-a bounded sample of the same product.
+(default: the member the library's selector picks), inputs resident in HBM.
+`value` is that product's TFLOP/s.  The same JSON line carries the dominant
+kernel's roofline position against the FP64 MFMA peak, the model's byte
+prediction next to the rocprofv3-measured traffic, the CPU oracle timed on a
+bounded sample, and the other forms of the method measured on their own
+workloads: the split-precision product (m = n = k = 8192, 16-decade data,
+speedup over the FP64 product and its error), 512 batched uneven problems,
+forward + hand-written backward at m = 4096, k = 8192, n = 2048, and every
+family member at 8192.
 """
 import argparse
 import json
@@ -19,7 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
-HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_f64_8192.json")
 
 
 def parse():
@@ -29,23 +36,31 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--member", default="AUTO")
     ap.add_argument("--size", type=int, default=8192)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--only", default="all", choices=["all", "fp64", "split", "batch", "backward", "members"])
+    ap.add_argument("--slices", type=int, default=7)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
-    ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_f64_8192.json"))
+    ap.add_argument("--profile", action="store_true", help="few steps, FP64 product only (for rocprofv3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (3 times): the reference for HBM byte counters")
     ap.add_argument("--profile-members", action="store_true",
                     help="run every family member once at --size, separated by marker fills (for rocprofv3)")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="turn the rocprofv3 CSV output of a profiling pass in DIR into profiles/ summaries")
     return ap.parse_args()
+
+
+def events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
 def copy_calibration():
     """A plain device-to-device copy of 2**27 doubles (1 GiB) three times.
 
     Under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE its dispatches must read
-    and write 1 GiB each; the ratio counter/known is the scale applied to the
-    GEMM kernels' counters.
+    and write 1 GiB each; the ratio known/counter is the scale applied to
+    the GEMM kernels' counters.
     """
     import torch
 
@@ -78,25 +93,23 @@ def profile_members(size):
         ws = torch.empty(wsb, dtype=torch.uint8, device="cuda:0") if wsb else None
         mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
         marker.fill_(1.0)
-        t0 = time.perf_counter()
         mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
         marker.fill_(2.0)
         torch.cuda.synchronize()
         order.append({"member": member, "launches": mm.member_plan(member, m, n, k)["launches"],
-                      "packed": ws is not None, "s": round(time.perf_counter() - t0, 4)})
+                      "packed": ws is not None})
         print(json.dumps({"profiled": order[-1]}), flush=True)
     print(json.dumps({"profile_members": order, "size": size}), flush=True)
 
 
 def cpu_baseline(m, n, k, target_s):
-    """Time the oracle on a bounded sample of the same product: full rows of C."""
+    """The oracle timed on a bounded sample of the same product: full rows of C."""
     import numpy as np
 
     import oracle
     import workloads
 
     A, B, C = workloads.gemm_operands(m, n, k)
-    # calibrate on one row, then size the sample to about target_s
     rows = np.zeros(n, dtype=np.int64)
     cols = np.arange(n, dtype=np.int64)
     t0 = time.perf_counter()
@@ -114,37 +127,20 @@ def cpu_baseline(m, n, k, target_s):
                                         f"{m}x{n}x{k} product, {dt:.1f} s"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.profile_members:
-        profile_members(args.size)
-        return
+def bench_fp64(args):
     import torch
 
     import paper_1904_05717_amd as mm
     import workloads
 
     m = n = k = args.size
-    member = args.member
-    if member == "AUTO":
-        member = mm.select_member(m, n, k)
+    member = args.member if args.member != "AUTO" else mm.select_member(m, n, k)
     plan = mm.member_plan(member, m, n, k)
-    dev = "cuda:0"
     A, B, C = workloads.gemm_operands(m, n, k)
-    Ad = torch.from_numpy(A).to(dev)
-    Bd = torch.from_numpy(B).to(dev)
-    Cd = torch.from_numpy(C).to(dev)
+    Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
     del A, B, C
-    ws = None
     wsb = mm.workspace_size(m, n, k, member)
-    if wsb:
-        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda:0") if wsb else None
     stream = torch.cuda.current_stream()
 
     def step():
@@ -155,58 +151,364 @@ def main():
     for _ in range(warm):
         step()
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    e0, e1 = events()
     t0 = time.perf_counter()
-    ev0.record(stream)
+    e0.record(stream)
     for _ in range(steps):
         step()
-    ev1.record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / steps
+    ms = e0.elapsed_time(e1) / steps
     flops = 2.0 * m * n * k
-    tflops = flops / (ms * 1e-3) / 1e12
-    # dominant kernel: the member's main kernel; one launch per step unless the
-    # plan splits k or the C region over several launches
-    compute_launches = plan["launches"] // (2 if plan["pack"] and ws is not None else 1)
-    launch_ms = ms / max(1, compute_launches)
-    achieved = (flops / max(1, compute_launches)) / (launch_ms * 1e-3) / 1e12
+    # The dominant kernel is the member's main kernel; a step is
+    # plan["launches"] back-to-back launches of it (plus packing launches for
+    # members that pack), so one launch takes ms / compute_launches.
+    compute_launches = max(1, plan["launches"] // (2 if plan["pack"] and ws is not None else 1))
+    launch_ms = ms / compute_launches
+    achieved = (flops / compute_launches) / (launch_ms * 1e-3) / 1e12
     model = mm.model_bytes(member, m, n, k, beta=1.0, packed=ws is not None)
     traffic = None
-    if os.path.exists(args.traffic_json):
+    measured = None
+    if os.path.exists(TRAFFIC_JSON):
         try:
-            tj = json.load(open(args.traffic_json))
-            if tj.get("member") == member and tj.get("size") == m:
-                traffic = tj.get("bytes_per_launch")
-        except (OSError, ValueError):
+            tj = json.load(open(TRAFFIC_JSON))
+            rec = tj.get("members", {}).get(member)
+            if rec and tj.get("size") == m and tj.get("kernel_source_sha") == kernel_source_sha():
+                traffic = rec["bytes_per_launch"]
+                measured = rec
+        except (OSError, ValueError, KeyError):
             traffic = None
-    out = {
-        "metric": "FP64 GEMM TFLOP/s + % MFMA peak; HBM bytes vs model; split-prec speedup",
-        "value": round(tflops, 3),
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
+    res = {
+        "value": round(flops / (ms * 1e-3) / 1e12, 3),
+        "ms_per_step": round(ms, 4),
         "steps": steps,
         "warmup": warm,
-        "ms_per_step": round(ms, 4),
+        "wall_s_timed": round(wall, 3),
+        "member": member,
+        "launches_per_step": compute_launches,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic},
+        "model_bytes": {"l2_read": model["l2_read"], "l2_write": model["l2_write"], "hbm_read": model["hbm_read"],
+                        "hbm_write": model["hbm_write"], "compulsory": model["compulsory"]},
+    }
+    if measured:
+        res["measured_vs_model"] = {"measured_bytes": measured["bytes_per_call"],
+                                    "model_bytes": model["l2_read"] + model["l2_write"],
+                                    "ratio": round(measured["bytes_per_call"] /
+                                                   (model["l2_read"] + model["l2_write"]), 3),
+                                    "source": os.path.relpath(TRAFFIC_JSON, ROOT)}
+    return res
+
+
+def kernel_source_sha():
+    """Hash of the FP64 kernel sources: stored traffic is only used while it matches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels_f64.hip", "gemm_f64.hip", "sched.h"):
+        with open(os.path.join(ROOT, "paper_1904_05717_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bench_split(args, fp64_ms=None):
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    m = n = k = args.size
+    S = args.slices
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform", with_c=False)
+    Ad, Bd = torch.from_numpy(A).to("cuda:0"), torch.from_numpy(B).to("cuda:0")
+    C = torch.empty((m, n), dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(mm.split_workspace_size(m, n, k, S), dtype=torch.uint8, device="cuda:0")
+    reps = 1 if args.profile else 3
+    mm.gemm_split(Ad, Bd, C, slices=S, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = events()
+    e0.record()
+    for _ in range(reps):
+        mm.gemm_split(Ad, Bd, C, slices=S, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    if fp64_ms is None:
+        mm.gemm(Ad, Bd, C, member=mm.select_member(m, n, k))
+        torch.cuda.synchronize()
+        f0, f1 = events()
+        f0.record()
+        for _ in range(reps):
+            mm.gemm(Ad, Bd, C, member=mm.select_member(m, n, k))
+        f1.record()
+        torch.cuda.synchronize()
+        fp64_ms = f0.elapsed_time(f1) / reps
+        mm.gemm_split(Ad, Bd, C, slices=S, workspace=ws)
+        torch.cuda.synchronize()
+    # error against the oracle on sampled entries, relative to (|A||B|)_ij
+    rng = np.random.Generator(np.random.PCG64(2024))
+    rows, cols = rng.integers(0, m, 256), rng.integers(0, n, 256)
+    got = C.cpu().numpy()[rows, cols]
+    exact = oracle.gemm_entries(A, B, rows, cols)
+    absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
+    rel = np.abs(got - exact) / absab
+    pairs = S * (S + 1) // 2
+    return {"slices": S, "slice_type": "bf16", "ms": round(ms, 3),
+            "fp64_equivalent_tflops": round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 3),
+            "bf16_slice_tflops": round(pairs * 2.0 * m * n * k / (ms * 1e-3) / 1e12, 1),
+            "bf16_frac_of_peak": round(pairs * 2.0 * m * n * k / (ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4),
+            "fp64_ms": round(fp64_ms, 3), "speedup_vs_fp64": round(fp64_ms / ms, 3),
+            "max_rel_err_vs_absAB_sampled": float(rel.max()), "median_rel_err_vs_absAB": float(np.median(rel)),
+            "sample": "256 entries", "data": "sign uniform, magnitude 10^U(-8,8)"}
+
+
+def bench_batch(args):
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    shapes = workloads.batch_shapes(512)
+    dev = []
+    for i, (m, n, k) in enumerate(shapes):
+        dev.append((torch.from_numpy(workloads.uniform((m, k), 3 * i)).to("cuda:0"),
+                    torch.from_numpy(workloads.uniform((k, n), 3 * i + 1)).to("cuda:0"),
+                    torch.from_numpy(workloads.uniform((m, n), 3 * i + 2)).to("cuda:0")))
+    plan = mm.BatchPlan([(A, B, C, 1.0, 1.0) for (A, B, C) in dev])
+    info = plan.info()
+    plan.run()
+    torch.cuda.synchronize()
+    reps = 2 if args.profile else 20
+    e0, e1 = events()
+    e0.record()
+    for _ in range(reps):
+        plan.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    plan.close()
+    return {"problems": 512, "ms_per_replay": round(ms, 3), "tflops": round(info["flops"] / (ms * 1e-3) / 1e12, 3),
+            "items": info["items"], "persistent_workgroups": info["workgroups"],
+            "tiles_128": sum(1 for t in info["tiles"] if t == 128), "graph": "hipGraph replay",
+            "shapes": "m, n, k each round(exp(U(ln 32, ln 2048)))"}
+
+
+def bench_backward(args):
+    import torch
+
+    import workloads
+    from paper_1904_05717_amd.autograd import matmul
+
+    m, k, n = 4096, 8192, 2048
+    out = {}
+    for dt in (torch.float64, torch.float32):
+        A = torch.from_numpy(workloads.uniform((m, k), workloads.SEED_A)).to("cuda:0", dt).requires_grad_()
+        B = torch.from_numpy(workloads.uniform((k, n), workloads.SEED_B)).to("cuda:0", dt).requires_grad_()
+        dC = torch.from_numpy(workloads.normal((m, n), workloads.SEED_DC)).to("cuda:0", dt)
+        C = matmul(A, B)
+        C.backward(dC)
+        torch.cuda.synchronize()
+        reps = 1 if args.profile else 3
+        f0, f1 = events()
+        b1 = torch.cuda.Event(enable_timing=True)
+        tot = [0.0, 0.0]
+        for _ in range(reps):
+            A.grad = None
+            B.grad = None
+            f0.record()
+            C = matmul(A, B)
+            f1.record()
+            C.backward(dC)
+            b1.record()
+            torch.cuda.synchronize()
+            tot[0] += f0.elapsed_time(f1)
+            tot[1] += f1.elapsed_time(b1)
+        fwd, bwd = tot[0] / reps, tot[1] / reps
+        flops = 2.0 * m * n * k
+        out["f64" if dt == torch.float64 else "f32_split3"] = {
+            "fwd_ms": round(fwd, 3), "bwd_ms": round(bwd, 3),
+            "tflops_fwd_bwd": round(3 * flops / ((fwd + bwd) * 1e-3) / 1e12, 3)}
+    out["shape"] = {"m": m, "k": k, "n": n}
+    return out
+
+
+def bench_members(args):
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    m = n = k = args.size
+    A, B, C = workloads.gemm_operands(m, n, k)
+    Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
+    del A, B, C
+    res = {}
+    for member in mm.FAMILY:
+        wsb = mm.workspace_size(m, n, k, member)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda:0") if wsb else None
+        mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record()
+        mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[member] = {"ms": round(ms, 3), "tflops": round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 2)}
+    return res
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def summarize(d, size=8192):
+    """Profiles from a pass with these rocprofv3 runs (all from /tmp, TMPDIR=/tmp):
+      kt_bench:      rocprofv3 --kernel-trace --stats -- python3 bench.py --profile
+      fetch_members: rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --profile-members
+      write_members: rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --profile-members
+      fetch_copy / write_copy: the same counters for bench.py --copy-calibration
+    Each member runs once after a warm-up, between two marker fills; the
+    dispatches between the first and second fill are its measured call.
+    """
+    import paper_1904_05717_amd as mm
+
+    def segments(rows):
+        segs, cur = [], []
+        for r in rows:
+            if "FillFunctor" in r["Kernel_Name"]:
+                segs.append(cur)
+                cur = []
+            else:
+                cur.append(r)
+        segs.append(cur)
+        return segs
+
+    def copy_scale(sub, counter):
+        rows = [r for r in _csv_rows(os.path.join(d, sub, "run_counter_collection.csv"))
+                if "copyBuffer" in r["Kernel_Name"] or "elementwise" in r["Kernel_Name"] and "copy" in
+                r["Kernel_Name"].lower()]
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in rows if r["Counter_Name"] == counter]
+        known = 8.0 * (1 << 27)
+        return known / (sum(vals) / len(vals)), vals
+
+    fscale, fvals = copy_scale("fetch_copy", "FETCH_SIZE")
+    wscale, wvals = copy_scale("write_copy", "WRITE_SIZE")
+    F = segments(_csv_rows(os.path.join(d, "fetch_members", "run_counter_collection.csv")))
+    W = segments(_csv_rows(os.path.join(d, "write_members", "run_counter_collection.csv")))
+    members = {}
+    for i, member in enumerate(mm.FAMILY):
+        fr = [r for r in F[2 * i + 1] if "momms" in r["Kernel_Name"]]
+        wr = [r for r in W[2 * i + 1] if "momms" in r["Kernel_Name"]]
+        fb = sum(float(r["Counter_Value"]) for r in fr) * 1024.0 * fscale
+        wb = sum(float(r["Counter_Value"]) for r in wr) * 1024.0 * wscale
+        plan = mm.member_plan(member, size, size, size)
+        launches = len([r for r in fr if "k_pack" not in r["Kernel_Name"]])
+        model = mm.model_bytes(member, size, size, size, beta=1.0, packed=plan["pack"] == 1)
+        mb = model["l2_read"] + model["l2_write"] + model["pack"]
+        members[member] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_call": fb + wb,
+                           "launches": launches, "bytes_per_launch": (fb + wb) / max(1, launches),
+                           "model_bytes": mb, "ratio": (fb + wb) / mb}
+    out = {"size": size, "kernel_source_sha": kernel_source_sha(), "fetch_scale": fscale, "write_scale": wscale,
+           "copy_fetch_bytes": fvals, "copy_write_bytes": wvals, "members": members}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    lines = [f"# L2-to-fabric traffic of every family member, FP64 m=n=k={size}", "",
+             "Commands (run from /tmp with TMPDIR=/tmp; repo at /root/repo):", "",
+             "    rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch_members -o run --output-format csv -- "
+             "python3 /root/repo/bench.py --profile-members --size 8192",
+             "    rocprofv3 --pmc WRITE_SIZE -d <dir>/write_members -o run --output-format csv -- "
+             "python3 /root/repo/bench.py --profile-members --size 8192",
+             "    rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch_copy -o run --output-format csv -- "
+             "python3 /root/repo/bench.py --copy-calibration",
+             "    rocprofv3 --pmc WRITE_SIZE -d <dir>/write_copy -o run --output-format csv -- "
+             "python3 /root/repo/bench.py --copy-calibration",
+             "    python3 bench.py --summarize <dir>", "",
+             f"Calibration on a plain 1 GiB device copy: FETCH_SIZE reads {1/fscale:.4f} of the bytes copied "
+             f"(scale {fscale:.4f}), WRITE_SIZE {1/wscale:.4f} (scale {wscale:.4f}).", "",
+             "| member | launches | fetch GB | write GB | measured GB | model GB | measured / model |",
+             "|---|---|---|---|---|---|---|"]
+    for member, r in members.items():
+        lines.append(f"| {member} | {r['launches']} | {r['fetch_bytes']/1e9:.2f} | {r['write_bytes']/1e9:.2f} | "
+                     f"{r['bytes_per_call']/1e9:.2f} | {r['model_bytes']/1e9:.2f} | {r['ratio']:.2f} |")
+    lines += ["", "Model: the library's momms_model_bytes (ideal residency at the boundary between the "
+              "per-XCD L2s and the fabric; packing included for members that pack).", ""]
+    with open(os.path.join(ROOT, "profiles", f"traffic_f64_{size}.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    ks = os.path.join(d, "kt_bench", "run_kernel_stats.csv")
+    if os.path.exists(ks):
+        import csv
+        with open(ks) as fh:
+            rows = list(csv.DictReader(fh))
+        lines = [f"# Kernel trace of the FP64 benchmark step (m=n=k={size}, selected member)", "",
+                 "    rocprofv3 --kernel-trace --stats -d <dir>/kt_bench -o run --output-format csv -- "
+                 "python3 /root/repo/bench.py --profile", "",
+                 "| kernel | calls | average ns | min ns | max ns | share |", "|---|---|---|---|---|---|"]
+        for r in rows:
+            name = r["Name"].split("(")[0][:90]
+            lines.append(f"| {name} | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['MinNs']} | {r['MaxNs']} | "
+                         f"{float(r['Percentage']):.1f} % |")
+        with open(os.path.join(ROOT, "profiles", f"kernel_stats_f64_{size}.md"), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"summarized": d, "members": {k: round(v["ratio"], 3) for k, v in members.items()}}))
+
+
+def main():
+    args = parse()
+    if args.summarize:
+        summarize(args.summarize)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.profile_members:
+        profile_members(args.size)
+        return
+    only = "fp64" if (args.profile and args.only == "all") else args.only
+    if only in ("split", "batch", "backward", "members"):
+        fn = {"split": bench_split, "batch": bench_batch, "backward": bench_backward, "members": bench_members}[only]
+        print(json.dumps({only: fn(args)}), flush=True)
+        return
+    f = bench_fp64(args)
+    out = {
+        "metric": "FP64 GEMM TFLOP/s + % MFMA peak; HBM bytes vs model; split-prec speedup",
+        "value": f["value"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": f["steps"],
+        "warmup": f["warmup"],
+        "ms_per_step": f["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"fp64 gemm C+=A*B m=n=k={m} row-major, U[-1,1], beta=1", "member": member,
-                   "m": m, "n": n, "k": k},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
-                     "traffic": traffic},
-        "frac_fp64_mfma_peak": round(tflops / FP64_MFMA_PEAK_TFLOPS, 4),
-        "model_bytes": {"l2_read": model["l2_read"], "l2_write": model["l2_write"],
-                        "hbm_read": model["hbm_read"], "hbm_write": model["hbm_write"],
-                        "compulsory": model["compulsory"]},
-        "wall_s_timed": round(wall, 3),
+        "config": {"workload": f"fp64 gemm C+=A*B m=n=k={args.size} row-major, U[-1,1] entries, beta=1",
+                   "member": f["member"], "m": args.size, "n": args.size, "k": args.size},
+        "roofline": f["roofline"],
+        "frac_fp64_mfma_peak": round(f["value"] / FP64_MFMA_PEAK_TFLOPS, 4),
+        "model_bytes": f["model_bytes"],
+        "wall_s_timed": f["wall_s_timed"],
     }
+    if "measured_vs_model" in f:
+        out["measured_vs_model"] = f["measured_vs_model"]
+    if only == "all":
+        out["split_precision"] = bench_split(args, fp64_ms=f["ms_per_step"])
+        out["batched"] = bench_batch(args)
+        out["backward"] = bench_backward(args)
+        out["members_8192"] = bench_members(args)
     if not args.no_cpu and not args.profile:
-        out["cpu_baseline"] = cpu_baseline(m, n, k, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.size, args.size, args.size, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
