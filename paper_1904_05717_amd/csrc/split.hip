@@ -164,69 +164,88 @@ __global__ __launch_bounds__(512) void k_split_diag(int64_t M, int64_t N, int64_
             for (int r = 0; r < 4; ++r) q[i][j][r] = 0.0;
         }
 
-    // staging: each thread moves 2 x 16 bytes of A and of B per k-slice;
-    // chunk c = tid + 512 i covers row c / 8, bytes 16 (c % 8) of the row.
-    uint4 ra0, ra1, rb0, rb1;
+    // Staging: each thread moves 2 x 16 bytes of A and of B per k-slice
+    // (chunk c = tid + 512 i covers row c / 8, bytes 16 (c % 8) of the row).
+    // Loads run kDepth k-slices ahead through a register FIFO: slice t lives
+    // in stage t % kDepth from its load until it is stored to LDS buffer t & 1.
+    constexpr int kDepth = 3;
+    uint4 st0_0, st0_1, st0_2, st0_3, st1_0, st1_1, st1_2, st1_3, st2_0, st2_1, st2_2, st2_3;
     const int nks = (int)(kp / kKS);
     const int total = (d + 1) * nks;
     const int row0 = tid >> 3, row1 = (tid + 512) >> 3, chb = (tid & 7) * 8;
-#define MOMMS_SPLIT_GLOAD(t_)                                                                       \
+    // Tiles sharing a slice panel start their k loops apart (as in the FP64
+    // kernel): slice t of pair s reads k-slice (t + kshift) mod nks.
+    const int kshift = ((tm + tn) & 7) % nks;
+
+#define MOMMS_SPLIT_GLOAD(t_, stage_)                                                             \
     do {                                                                                          \
         const int s_ = (t_) / nks;                                                                \
-        const int64_t kk_ = (int64_t)((t_) - s_ * nks) * kKS;                                     \
+        int kq_ = (t_) - s_ * nks + kshift;                                                       \
+        if (kq_ >= nks) kq_ -= nks;                                                               \
+        const int64_t kk_ = (int64_t)kq_ * kKS;                                                   \
         const uint16_t* pa_ = SA + (int64_t)s_ * sa_stride + m0 * kp + kk_ + chb;                 \
         const uint16_t* pb_ = SB + (int64_t)(d - s_) * sb_stride + n0 * kp + kk_ + chb;           \
-        ra0 = *reinterpret_cast<const uint4*>(pa_ + (int64_t)row0 * kp);                          \
-        ra1 = *reinterpret_cast<const uint4*>(pa_ + (int64_t)row1 * kp);                          \
-        rb0 = *reinterpret_cast<const uint4*>(pb_ + (int64_t)row0 * kp);                          \
-        rb1 = *reinterpret_cast<const uint4*>(pb_ + (int64_t)row1 * kp);                          \
+        st##stage_##_0 = *reinterpret_cast<const uint4*>(pa_ + (int64_t)row0 * kp);               \
+        st##stage_##_1 = *reinterpret_cast<const uint4*>(pa_ + (int64_t)row1 * kp);               \
+        st##stage_##_2 = *reinterpret_cast<const uint4*>(pb_ + (int64_t)row0 * kp);               \
+        st##stage_##_3 = *reinterpret_cast<const uint4*>(pb_ + (int64_t)row1 * kp);               \
     } while (0)
-#define MOMMS_SPLIT_LSTORE(buf_)                                                                  \
+#define MOMMS_SPLIT_LSTORE(buf_, stage_)                                                          \
     do {                                                                                          \
-        *reinterpret_cast<uint4*>(&As[buf_][row0 * kLdsPitch + chb]) = ra0;                       \
-        *reinterpret_cast<uint4*>(&As[buf_][row1 * kLdsPitch + chb]) = ra1;                       \
-        *reinterpret_cast<uint4*>(&Bs[buf_][row0 * kLdsPitch + chb]) = rb0;                       \
-        *reinterpret_cast<uint4*>(&Bs[buf_][row1 * kLdsPitch + chb]) = rb1;                       \
+        *reinterpret_cast<uint4*>(&As[buf_][row0 * kLdsPitch + chb]) = st##stage_##_0;            \
+        *reinterpret_cast<uint4*>(&As[buf_][row1 * kLdsPitch + chb]) = st##stage_##_1;            \
+        *reinterpret_cast<uint4*>(&Bs[buf_][row0 * kLdsPitch + chb]) = st##stage_##_2;            \
+        *reinterpret_cast<uint4*>(&Bs[buf_][row1 * kLdsPitch + chb]) = st##stage_##_3;            \
     } while (0)
 
-    MOMMS_SPLIT_GLOAD(0);
-    MOMMS_SPLIT_LSTORE(0);
-    __syncthreads();
-    for (int t = 0; t < total; ++t) {
-        const int cur = t & 1;
-        const bool more = t + 1 < total;
-        if (more) MOMMS_SPLIT_GLOAD(t + 1);
-#pragma unroll
-        for (int ks = 0; ks < kKS / 32; ++ks) {
-            bf16x8 a[4], b[2];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][(wm * 64 + i * 16 + li) * kLdsPitch + ks * 32 + 8 * lk]);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(wn * 32 + j * 16 + li) * kLdsPitch + ks * 32 + 8 * lk]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        if (more) MOMMS_SPLIT_LSTORE(cur ^ 1);
-        // 4 k-slices = 256 products per accumulator: fold the exact FP32
-        // integers into FP64 before they could reach 2^24.
-        if ((t & 3) == 3 || !more) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) q[i][j][r] += (double)acc[i][j][r];
-                    acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-                }
-        }
-        __syncthreads();
-    }
+    // One k-slice step: slice t is in LDS buffer t & 1 and stage (t % kDepth)
+    // is free again; refill it with slice t + kDepth, compute slice t, then
+    // move slice t + 1 from its stage into the other LDS buffer.
+#define MOMMS_SPLIT_STEP(t_, stage_, next_)                                                       \
+    do {                                                                                          \
+        const int tt_ = (t_);                                                                     \
+        if (tt_ + kDepth < total) MOMMS_SPLIT_GLOAD(tt_ + kDepth, stage_);                        \
+        const int cur_ = tt_ & 1;                                                                 \
+        _Pragma("unroll") for (int ks = 0; ks < kKS / 32; ++ks) {                                 \
+            bf16x8 a[4], b[2];                                                                    \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i)                                         \
+                a[i] = *reinterpret_cast<const bf16x8*>(                                          \
+                    &As[cur_][(wm * 64 + i * 16 + li) * kLdsPitch + ks * 32 + 8 * lk]);           \
+            _Pragma("unroll") for (int j = 0; j < 2; ++j)                                         \
+                b[j] = *reinterpret_cast<const bf16x8*>(                                          \
+                    &Bs[cur_][(wn * 32 + j * 16 + li) * kLdsPitch + ks * 32 + 8 * lk]);           \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i)                                         \
+                _Pragma("unroll") for (int j = 0; j < 2; ++j)                                     \
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0); \
+        }                                                                                         \
+        if (tt_ + 1 < total) MOMMS_SPLIT_LSTORE(cur_ ^ 1, next_);                                 \
+        /* 4 k-slices = 256 products per accumulator: fold the exact FP32    */                   \
+        /* integers into FP64 before they could reach 2^24.                  */                   \
+        if ((tt_ & 3) == 3 || tt_ + 1 == total) {                                                 \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i)                                         \
+                _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                   \
+                    _Pragma("unroll") for (int r = 0; r < 4; ++r) q[i][j][r] += (double)acc[i][j][r]; \
+                    acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};                                           \
+                }                                                                                 \
+        }                                                                                         \
+        __syncthreads();                                                                          \
+    } while (0)
 
+    // prologue: slice 0 into LDS buffer 0, slices 1 and 2 in flight; step t
+    // starts with stage t % kDepth free and loads slice t + kDepth into it.
+    MOMMS_SPLIT_GLOAD(0, 0);
+    MOMMS_SPLIT_LSTORE(0, 0);
+    if (1 < total) MOMMS_SPLIT_GLOAD(1, 1);
+    if (2 < total) MOMMS_SPLIT_GLOAD(2, 2);
+    __syncthreads();
+    // The loop runs in steps of kDepth so every stage index is a constant.
+    static_assert(kDepth == 3, "the step unrolling below assumes three stages");
+    for (int t = 0; t < total; t += kDepth) {
+        MOMMS_SPLIT_STEP(t, 0, 1);
+        if (t + 1 < total) MOMMS_SPLIT_STEP(t + 1, 1, 2);
+        if (t + 2 < total) MOMMS_SPLIT_STEP(t + 2, 2, 0);
+    }
+#undef MOMMS_SPLIT_STEP
 #undef MOMMS_SPLIT_GLOAD
 #undef MOMMS_SPLIT_LSTORE
     // s4: lane (li, lk) holds rows 4 lk + r, column li of each 16 x 16 block.
