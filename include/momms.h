@@ -167,9 +167,20 @@ int momms_member_plan(int member, int64_t m, int64_t n, int64_t k,
  * 5 beta, 6 packed (nonzero: count packing traffic), 7 out. */
 int momms_model_bytes(int member, int64_t m, int64_t n, int64_t k,
                       double beta, int packed, momms_bytes *out);
-/* Member MOMMS_AUTO resolves to for the shape (ties: fewer model bytes,
- * then lower id). */
+/* Member MOMMS_AUTO resolves to for the shape: the measured table entry of
+ * the shape's bucket (rounded log2 of m, n and k) if one is set, else the
+ * analytic prior: among the members that keep C in registers over all of k,
+ * the fewest model bytes, then the lower id.  Host-only. */
 int momms_select_member(int64_t m, int64_t n, int64_t k);
+/* The analytic prior alone.  Host-only. */
+int momms_select_member_prior(int64_t m, int64_t n, int64_t k);
+/* Installs the measured table (at most 64 entries; count 0 clears it):
+ * entry i maps the bucket (log2_m[i], log2_n[i], log2_k[i]) to member[i].
+ * The table is process-wide; calls racing with momms_gemm on other threads
+ * must be serialised by the caller.  Argument numbers: 1 count, 2 log2_m,
+ * 3 log2_n, 4 log2_k, 5 member.  Host-only. */
+int momms_set_member_table(int count, const int *log2_m, const int *log2_n, const int *log2_k,
+                           const int *member);
 
 const char *momms_status_string(int status);
 

@@ -14,6 +14,11 @@ MEMBER_NAMES = [_lib.momms_member_name(i).decode() for i in range(_lib.momms_num
 MEMBERS = {name: i for i, name in enumerate(MEMBER_NAMES)}
 FAMILY = [name for name in MEMBER_NAMES if name != "AUTO"]
 
+# the measured member table written by tuner.sweep on the device, if present
+from . import tuner as _tuner  # noqa: E402
+
+_tuner.install()
+
 
 class MommsError(RuntimeError):
     pass

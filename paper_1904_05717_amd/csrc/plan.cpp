@@ -53,17 +53,29 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             if (member == MOMMS_C3C0) {
                 // Level 3: the workgroups resident on one XCD at a time cover
                 // one C block of group_m x (per_xcd / group_m) tiles.  Level
-                // 4: one launch covers the C region all 8 XCDs hold at once
-                // (2 x 4 such blocks), so every launch starts its workgroups
-                // together and their k loops stay in step; the host loops
-                // over these regions.
+                // 4: one launch covers a C region of as many tiles as the
+                // chip holds at once (8 XCD blocks, at most 4 blocks wide),
+                // so every launch starts its workgroups together and their k
+                // loops stay in step; the host loops over these regions.
+                // When the whole problem fits one such region, or k is so
+                // short that a launch per region costs more than the
+                // lockstep saves, one launch covers everything.
                 const int per_xcd = (t >= 128) ? kWGsPerXcd128 : kWGsPerXcd64;
+                const int64_t conc = (int64_t)8 * per_xcd;
                 p->xcd_aware = 1;
-                p->group_m = 8;
+                p->group_m = (int)(tm < 8 ? tm : 8);
                 p->mc3 = (int64_t)8 * t;
                 p->nc3 = (int64_t)(per_xcd / 8) * t;
-                p->mc4 = 2 * p->mc3;
-                p->nc4 = 4 * p->nc3;
+                if (tm * tn <= conc || k < 2048) {
+                    p->mc4 = tm * t;
+                    p->nc4 = tn * t;
+                } else {
+                    int64_t rn = tn < 4 * (per_xcd / 8) ? tn : 4 * (per_xcd / 8);
+                    int64_t rm = conc / rn;
+                    if (rm > tm) rm = tm;
+                    p->mc4 = rm * t;
+                    p->nc4 = rn * t;
+                }
                 p->launches = cdiv(m, p->mc4) * cdiv(n, p->nc4);
             } else if (member == MOMMS_B3C0 || member == MOMMS_A3C0) {
                 p->xcd_aware = 1;
@@ -369,7 +381,37 @@ int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int pa
     return 0;
 }
 
+// Measured table: shape buckets (rounded log2 of m, n, k) whose best member
+// was measured on the device by the tuning sweep; consulted before the
+// analytic prior.
+struct TunedEntry {
+    int lm, ln, lk, member;
+};
+static TunedEntry g_tuned[64];
+static int g_ntuned = 0;
+
+static int log2_bucket(int64_t x) {
+    if (x <= 1) return 0;
+    return (int)std::lround(std::log2((double)x));
+}
+
+int set_tuned(int count, const int* lm, const int* ln, const int* lk, const int* member) {
+    if (count < 0 || count > 64) return -1;
+    for (int i = 0; i < count; ++i)
+        if (member[i] < 1 || member[i] >= MOMMS_NUM_MEMBERS) return -5;
+    for (int i = 0; i < count; ++i) g_tuned[i] = TunedEntry{lm[i], ln[i], lk[i], member[i]};
+    g_ntuned = count;
+    return 0;
+}
+
 int select_member(int64_t m, int64_t n, int64_t k) {
+    const int bm = log2_bucket(m), bn = log2_bucket(n), bk = log2_bucket(k);
+    for (int i = 0; i < g_ntuned; ++i)
+        if (g_tuned[i].lm == bm && g_tuned[i].ln == bn && g_tuned[i].lk == bk) return g_tuned[i].member;
+    return select_member_prior(m, n, k);
+}
+
+int select_member_prior(int64_t m, int64_t n, int64_t k) {
     // Analytic prior (Sec. 2.3: resident C needs k large, resident B needs m
     // large, resident A needs n large), then fewest model bytes, then lowest
     // id.  Only members that keep C in registers over all of k are
@@ -439,6 +481,20 @@ int momms_model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, 
     if (!out) return -7;
     if (member == MOMMS_AUTO) member = momms::select_member(m, n, k);
     return momms::model_bytes(member, m, n, k, beta, packed, out) == 0 ? 0 : MOMMS_ERR_INTERNAL;
+}
+
+int momms_set_member_table(int count, const int* log2_m, const int* log2_n, const int* log2_k, const int* member) {
+    if (count < 0 || count > 64) return -1;
+    if (count > 0 && !log2_m) return -2;
+    if (count > 0 && !log2_n) return -3;
+    if (count > 0 && !log2_k) return -4;
+    if (count > 0 && !member) return -5;
+    return momms::set_tuned(count, log2_m, log2_n, log2_k, member);
+}
+
+int momms_select_member_prior(int64_t m, int64_t n, int64_t k) {
+    if (m < 0 || n < 0 || k < 0) return -1;
+    return momms::select_member_prior(m, n, k);
 }
 
 size_t momms_workspace_size(int64_t m, int64_t n, int64_t k, int member) {

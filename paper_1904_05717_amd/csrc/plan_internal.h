@@ -18,6 +18,8 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p);
 size_t workspace_bytes(int member, int64_t m, int64_t n, int64_t k);
 int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int packed, momms_bytes* o);
 int select_member(int64_t m, int64_t n, int64_t k);
+int select_member_prior(int64_t m, int64_t n, int64_t k);
+int set_tuned(int count, const int* lm, const int* ln, const int* lk, const int* member);
 void resident_counts(int resident, int64_t m, int64_t n, int64_t k, int64_t b1, int64_t b2, double beta,
                      double* counts);
 const char* member_name(int member);

@@ -1,0 +1,128 @@
+"""Measured half of the member autotuner.
+
+`sweep` times every family member on the device for a list of shapes and
+returns, per shape bucket (rounded log2 of m, n, k), the fastest member.
+`save` writes that table as JSON; `install` loads a table into the library
+(momms_set_member_table), after which MOMMS_AUTO uses it before the analytic
+prior.  The package installs tuned_members.json (next to this file) at
+import when it exists.
+
+    python -c "from paper_1904_05717_amd import tuner; tuner.main()"   # on the GPU
+"""
+import ctypes
+import json
+import math
+import os
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_members.json")
+
+SWEEP_SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
+                (16384, 16384, 256), (16384, 256, 16384), (4096, 8192, 2048), (4096, 2048, 4096),
+                (8192, 2048, 4096)]
+
+
+def bucket(m, n, k):
+    return tuple(0 if x <= 1 else int(round(math.log2(x))) for x in (m, n, k))
+
+
+def time_member(mm, A, B, C, member, reps=3):
+    import torch
+    m, k = A.shape
+    n = B.shape[1]
+    wsb = mm.workspace_size(m, n, k, member)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=A.device) if wsb else None
+    mm.gemm(A, B, C, 1.0, 1.0, member=member, workspace=ws)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        mm.gemm(A, B, C, 1.0, 1.0, member=member, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+TIE = 0.01
+
+
+def pick(mm, m, n, k, times):
+    """Fastest member; members within 1% of it tie.  A tie goes to the
+    analytic prior's choice when it is among the tied members, else to fewer
+    model bytes, then the lower member id."""
+    fastest = min(times.values())
+    tied = [mem for mem, t in times.items() if t <= fastest * (1.0 + TIE)]
+    prior = mm.MEMBER_NAMES[mm._lib.momms_select_member_prior(m, n, k)]
+    if prior in tied:
+        return prior
+
+    def key(mem):
+        b = mm.model_bytes(mem, m, n, k, beta=1.0)
+        return (b["l2_read"] + b["l2_write"], mm.MEMBERS[mem])
+
+    return min(tied, key=key)
+
+
+def repick(path=TABLE):
+    """Recompute `best` of a saved table from its stored timings."""
+    import paper_1904_05717_amd as mm
+    with open(path) as fh:
+        entries = json.load(fh)["entries"]
+    for e in entries:
+        e["best"] = pick(mm, *e["shape"], e["ms"])
+    save(entries, path)
+    return entries
+
+
+def sweep(shapes=SWEEP_SHAPES, members=None):
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    members = members or mm.FAMILY
+    entries = []
+    for (m, n, k) in shapes:
+        A, B, C = workloads.gemm_operands(m, n, k)
+        Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
+        del A, B, C
+        times = {mem: time_member(mm, Ad, Bd, Cd, mem) for mem in members}
+        best = pick(mm, m, n, k, times)
+        entries.append({"shape": [m, n, k], "bucket": list(bucket(m, n, k)), "best": best,
+                        "ms": {k2: round(v, 4) for k2, v in times.items()},
+                        "prior": mm.MEMBER_NAMES[mm._lib.momms_select_member_prior(m, n, k)]})
+        print(json.dumps(entries[-1]), flush=True)
+        del Ad, Bd, Cd
+        torch.cuda.empty_cache()
+    return entries
+
+
+def save(entries, path=TABLE):
+    with open(path, "w") as fh:
+        json.dump({"entries": entries}, fh, indent=1)
+
+
+def install(path=TABLE):
+    """Load a saved table into the library; returns the number of entries."""
+    from . import MEMBERS, _lib
+    if not os.path.exists(path):
+        return 0
+    with open(path) as fh:
+        entries = json.load(fh)["entries"]
+    rows = [(e["bucket"], MEMBERS[e["best"]]) for e in entries]
+    n = len(rows)
+    arr = ctypes.c_int * max(n, 1)
+    st = _lib.momms_set_member_table(n, arr(*[r[0][0] for r in rows]), arr(*[r[0][1] for r in rows]),
+                                     arr(*[r[0][2] for r in rows]), arr(*[r[1] for r in rows]))
+    if st != 0:
+        raise RuntimeError(f"momms_set_member_table failed: {st}")
+    return n
+
+
+def main():
+    save(sweep())
+    print(json.dumps({"saved": TABLE}))
+
+
+if __name__ == "__main__":
+    main()

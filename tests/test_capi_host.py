@@ -94,3 +94,21 @@ def test_plans_are_consistent():
     assert mm.member_plan("AUTO", 8192, 8192, 8192)["member"] == mm.MEMBERS[mm.select_member(8192, 8192, 8192)]
     assert _lib.momms_member_plan(1, -1, 4, 4, mm.MommsPlan()) == -2
     assert _lib.momms_member_plan(1, 4, 4, 4, None) == -5
+
+
+def test_member_table_overrides_prior_and_validates():
+    import ctypes
+    from paper_1904_05717_amd import tuner
+    arr = ctypes.c_int * 1
+    lib = _lib
+    assert lib.momms_set_member_table(65, arr(0), arr(0), arr(0), arr(1)) == -1
+    assert lib.momms_set_member_table(1, arr(5), arr(5), arr(5), arr(0)) == -5     # AUTO is not a member
+    assert lib.momms_set_member_table(1, arr(5), arr(5), arr(5), arr(10)) == -5
+    try:
+        assert lib.momms_set_member_table(1, arr(5), arr(5), arr(5), arr(mm.MEMBERS["B3C0"])) == 0
+        assert mm.select_member(32, 32, 32) == "B3C0"        # bucket (5, 5, 5)
+        assert mm.select_member(64, 64, 64) == mm.MEMBER_NAMES[_lib.momms_select_member_prior(64, 64, 64)]
+    finally:
+        lib.momms_set_member_table(0, None, None, None, None)
+        tuner.install()
+    assert mm.select_member(8192, 8192, 8192) in mm.FAMILY

@@ -1,0 +1,21 @@
+"""The autotuned member (MOMMS_AUTO) against an exhaustive timing of the
+members that keep C in registers over all of k: within 5% of the fastest."""
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+mm = pytest.importorskip("paper_1904_05717_amd")
+from paper_1904_05717_amd import tuner  # noqa: E402
+
+
+@pytest.mark.parametrize("shape", [(2048, 2048, 2048), (4096, 4096, 4096), (16384, 256, 16384)])
+def test_auto_within_five_percent_of_best(shape):
+    m, n, k = shape
+    A, B, C = workloads.gemm_operands(m, n, k)
+    Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
+    times = {mem: min(tuner.time_member(mm, Ad, Bd, Cd, mem, reps=3) for _ in range(2))
+             for mem in ["C0", "C3C0", "B3C0", "A3C0"]}
+    auto = min(tuner.time_member(mm, Ad, Bd, Cd, "AUTO", reps=3) for _ in range(2))
+    assert auto <= 1.05 * min(times.values()), (mm.select_member(m, n, k), auto, times)
