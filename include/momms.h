@@ -212,15 +212,22 @@ int momms_balanced_block(double M, double beta_b, double beta_c, double *mc, dou
  * + (slices+2) u (|A||B|)_ij, where 2^e_i > max_p |op(A)_ip| and
  * 2^f_j > max_p |op(B)_pj|; 7 slices give FP64-level accuracy for data
  * spanning 16 decades.  Inputs must be finite.
+ * MOMMS_SLICE_INT8 uses 7-bit slices cut by truncation (|d| <= 127, exact
+ * in int8) multiplied on INT8 MFMA with INT32 accumulation, exact over a
+ * whole diagonal while slices * k (k rounded up to 128) <= 2^17; larger k
+ * returns MOMMS_ERR_INFEASIBLE.  Its error bound is the BF16 one with
+ * 2^-(7 slices) for 2^-(9 slices), so 9 INT8 slices match 7 BF16 ones.
+ * MOMMS_SLICE_FP8 is not built (-15).
  * Argument numbers: 1 transA, 2 transB, 3 m, 4 n, 5 k, 6 alpha, 7 A, 8 lda,
- * 9 B, 10 ldb, 11 beta, 12 C, 13 ldc, 14 slices (1..8), 15 slice_type
- * (MOMMS_SLICE_BF16), 16 family_member (MOMMS_AUTO, MOMMS_C0 or
+ * 9 B, 10 ldb, 11 beta, 12 C, 13 ldc, 14 slices (1..8 BF16, 1..10 INT8),
+ * 15 slice_type
+ * (MOMMS_SLICE_BF16 or MOMMS_SLICE_INT8), 16 family_member (MOMMS_AUTO, MOMMS_C0 or
  * MOMMS_C3C0: tile order of the slice products), 17 workspace (device,
  * 256-byte aligned), 18 ws_bytes (>= momms_split_workspace_size), 19 stream.
  * The workspace holds the exponents, the slices and the FP64 partial sums;
  * it must not be used concurrently by another call.
  */
-enum momms_slice_type { MOMMS_SLICE_BF16 = 0, MOMMS_SLICE_FP8 = 1 };
+enum momms_slice_type { MOMMS_SLICE_BF16 = 0, MOMMS_SLICE_FP8 = 1, MOMMS_SLICE_INT8 = 2 };
 
 size_t momms_split_workspace_size(int64_t m, int64_t n, int64_t k, int slices, int slice_type);
 

@@ -6,17 +6,21 @@ reading used by the GPU library:
 
   s1  exponent scan: e_i with max_p |A_ip| < 2**e_i (frexp exponent of the row
       maximum; 0 for a zero row), f_j likewise for the columns of B.
-  s2  error-free slicing with round-to-nearest: with a' = A_ip * 2**-e_i,
-      d_0 = rint(a' * 2**w_0), r_1 = a' - d_0 * 2**-w_0, d_s = rint(r_s * 2**w_s),
+  s2  error-free slicing: with a' = A_ip * 2**-e_i, d_0 = R(a' * 2**w_0),
+      r_1 = a' - d_0 * 2**-w_0, d_s = R(r_s * 2**w_s),
       r_{s+1} = r_s - d_s * 2**-w_s, where w_s = b0 + s*b.  Every d_s is an
-      integer with |d_0| <= 2**b0 and |d_s| <= 2**(b-1) for s >= 1, so it is
-      exact in the slice type: BF16 (b0 = 8, b = 9: integers up to 256) or
-      FP8 E4M3 (b0 = 4, b = 5: integers up to 16).
+      integer exact in the slice type:
+        BF16 (R = round to nearest, b0 = 8, b = 9): |d_0| <= 256 and
+          |d_s| <= 2**(b-1) = 256 (integers up to 256 are exact);
+        FP8 E4M3 (R = round to nearest, b0 = 4, b = 5): |d| <= 16;
+        INT8 (R = truncation toward zero, b0 = b = 7): |d| <= 127, because
+          each residual is below one unit of the previous slice.
   s3  slice products on the pairs s + t <= S - 1, grouped by diagonal
       d = s + t: Q_d = sum_s D^A_s D^B_{d-s}.  All terms are integers and every
       partial sum stays below 2**53, so Q_d is exact in any summation order
-      (on the GPU: exact FP32 sums of at most 2**24 over chunks, added
-      exactly in FP64).
+      (on the GPU: BF16 products in exact FP32 sums of at most 256 terms
+      added exactly in FP64; INT8 products in INT32, exact while
+      (d+1) k 127**2 < 2**31).
   s4  recombination, smallest diagonal first:
       V = sum_{d = S-1 .. 0} Q_d * 2**-(2 b0 + d b)  (FP64, in that order),
       T_ij = V_ij * 2**(e_i + f_j),  C = fl(fl(alpha T) + fl(beta C)).
@@ -28,7 +32,8 @@ error bound against the compensated FP64 oracle).
 """
 import numpy as np
 
-SLICE_BITS = {"bf16": (8, 9), "fp8": (4, 5)}
+SLICE_BITS = {"bf16": (8, 9), "fp8": (4, 5), "int8": (7, 7)}
+ROUNDING = {"bf16": np.rint, "fp8": np.rint, "int8": np.trunc}
 
 
 def exponents(X, axis):
@@ -45,12 +50,13 @@ def slices(X, e, S, kind, axis):
     (the B side).
     """
     b0, b = SLICE_BITS[kind]
+    rnd = ROUNDING[kind]
     ee = e[:, None] if axis == 1 else e[None, :]
     r = np.ldexp(X, -ee)
     out = []
     for s in range(S):
         w = b0 + s * b
-        d = np.rint(np.ldexp(r, w))
+        d = rnd(np.ldexp(r, w))
         out.append(d)
         r = r - np.ldexp(d, -w)
     return out

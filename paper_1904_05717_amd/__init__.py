@@ -117,7 +117,7 @@ def select_member(m, n, k):
     return MEMBER_NAMES[_lib.momms_select_member(m, n, k)]
 
 
-SLICE_TYPES = {"bf16": 0, "fp8": 1}
+SLICE_TYPES = {"bf16": 0, "fp8": 1, "int8": 2}
 
 
 def split_workspace_size(m, n, k, slices, slice_type="bf16"):
@@ -126,7 +126,7 @@ def split_workspace_size(m, n, k, slices, slice_type="bf16"):
 
 def gemm_split(A, B, C=None, alpha=1.0, beta=0.0, slices=7, slice_type="bf16", member="AUTO", transA=False,
                transB=False, workspace=None, stream=None):
-    """FP64-accurate C := alpha op(A) op(B) + beta C from BF16 slice products.
+    """FP64-accurate C := alpha op(A) op(B) + beta C from BF16 or INT8 slice products.
 
     Same conventions as gemm().  `workspace` (uint8 device tensor of at
     least split_workspace_size bytes) is allocated through torch when None.

@@ -33,6 +33,7 @@ namespace split {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
 
 constexpr int kB0 = 8;       // bits of the first BF16 slice
 constexpr int kB = 9;        // bits of every further slice
@@ -41,6 +42,15 @@ constexpr int kKS = 64;      // k-slice staged in LDS (bf16 elements)
 constexpr int kKPad = 64;    // k padded to a multiple of this
 constexpr int kLdsPitch = kKS + 8;  // 144-byte rows: conflict-free 16-byte fragment reads
 constexpr int kExpNone = INT_MIN;   // exponent of an all-zero row/column
+// INT8 slices: 7 bits each (truncation keeps |d| <= 127); workgroup tile
+// 256 x 128, k-slice 128 bytes.  Every INT32 sum of one diagonal is exact
+// while slices * kp * 127^2 < 2^31, i.e. slices * kp <= 2^17.
+constexpr int kI8Bits = 7;
+constexpr int kI8MT = 256, kI8NT = 128, kI8KS = 128, kI8Pitch = kI8KS + 16;
+constexpr int64_t kI8MaxProducts = (int64_t)1 << 17;
+// 8 BF16 slices carry 8 + 7 * 9 = 71 bits and 10 INT8 slices 70: beyond the
+// 53 of a double in both cases, so larger counts add nothing.
+constexpr int kMaxSlicesBf16 = 8, kMaxSlicesI8 = 10;
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
@@ -89,12 +99,13 @@ __global__ __launch_bounds__(256) void k_colmax_exp(const double* __restrict__ P
 
 // Slices of the logical R x Cc matrix X, X(r, c) = P[r*ld + c] (TRANSPOSED =
 // false) or P[c*ld + r] (true), scaled per row by 2^-e[r].  Writes
-// out[s][r][c] (pitch Cp, slice stride Rp*Cp) as BF16 bit patterns for all
-// r < Rp, c < Cp (zero outside X).  64 x 64 tiles go through LDS so that
-// global reads and writes are both contiguous.
-template <bool TRANSPOSED>
+// out[s][r][c] (pitch Cp, slice stride Rp*Cp) for all r < Rp, c < Cp (zero
+// outside X): BF16 bit patterns (INT8 = false: round to nearest, 8 + 9 s
+// bits) or int8 values (INT8 = true: truncation, 7 (s + 1) bits).  64 x 64
+// tiles go through LDS so that global reads and writes are both contiguous.
+template <bool TRANSPOSED, bool INT8>
 __global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int64_t ld, int64_t R, int64_t Cc,
-                                               const int* __restrict__ e, int S, uint16_t* __restrict__ out,
+                                               const int* __restrict__ e, int S, void* __restrict__ outv,
                                                int64_t Rp, int64_t Cp) {
     __shared__ double tile[64][65];
     const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
@@ -120,12 +131,19 @@ __global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int
         if (gr >= Rp || gc >= Cp) continue;
         const int ee = gr < R ? exp_or_zero(e[gr]) : 0;
         double rem = ldexp(tile[rr][cc], -ee);
-        uint16_t* o = out + gr * Cp + gc;
+        const int64_t o = gr * Cp + gc;
         for (int s = 0; s < S; ++s) {
-            const int w = kB0 + s * kB;
-            const double d = rint(ldexp(rem, w));
-            o[s * slice] = (uint16_t)(__float_as_uint((float)d) >> 16);  // exact: |d| <= 256
-            rem = rem - ldexp(d, -w);
+            if (INT8) {
+                const int w = kI8Bits * (s + 1);
+                const double d = trunc(ldexp(rem, w));                  // |d| <= 127
+                static_cast<int8_t*>(outv)[o + s * slice] = (int8_t)d;
+                rem = rem - ldexp(d, -w);
+            } else {
+                const int w = kB0 + s * kB;
+                const double d = rint(ldexp(rem, w));                   // |d| <= 256
+                static_cast<uint16_t*>(outv)[o + s * slice] = (uint16_t)(__float_as_uint((float)d) >> 16);
+                rem = rem - ldexp(d, -w);
+            }
         }
     }
 }
@@ -271,6 +289,113 @@ __global__ __launch_bounds__(512) void k_split_diag(int64_t M, int64_t N, int64_
             }
 }
 
+// INT8 form of one diagonal: Q = sum_{s=0..d} D^A_s D^B_{d-s} with
+// v_mfma_i32_16x16x64_i8 into INT32 accumulators (exact, no folding), then
+// the same recombination step as the BF16 kernel.  SA is [S][mp][kp] int8,
+// SB is [S][np][kp] int8 (B stored column by column), zero-padded.  8 waves
+// as 4 (m) x 2 (n), each owning a 64 x 64 sub-tile of the 256 x 128 tile.
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int64_t kp, int d,
+                                                       const int8_t* __restrict__ SA,
+                                                       const int8_t* __restrict__ SB, int64_t sa_stride,
+                                                       int64_t sb_stride, int shift, const int* __restrict__ ea,
+                                                       const int* __restrict__ eb, double* __restrict__ V,
+                                                       int64_t ldv, double alpha, double beta,
+                                                       double* __restrict__ C, int64_t ldc, Sched sc) {
+    __shared__ __attribute__((aligned(16))) int8_t As[2][kI8MT * kI8Pitch];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][kI8NT * kI8Pitch];
+    int tm, tn;
+    decode_tile(sc, blockIdx.x, tm, tn);
+    const int64_t m0 = sc.m_off + (int64_t)tm * kI8MT, n0 = sc.n_off + (int64_t)tn * kI8NT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 15, lk = lane >> 4;
+
+    i4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = i4{0, 0, 0, 0};
+
+    // staging: A moves 4 and B 2 chunks of 16 bytes per thread per k-slice;
+    // chunk c = tid + 512 i covers row c / 8, bytes 16 (c % 8) of the row.
+    const int nks = (int)(kp / kI8KS);
+    const int total = (d + 1) * nks;
+    const int kshift = ((tm + tn) & 7) % nks;
+    const int rA = tid >> 3, chb = (tid & 7) * 16;
+    uint4 a0, a1, a2, a3, b0, b1;
+    auto gload = [&](int t, uint4& x0, uint4& x1, uint4& x2, uint4& x3, uint4& y0, uint4& y1) {
+        const int s_ = t / nks;
+        int kq = t - s_ * nks + kshift;
+        if (kq >= nks) kq -= nks;
+        const int64_t kk = (int64_t)kq * kI8KS + chb;
+        const int8_t* pa = SA + (int64_t)s_ * sa_stride + m0 * kp + kk;
+        const int8_t* pb = SB + (int64_t)(d - s_) * sb_stride + n0 * kp + kk;
+        x0 = *reinterpret_cast<const uint4*>(pa + (int64_t)(rA) * kp);
+        x1 = *reinterpret_cast<const uint4*>(pa + (int64_t)(rA + 64) * kp);
+        x2 = *reinterpret_cast<const uint4*>(pa + (int64_t)(rA + 128) * kp);
+        x3 = *reinterpret_cast<const uint4*>(pa + (int64_t)(rA + 192) * kp);
+        y0 = *reinterpret_cast<const uint4*>(pb + (int64_t)(rA) * kp);
+        y1 = *reinterpret_cast<const uint4*>(pb + (int64_t)(rA + 64) * kp);
+    };
+    auto lstore = [&](int buf, const uint4& x0, const uint4& x1, const uint4& x2, const uint4& x3,
+                      const uint4& y0, const uint4& y1) {
+        *reinterpret_cast<uint4*>(&As[buf][(rA) * kI8Pitch + chb]) = x0;
+        *reinterpret_cast<uint4*>(&As[buf][(rA + 64) * kI8Pitch + chb]) = x1;
+        *reinterpret_cast<uint4*>(&As[buf][(rA + 128) * kI8Pitch + chb]) = x2;
+        *reinterpret_cast<uint4*>(&As[buf][(rA + 192) * kI8Pitch + chb]) = x3;
+        *reinterpret_cast<uint4*>(&Bs[buf][(rA) * kI8Pitch + chb]) = y0;
+        *reinterpret_cast<uint4*>(&Bs[buf][(rA + 64) * kI8Pitch + chb]) = y1;
+    };
+
+    gload(0, a0, a1, a2, a3, b0, b1);
+    lstore(0, a0, a1, a2, a3, b0, b1);
+    __syncthreads();
+    for (int t = 0; t < total; ++t) {
+        const int cur = t & 1;
+        const bool more = t + 1 < total;
+        if (more) gload(t + 1, a0, a1, a2, a3, b0, b1);
+#pragma unroll
+        for (int ks = 0; ks < kI8KS / 64; ++ks) {
+            i4 af[4], bf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                af[i] = *reinterpret_cast<const i4*>(&As[cur][(wm * 64 + i * 16 + li) * kI8Pitch + ks * 64 + 16 * lk]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bf[j] = *reinterpret_cast<const i4*>(&Bs[cur][(wn * 64 + j * 16 + li) * kI8Pitch + ks * 64 + 16 * lk]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) lstore(cur ^ 1, a0, a1, a2, a3, b0, b1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm * 64 + i * 16 + 4 * lk + r;
+                const int64_t col = n0 + wn * 64 + j * 16 + li;
+                if (row >= M || col >= N) continue;
+                const double term = ldexp((double)acc[i][j][r], -shift);
+                const double v = FIRST ? term : __dadd_rn(V[row * ldv + col], term);
+                if (LAST) {
+                    const double T = ldexp(v, exp_or_zero(ea[row]) + exp_or_zero(eb[col]));
+                    double o = __dmul_rn(alpha, T);
+                    if (beta != 0.0) o = __dadd_rn(o, __dmul_rn(beta, C[row * ldc + col]));
+                    C[row * ldc + col] = o;
+                } else {
+                    V[row * ldv + col] = v;
+                }
+            }
+}
+
 // C = beta * C (beta == 0 writes zeros).
 __global__ __launch_bounds__(256) void k_scale(int64_t M, int64_t N, double beta, double* __restrict__ C,
                                                int64_t ldc) {
@@ -289,19 +414,28 @@ struct Layout {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Layout layout(int64_t m, int64_t n, int64_t k, int S) {
+static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool int8) {
     Layout L;
-    L.mp = rup(m > 0 ? m : 1, kMT);
-    L.np = rup(n > 0 ? n : 1, kMT);
-    L.kp = rup(k > 0 ? k : 1, kKPad);
+    const size_t esz = int8 ? sizeof(int8_t) : sizeof(uint16_t);
+    L.mp = rup(m > 0 ? m : 1, int8 ? kI8MT : kMT);
+    L.np = rup(n > 0 ? n : 1, int8 ? kI8NT : kMT);
+    L.kp = rup(k > 0 ? k : 1, int8 ? kI8KS : kKPad);
     size_t o = 0;
     L.off_ea = o; o = align256(o + sizeof(int) * (size_t)m);
     L.off_eb = o; o = align256(o + sizeof(int) * (size_t)n);
-    L.off_sa = o; o = align256(o + sizeof(uint16_t) * (size_t)S * L.mp * L.kp);
-    L.off_sb = o; o = align256(o + sizeof(uint16_t) * (size_t)S * L.np * L.kp);
+    L.off_sa = o; o = align256(o + esz * (size_t)S * L.mp * L.kp);
+    L.off_sb = o; o = align256(o + esz * (size_t)S * L.np * L.kp);
     L.off_v = o;  o = align256(o + (S > 1 ? sizeof(double) * (size_t)m * n : 0));
     L.total = o;
     return L;
+}
+
+template <bool F, bool L>
+static void launch_i8_diag(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t kp, int d, const int8_t* SA,
+                           const int8_t* SB, int64_t sas, int64_t sbs, int shift, const int* ea, const int* eb,
+                           double* V, int64_t ldv, double alpha, double beta, double* C, int64_t ldc, Sched s) {
+    hipLaunchKernelGGL((k_split_i8_diag<F, L>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs, shift, ea,
+                       eb, V, ldv, alpha, beta, C, ldc, s);
 }
 
 template <bool F, bool L>
@@ -318,8 +452,12 @@ static void launch_diag(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t
 extern "C" {
 
 size_t momms_split_workspace_size(int64_t m, int64_t n, int64_t k, int slices, int slice_type) {
-    if (m < 0 || n < 0 || k < 0 || slices < 1 || slices > 8 || slice_type != MOMMS_SLICE_BF16) return 0;
-    return momms::split::layout(m, n, k, slices).total;
+    using namespace momms::split;
+    if (m < 0 || n < 0 || k < 0 || slices < 1) return 0;
+    if (slice_type == MOMMS_SLICE_BF16 ? slices > kMaxSlicesBf16
+                                       : slice_type != MOMMS_SLICE_INT8 || slices > kMaxSlicesI8)
+        return 0;
+    return layout(m, n, k, slices, slice_type == MOMMS_SLICE_INT8).total;
 }
 
 int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
@@ -339,11 +477,15 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     if (ldb < (tb ? (k > 1 ? k : 1) : (n > 1 ? n : 1))) return -10;
     if (m > 0 && n > 0 && C == nullptr) return -12;
     if (ldc < (n > 1 ? n : 1)) return -13;
-    if (slices < 1 || slices > 8) return -14;
-    if (slice_type != MOMMS_SLICE_BF16) return -15;
+    if (slices < 1 || slices > kMaxSlicesI8) return -14;
+    if (slice_type != MOMMS_SLICE_BF16 && slice_type != MOMMS_SLICE_INT8) return -15;
+    const bool int8 = slice_type == MOMMS_SLICE_INT8;
+    if (!int8 && slices > kMaxSlicesBf16) return -14;
     if (family_member != MOMMS_AUTO && family_member != MOMMS_C0 && family_member != MOMMS_C3C0) return -16;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return -17;
-    const Layout L = layout(m, n, k, slices);
+    const Layout L = layout(m, n, k, slices, int8);
+    // INT8: every diagonal's INT32 sum must stay exact (slices * kp <= 2^17).
+    if (int8 && reads_ab && (int64_t)slices * L.kp > kI8MaxProducts) return MOMMS_ERR_INFEASIBLE;
     if (reads_ab && (workspace == nullptr || ws_bytes < L.total)) return -18;
     if (cdiv(m, kMT) * cdiv(n, kMT) >= (int64_t)INT_MAX / 2) return MOMMS_ERR_INFEASIBLE;
 
@@ -360,8 +502,8 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     char* ws = static_cast<char*>(workspace);
     int* ea = reinterpret_cast<int*>(ws + L.off_ea);
     int* eb = reinterpret_cast<int*>(ws + L.off_eb);
-    uint16_t* SA = reinterpret_cast<uint16_t*>(ws + L.off_sa);
-    uint16_t* SB = reinterpret_cast<uint16_t*>(ws + L.off_sb);
+    void* SA = ws + L.off_sa;
+    void* SB = ws + L.off_sb;
     double* V = reinterpret_cast<double*>(ws + L.off_v);
 
     // s1: exponents of the rows of op(A) and the columns of op(B)
@@ -383,40 +525,69 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     // s2: slices.  A side X = op(A) (m x k); B side X = op(B)^T (n x k).
     {
         const dim3 ga((unsigned)cdiv(L.kp, 64), (unsigned)cdiv(L.mp, 64));
-        if (!ta) hipLaunchKernelGGL((k_slice<false>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
-        else     hipLaunchKernelGGL((k_slice<true>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
         const dim3 gb((unsigned)cdiv(L.kp, 64), (unsigned)cdiv(L.np, 64));
-        if (!tb) hipLaunchKernelGGL((k_slice<true>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
-        else     hipLaunchKernelGGL((k_slice<false>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
+        if (int8) {
+            if (!ta) hipLaunchKernelGGL((k_slice<false, true>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
+            else     hipLaunchKernelGGL((k_slice<true, true>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
+            if (!tb) hipLaunchKernelGGL((k_slice<true, true>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
+            else     hipLaunchKernelGGL((k_slice<false, true>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
+        } else {
+            if (!ta) hipLaunchKernelGGL((k_slice<false, false>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
+            else     hipLaunchKernelGGL((k_slice<true, false>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
+            if (!tb) hipLaunchKernelGGL((k_slice<true, false>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
+            else     hipLaunchKernelGGL((k_slice<false, false>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
+        }
     }
     // s3 + s4: one launch per diagonal, smallest first.
+    const int tile_m = int8 ? kI8MT : kMT, tile_n = int8 ? kI8NT : kMT;
     Sched s;
     s.m_off = 0;
     s.n_off = 0;
     s.m_lim = m;
     s.n_lim = n;
-    s.tiles_m = (int)cdiv(m, kMT);
-    s.tiles_n = (int)cdiv(n, kMT);
+    s.tiles_m = (int)cdiv(m, tile_m);
+    s.tiles_n = (int)cdiv(n, tile_n);
     const bool grouped = family_member != MOMMS_C0;
-    s.group_m = grouped ? (s.tiles_m < 8 ? s.tiles_m : 8) : 1;
+    const int gm = int8 ? 4 : 8;  // one XCD's 32 resident workgroups as a gm x (32/gm) tile block
+    s.group_m = grouped ? (s.tiles_m < gm ? s.tiles_m : gm) : 1;
     s.xcd = grouped ? kXcds : 1;
     const dim3 grid((unsigned)(s.tiles_m * s.tiles_n));
     const int64_t sas = L.mp * L.kp, sbs = L.np * L.kp;
     for (int d = slices - 1; d >= 0; --d) {
-        const int shift = 2 * kB0 + d * kB;
         const bool first = d == slices - 1, last = d == 0;
+        if (int8) {
+            const int shift = 2 * kI8Bits + d * kI8Bits;
+            const int8_t* a8 = static_cast<const int8_t*>(SA);
+            const int8_t* b8 = static_cast<const int8_t*>(SB);
+            if (first && last)
+                launch_i8_diag<true, true>(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha,
+                                           beta, C, ldc, s);
+            else if (first)
+                launch_i8_diag<true, false>(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha,
+                                            beta, C, ldc, s);
+            else if (last)
+                launch_i8_diag<false, true>(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha,
+                                            beta, C, ldc, s);
+            else
+                launch_i8_diag<false, false>(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha,
+                                             beta, C, ldc, s);
+            continue;
+        }
+        const int shift = 2 * kB0 + d * kB;
+        const uint16_t* a16 = static_cast<const uint16_t*>(SA);
+        const uint16_t* b16 = static_cast<const uint16_t*>(SB);
         if (first && last)
-            launch_diag<true, true>(grid, st, m, n, L.kp, d, SA, SB, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
+            launch_diag<true, true>(grid, st, m, n, L.kp, d, a16, b16, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
                                     ldc, s);
         else if (first)
-            launch_diag<true, false>(grid, st, m, n, L.kp, d, SA, SB, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
-                                     ldc, s);
+            launch_diag<true, false>(grid, st, m, n, L.kp, d, a16, b16, sas, sbs, shift, ea, eb, V, n, alpha, beta,
+                                     C, ldc, s);
         else if (last)
-            launch_diag<false, true>(grid, st, m, n, L.kp, d, SA, SB, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
-                                     ldc, s);
+            launch_diag<false, true>(grid, st, m, n, L.kp, d, a16, b16, sas, sbs, shift, ea, eb, V, n, alpha, beta,
+                                     C, ldc, s);
         else
-            launch_diag<false, false>(grid, st, m, n, L.kp, d, SA, SB, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
-                                      ldc, s);
+            launch_diag<false, false>(grid, st, m, n, L.kp, d, a16, b16, sas, sbs, shift, ea, eb, V, n, alpha, beta,
+                                      C, ldc, s);
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : (int)e;

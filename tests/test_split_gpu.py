@@ -18,9 +18,10 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
 
 
-def run(A, B, C, alpha, beta, S, member="AUTO", ta=False, tb=False):
+def run(A, B, C, alpha, beta, S, member="AUTO", ta=False, tb=False, kind="bf16"):
     Cd = dev(C.copy()) if C is not None else None
-    out = mm.gemm_split(dev(A), dev(B), Cd, alpha=alpha, beta=beta, slices=S, member=member, transA=ta, transB=tb)
+    out = mm.gemm_split(dev(A), dev(B), Cd, alpha=alpha, beta=beta, slices=S, member=member, transA=ta, transB=tb,
+                        slice_type=kind)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -106,6 +107,81 @@ def test_config3_sampled_8192():
     rows = np.concatenate([rng.integers(0, m, 300), [0, m - 1, 127, 128]])
     cols = np.concatenate([rng.integers(0, n, 300), [n - 1, 0, 128, 127]])
     emu = se.split_gemm_entries(A, B, rows, cols, 7, "bf16")
+    np.testing.assert_array_equal(got[rows, cols], emu)
+    exact = oracle.gemm_entries(A, B, rows, cols)
+    absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
+    assert np.max(np.abs(got[rows, cols] - exact) / absab) <= 1e-13
+
+
+# INT8 slices: 7-bit truncated slices on INT8 MFMA with INT32 accumulation.
+
+@pytest.mark.parametrize("S", [1, 2, 4, 7, 9, 10])
+@pytest.mark.parametrize("kind", ["uniform", "loguniform"])
+def test_int8_bit_exact_against_emulation(S, kind):
+    # 300 x 280 x 260: two 256-row and three 128-column tiles with ragged
+    # tails, k over three 128-deep slabs (ragged), so the staggered k start wraps.
+    m, n, k = 300, 280, 260
+    A, B, C = workloads.gemm_operands(m, n, k, kind=kind)
+    want = se.split_gemm(A, B, S, "int8", C, 1.0, 1.0)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, S, kind="int8"), want)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (129, 7, 65), (17, 200, 3), (520, 130, 1000), (256, 128, 128)])
+@pytest.mark.parametrize("member", ["AUTO", "C0"])
+def test_int8_ragged_shapes_bit_exact(shape, member):
+    m, n, k = shape
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = se.split_gemm(A, B, 7, "int8", C, -1.5, 0.25)
+    np.testing.assert_array_equal(run(A, B, C, -1.5, 0.25, 7, member, kind="int8"), want)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, True), (True, False), (True, True)])
+def test_int8_transposed_operands_bit_exact(ta, tb):
+    m, n, k = 200, 150, 170
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = se.split_gemm(A, B, 5, "int8", C, 1.0, 1.0)
+    got = run(A.T.copy() if ta else A, B.T.copy() if tb else B, C, 1.0, 1.0, 5, ta=ta, tb=tb, kind="int8")
+    np.testing.assert_array_equal(got, want)
+
+
+def test_int8_integers_exact_and_zero_lines():
+    m, n, k = 160, 144, 300
+    A, B, C = workloads.gemm_operands(m, n, k, kind="int")
+    want = (A.astype(np.int64) @ B.astype(np.int64) + C.astype(np.int64)).astype(np.float64)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, 1, kind="int8"), want)
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform")
+    A[5] = 0.0
+    B[:, 7] = 0.0
+    got = run(A, B, np.full((m, n), np.nan), 1.0, 0.0, 4, kind="int8")
+    np.testing.assert_array_equal(got, se.split_gemm(A, B, 4, "int8"))
+    assert (got[5] == 0).all() and (got[:, 7] == 0).all()
+
+
+def test_int8_error_against_fp64_oracle():
+    m, n, k = 192, 160, 512
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = oracle.gemm(A, B)
+    absab = np.abs(A) @ np.abs(B)
+    # 9 INT8 slices carry 63 bits, as many as 7 BF16 slices
+    assert np.max(np.abs(run(A, B, None, 1.0, 0.0, 9, kind="int8") - want) / absab) <= 1e-13
+    e = se.exponents(A, 1)
+    f = se.exponents(B, 0)
+    for S in (3, 6, 8, 10):
+        got = run(A, B, None, 1.0, 0.0, S, kind="int8")
+        tau = 2.0 ** -(7 * S)
+        bound = (S + 2) * 1.01 * tau * k * np.ldexp(1.0, e[:, None] + f[None, :]) + (S + 2) * 2.0 ** -53 * absab
+        assert np.all(np.abs(got - want) <= bound), S
+
+
+def test_int8_config3_sampled_8192():
+    # m = n = k = 8192, signed log-uniform over [1e-8, 1e8], nine INT8 slices.
+    m = n = k = 8192
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform", with_c=False)
+    got = run(A, B, None, 1.0, 0.0, 9, kind="int8")
+    rng = np.random.Generator(np.random.PCG64(4))
+    rows = np.concatenate([rng.integers(0, m, 300), [0, m - 1, 255, 256]])
+    cols = np.concatenate([rng.integers(0, n, 300), [n - 1, 0, 128, 127]])
+    emu = se.split_gemm_entries(A, B, rows, cols, 9, "int8")
     np.testing.assert_array_equal(got[rows, cols], emu)
     exact = oracle.gemm_entries(A, B, rows, cols)
     absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))

@@ -11,33 +11,41 @@ import workloads
 from oracle import split_emul as se
 
 
-@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "int8"])
 def test_slices_are_small_integers_exact_in_the_slice_type(kind):
     b0, b = se.SLICE_BITS[kind]
     X = workloads.signed_log_uniform((40, 70), 31)
     e = se.exponents(X, 1)
     D = se.slices(X, e, 6, kind, 1)
-    ttype = torch.bfloat16 if kind == "bf16" else torch.float8_e4m3fn
+    ttype = {"bf16": torch.bfloat16, "fp8": torch.float8_e4m3fn, "int8": torch.int8}[kind]
     for s, d in enumerate(D):
         assert np.array_equal(d, np.rint(d))
-        lim = 2 ** b0 if s == 0 else 2 ** (b - 1)
+        if kind == "int8":
+            lim = 127
+        else:
+            lim = 2 ** b0 if s == 0 else 2 ** (b - 1)
         assert np.abs(d).max() <= lim
         back = torch.from_numpy(d).to(ttype).to(torch.float64).numpy()
         np.testing.assert_array_equal(back, d)
 
 
-@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "int8"])
 @pytest.mark.parametrize("S", [1, 2, 4, 7])
 def test_slicing_residual_bound(kind, S):
     # After S round-to-nearest slices the residual is at most half a unit of
-    # the last slice's grid: |x - sum_s d_s 2^(e - w_s)| <= 2^(e - w_{S-1} - 1).
+    # the last slice's grid, |x - sum_s d_s 2^(e - w_s)| <= 2^(e - w_{S-1} - 1);
+    # after S truncated slices it is below one unit, < 2^(e - w_{S-1}).
     b0, b = se.SLICE_BITS[kind]
     X = workloads.signed_log_uniform((30, 50), 32)
     e = se.exponents(X, 1)
     D = se.slices(X, e, S, kind, 1)
     recon = sum(np.ldexp(D[s], e[:, None] - (b0 + s * b)) for s in range(S))
-    bound = np.ldexp(np.ones_like(X), e[:, None] - (b0 + (S - 1) * b) - 1)
-    assert np.all(np.abs(X - recon) <= bound)
+    if kind == "int8":
+        bound = np.ldexp(np.ones_like(X), e[:, None] - (b0 + (S - 1) * b))
+        assert np.all(np.abs(X - recon) < bound)
+    else:
+        bound = np.ldexp(np.ones_like(X), e[:, None] - (b0 + (S - 1) * b) - 1)
+        assert np.all(np.abs(X - recon) <= bound)
 
 
 def test_exponent_scan():
@@ -59,7 +67,7 @@ def test_full_slicing_reconstructs_doubles_exactly():
     np.testing.assert_array_equal(recon, X)
 
 
-@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "int8"])
 def test_small_integers_are_reproduced_exactly(kind):
     # Integers with |x| <= 8 fit in the first slice of either type, so the
     # split product is the exact integer product for every S >= 1.
@@ -87,14 +95,15 @@ def relative_to_absab(got, want, A, B):
 def split_error_bound(A, B, S, kind, k):
     """Per-entry bound on |split - exact| (derivation in the oracle module doc).
 
-    With tau = 2^-(w_{S-1} + 1) the slicing residual, every product term
-    2^(e_i + f_j) a'_ip b'_pj is reproduced up to the two residual terms
-    (<= tau each, |a'|, |b'| < 1), their product, and the dropped pairs
-    s + t >= S (both s, t >= 1: at most (S-1) tau (1 + 2^-b + ...));
-    the FP64 recombination adds at most (S + 2) u |result|.
+    With tau the slicing residual (2^-(w_{S-1} + 1) rounding to nearest,
+    2^-w_{S-1} truncating), every product term 2^(e_i + f_j) a'_ip b'_pj is
+    reproduced up to the two residual terms (<= tau each, |a'|, |b'| < 1),
+    their product, and the dropped pairs s + t >= S (both s, t >= 1: at most
+    (S-1) tau (1 + 2^-b + ...)); the FP64 recombination adds at most
+    (S + 2) u |result|.
     """
     b0, b = se.SLICE_BITS[kind]
-    tau = 2.0 ** -(b0 + (S - 1) * b + 1)
+    tau = 2.0 ** -(b0 + (S - 1) * b + (0 if kind == "int8" else 1))
     e = se.exponents(A, 1)
     f = se.exponents(B, 0)
     scale = np.ldexp(np.ones((A.shape[0], B.shape[1])), e[:, None] + f[None, :])
@@ -102,7 +111,7 @@ def split_error_bound(A, B, S, kind, k):
     return (S + 2) * 1.01 * tau * k * scale + (S + 2) * u * (np.abs(A) @ np.abs(B))
 
 
-@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "int8"])
 @pytest.mark.parametrize("S", [2, 4, 6, 7])
 def test_split_error_within_per_entry_bound(kind, S):
     m, n, k = 48, 40, 200
