@@ -46,7 +46,7 @@ constexpr int kExpNone = INT_MIN;   // exponent of an all-zero row/column
 // 256 x 128, k-slice 128 bytes.  Every INT32 sum of one diagonal is exact
 // while slices * kp * 127^2 < 2^31, i.e. slices * kp <= 2^17.
 constexpr int kI8Bits = 7;
-constexpr int kI8MT = 256, kI8NT = 128, kI8KS = 128, kI8Pitch = kI8KS + 16;
+constexpr int kI8MT = 256, kI8NT = 256, kI8KS = 128;
 constexpr int64_t kI8MaxProducts = (int64_t)1 << 17;
 // 8 BF16 slices carry 8 + 7 * 9 = 71 bits and 10 INT8 slices 70: beyond the
 // 53 of a double in both cases, so larger counts add nothing.
@@ -292,95 +292,133 @@ __global__ __launch_bounds__(512) void k_split_diag(int64_t M, int64_t N, int64_
 // INT8 form of one diagonal: Q = sum_{s=0..d} D^A_s D^B_{d-s} with
 // v_mfma_i32_16x16x64_i8 into INT32 accumulators (exact, no folding), then
 // the same recombination step as the BF16 kernel.  SA is [S][mp][kp] int8,
-// SB is [S][np][kp] int8 (B stored column by column), zero-padded.  8 waves
-// as 4 (m) x 2 (n), each owning a 64 x 64 sub-tile of the 256 x 128 tile.
+// SB is [S][np][kp] int8 (B stored column by column), zero-padded.  The
+// 256 x 256 workgroup tile is split over 8 waves as 2 (m) x 4 (n), each
+// owning 128 x 64: per 128-deep k-step a wave reads 24 KiB of fragments for
+// 64 MFMAs, which keeps the LDS (about 205 B/clk for conflict-free 16-byte
+// reads, 138 B/clk for writes) below the MFMA time.
+//
+// LDS holds each k-step as two 64-byte windows per row, unpadded; the
+// 16-byte chunk q of row r sits in slot q ^ ((r >> 1) & 3), which makes the
+// 16-row fragment reads (row li, chunk lk) free of bank conflicts on gfx950.
+// Two LDS stages; the next step's global loads are in flight in registers
+// during a whole step's MFMAs.
+namespace i8 {
+constexpr int kWinA = kI8MT * 64, kWinB = kI8NT * 64;     // bytes of one 64-deep window
+constexpr int kStageA = 2 * kWinA, kStageB = 2 * kWinB;   // one 128-deep k-step
+
+__device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^ ((r >> 1) & 3)); }
+}  // namespace i8
+
+#define MOMMS_I8_GLOAD(t_)                                                                      \
+    do {                                                                                         \
+        const int s_ = (t_) / nks;                                                               \
+        int kq = (t_) - s_ * nks + kshift;                                                       \
+        if (kq >= nks) kq -= nks;                                                                \
+        const int64_t kk = (int64_t)kq * kI8KS + gcol;                                           \
+        const int8_t* pa = SA + (int64_t)s_ * sa_stride + (m0 + grow) * kp + kk;                 \
+        const int8_t* pb = SB + (int64_t)(d - s_) * sb_stride + (n0 + grow) * kp + kk;           \
+        g0 = *reinterpret_cast<const uint4*>(pa);                                                \
+        g1 = *reinterpret_cast<const uint4*>(pa + 64 * kp);                                      \
+        g2 = *reinterpret_cast<const uint4*>(pa + 128 * kp);                                     \
+        g3 = *reinterpret_cast<const uint4*>(pa + 192 * kp);                                     \
+        g4 = *reinterpret_cast<const uint4*>(pb);                                                \
+        g5 = *reinterpret_cast<const uint4*>(pb + 64 * kp);                                      \
+        g6 = *reinterpret_cast<const uint4*>(pb + 128 * kp);                                     \
+        g7 = *reinterpret_cast<const uint4*>(pb + 192 * kp);                                     \
+    } while (0)
+
+#define MOMMS_I8_LSTORE(buf_)                                                                    \
+    do {                                                                                         \
+        int8_t* la = As + (buf_) * i8::kStageA + sw;                                             \
+        int8_t* lb = Bs + (buf_) * i8::kStageB + sw;                                             \
+        *reinterpret_cast<uint4*>(la) = g0;                                                      \
+        *reinterpret_cast<uint4*>(la + 64 * 64) = g1;                                            \
+        *reinterpret_cast<uint4*>(la + 128 * 64) = g2;                                           \
+        *reinterpret_cast<uint4*>(la + 192 * 64) = g3;                                           \
+        *reinterpret_cast<uint4*>(lb) = g4;                                                      \
+        *reinterpret_cast<uint4*>(lb + 64 * 64) = g5;                                            \
+        *reinterpret_cast<uint4*>(lb + 128 * 64) = g6;                                           \
+        *reinterpret_cast<uint4*>(lb + 192 * 64) = g7;                                           \
+    } while (0)
+
+// SA and SB are deliberately not __restrict__: as provably unclobbered loads
+// the compiler would sink the prefetch past the barrier to its use.
 template <bool FIRST, bool LAST>
 __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int64_t kp, int d,
-                                                       const int8_t* __restrict__ SA,
-                                                       const int8_t* __restrict__ SB, int64_t sa_stride,
+                                                       const int8_t* SA, const int8_t* SB, int64_t sa_stride,
                                                        int64_t sb_stride, int shift, const int* __restrict__ ea,
                                                        const int* __restrict__ eb, double* __restrict__ V,
                                                        int64_t ldv, double alpha, double beta,
                                                        double* __restrict__ C, int64_t ldc, Sched sc) {
-    __shared__ __attribute__((aligned(16))) int8_t As[2][kI8MT * kI8Pitch];
-    __shared__ __attribute__((aligned(16))) int8_t Bs[2][kI8NT * kI8Pitch];
+    __shared__ __attribute__((aligned(16))) int8_t As[2 * i8::kStageA];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2 * i8::kStageB];
     int tm, tn;
     decode_tile(sc, blockIdx.x, tm, tn);
     const int64_t m0 = sc.m_off + (int64_t)tm * kI8MT, n0 = sc.n_off + (int64_t)tn * kI8NT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave >> 2, wn = wave & 3;
     const int li = lane & 15, lk = lane >> 4;
 
-    i4 acc[4][4];
+    i4 acc[8][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = i4{0, 0, 0, 0};
 
-    // staging: A moves 4 and B 2 chunks of 16 bytes per thread per k-slice;
-    // chunk c = tid + 512 i covers row c / 8, bytes 16 (c % 8) of the row.
+    // staging: thread tid moves the 16-byte chunk gq of rows grow, grow + 64,
+    // grow + 128, grow + 192 of both operands (8 threads cover one row's 128
+    // bytes of a k-step); chunks 0-3 go to window 0, chunks 4-7 to window 1.
+    // Rows grow + 64 i share grow's swizzle; A and B windows have equal size.
+    const int grow = tid >> 3, gq = tid & 7, gcol = gq * 16;
+    const int sw = i8::lds_off(grow, gq & 3) + (gq >> 2) * i8::kWinA;
+    int fa_off[8], fb_off[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) fa_off[i] = i8::lds_off(wm * 128 + i * 16 + li, lk);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) fb_off[j] = i8::lds_off(wn * 64 + j * 16 + li, lk);
+
     const int nks = (int)(kp / kI8KS);
     const int total = (d + 1) * nks;
+    const int last = total - 1;
     const int kshift = ((tm + tn) & 7) % nks;
-    const int rA = tid >> 3, chb = (tid & 7) * 16;
-    uint4 a0, a1, a2, a3, b0, b1;
-    auto gload = [&](int t, uint4& x0, uint4& x1, uint4& x2, uint4& x3, uint4& y0, uint4& y1) {
-        const int s_ = t / nks;
-        int kq = t - s_ * nks + kshift;
-        if (kq >= nks) kq -= nks;
-        const int64_t kk = (int64_t)kq * kI8KS + chb;
-        const int8_t* pa = SA + (int64_t)s_ * sa_stride + m0 * kp + kk;
-        const int8_t* pb = SB + (int64_t)(d - s_) * sb_stride + n0 * kp + kk;
-        x0 = *reinterpret_cast<const uint4*>(pa + (int64_t)(rA) * kp);
-        x1 = *reinterpret_cast<const uint4*>(pa + (int64_t)(rA + 64) * kp);
-        x2 = *reinterpret_cast<const uint4*>(pa + (int64_t)(rA + 128) * kp);
-        x3 = *reinterpret_cast<const uint4*>(pa + (int64_t)(rA + 192) * kp);
-        y0 = *reinterpret_cast<const uint4*>(pb + (int64_t)(rA) * kp);
-        y1 = *reinterpret_cast<const uint4*>(pb + (int64_t)(rA + 64) * kp);
-    };
-    auto lstore = [&](int buf, const uint4& x0, const uint4& x1, const uint4& x2, const uint4& x3,
-                      const uint4& y0, const uint4& y1) {
-        *reinterpret_cast<uint4*>(&As[buf][(rA) * kI8Pitch + chb]) = x0;
-        *reinterpret_cast<uint4*>(&As[buf][(rA + 64) * kI8Pitch + chb]) = x1;
-        *reinterpret_cast<uint4*>(&As[buf][(rA + 128) * kI8Pitch + chb]) = x2;
-        *reinterpret_cast<uint4*>(&As[buf][(rA + 192) * kI8Pitch + chb]) = x3;
-        *reinterpret_cast<uint4*>(&Bs[buf][(rA) * kI8Pitch + chb]) = y0;
-        *reinterpret_cast<uint4*>(&Bs[buf][(rA + 64) * kI8Pitch + chb]) = y1;
-    };
+    uint4 g0, g1, g2, g3, g4, g5, g6, g7;
 
-    gload(0, a0, a1, a2, a3, b0, b1);
-    lstore(0, a0, a1, a2, a3, b0, b1);
+    MOMMS_I8_GLOAD(0);
+    MOMMS_I8_LSTORE(0);
     __syncthreads();
     for (int t = 0; t < total; ++t) {
         const int cur = t & 1;
-        const bool more = t + 1 < total;
-        if (more) gload(t + 1, a0, a1, a2, a3, b0, b1);
+        // Unconditional (past the end it re-reads the last step, in bounds):
+        // a conditional load would make every later wait a full one.
+        MOMMS_I8_GLOAD(t + 1 < last ? t + 1 : last);
+        __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the MFMAs
+        const int8_t* la = As + cur * i8::kStageA;
+        const int8_t* lb = Bs + cur * i8::kStageB;
 #pragma unroll
-        for (int ks = 0; ks < kI8KS / 64; ++ks) {
-            i4 af[4], bf[4];
+        for (int w = 0; w < 2; ++w) {
+            i4 af[8], bf[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                af[i] = *reinterpret_cast<const i4*>(&As[cur][(wm * 64 + i * 16 + li) * kI8Pitch + ks * 64 + 16 * lk]);
+            for (int i = 0; i < 8; ++i) af[i] = *reinterpret_cast<const i4*>(la + w * i8::kWinA + fa_off[i]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                bf[j] = *reinterpret_cast<const i4*>(&Bs[cur][(wn * 64 + j * 16 + li) * kI8Pitch + ks * 64 + 16 * lk]);
+            for (int j = 0; j < 4; ++j) bf[j] = *reinterpret_cast<const i4*>(lb + w * i8::kWinB + fb_off[j]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 8; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
-        if (more) lstore(cur ^ 1, a0, a1, a2, a3, b0, b1);
+        if (t + 1 < total) MOMMS_I8_LSTORE(cur ^ 1);
         __syncthreads();
     }
 
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = m0 + wm * 64 + i * 16 + 4 * lk + r;
+                const int64_t row = m0 + wm * 128 + i * 16 + 4 * lk + r;
                 const int64_t col = n0 + wn * 64 + j * 16 + li;
                 if (row >= M || col >= N) continue;
                 const double term = ldexp((double)acc[i][j][r], -shift);
@@ -395,6 +433,8 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
                 }
             }
 }
+#undef MOMMS_I8_GLOAD
+#undef MOMMS_I8_LSTORE
 
 // C = beta * C (beta == 0 writes zeros).
 __global__ __launch_bounds__(256) void k_scale(int64_t M, int64_t N, double beta, double* __restrict__ C,
@@ -548,7 +588,7 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     s.tiles_m = (int)cdiv(m, tile_m);
     s.tiles_n = (int)cdiv(n, tile_n);
     const bool grouped = family_member != MOMMS_C0;
-    const int gm = int8 ? 4 : 8;  // one XCD's 32 resident workgroups as a gm x (32/gm) tile block
+    const int gm = int8 ? 4 : 8;  // tiles per group along m in the grouped order
     s.group_m = grouped ? (s.tiles_m < gm ? s.tiles_m : gm) : 1;
     s.xcd = grouped ? kXcds : 1;
     const dim3 grid((unsigned)(s.tiles_m * s.tiles_n));
