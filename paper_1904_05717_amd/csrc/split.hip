@@ -93,7 +93,15 @@ __global__ __launch_bounds__(256) void k_colmax_exp(const double* __restrict__ P
     const int64_t r0 = (int64_t)blockIdx.y * chunk;
     const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
     double mx = 0.0;
-    for (int64_t r = r0; r < r1; ++r) mx = fmax(mx, fabs(P[r * ld + c]));
+    int64_t r = r0;
+    for (; r + 8 <= r1; r += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = P[(r + u) * ld + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mx = fmax(mx, fabs(v[u]));
+    }
+    for (; r < r1; ++r) mx = fmax(mx, fabs(P[r * ld + c]));
     if (mx != 0.0) atomicMax(out + c, exp_of(mx));
 }
 
@@ -122,28 +130,53 @@ __global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int
         tile[rr][cc] = v;
     }
     __syncthreads();
+    // Thread tid slices 16 consecutive columns of row tid / 4 and stores each
+    // slice's 16 values with 16-byte stores (Cp is a multiple of 64).
+    const int rr = tid >> 2, cb = (tid & 3) * 16;
+    const int64_t gr = r0 + rr;
+    if (gr >= Rp) return;
+    const int ee = gr < R ? exp_or_zero(e[gr]) : 0;
+    double rem[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) rem[j] = ldexp(tile[rr][cb + j], -ee);
     const int64_t slice = Rp * Cp;
-#pragma unroll 2
-    for (int i = 0; i < 16; ++i) {
-        const int idx = tid + 256 * i;
-        const int rr = idx >> 6, cc = idx & 63;
-        const int64_t gr = r0 + rr, gc = c0 + cc;
-        if (gr >= Rp || gc >= Cp) continue;
-        const int ee = gr < R ? exp_or_zero(e[gr]) : 0;
-        double rem = ldexp(tile[rr][cc], -ee);
-        const int64_t o = gr * Cp + gc;
-        for (int s = 0; s < S; ++s) {
-            if (INT8) {
-                const int w = kI8Bits * (s + 1);
-                const double d = trunc(ldexp(rem, w));                  // |d| <= 127
-                static_cast<int8_t*>(outv)[o + s * slice] = (int8_t)d;
-                rem = rem - ldexp(d, -w);
-            } else {
-                const int w = kB0 + s * kB;
-                const double d = rint(ldexp(rem, w));                   // |d| <= 256
-                static_cast<uint16_t*>(outv)[o + s * slice] = (uint16_t)(__float_as_uint((float)d) >> 16);
-                rem = rem - ldexp(d, -w);
+    const int64_t o = gr * Cp + c0 + cb;
+    for (int s_ = 0; s_ < S; ++s_) {
+        if (INT8) {
+            const int w = kI8Bits * (s_ + 1);
+            const double up = ldexp(1.0, w), down = ldexp(1.0, -w);
+            uint32_t word[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const double d = trunc(rem[4 * q + b] * up);            // |d| <= 127
+                    rem[4 * q + b] -= d * down;
+                    x |= (uint32_t)(uint8_t)(int8_t)d << (8 * b);
+                }
+                word[q] = x;
             }
+            *reinterpret_cast<uint4*>(static_cast<int8_t*>(outv) + o + s_ * slice) =
+                make_uint4(word[0], word[1], word[2], word[3]);
+        } else {
+            const int w = kB0 + s_ * kB;
+            const double up = ldexp(1.0, w), down = ldexp(1.0, -w);
+            uint32_t word[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double d = rint(rem[2 * q + b] * up);             // |d| <= 256
+                    rem[2 * q + b] -= d * down;
+                    x |= (__float_as_uint((float)d) >> 16) << (16 * b);
+                }
+                word[q] = x;
+            }
+            uint4* dst = reinterpret_cast<uint4*>(static_cast<uint16_t*>(outv) + o + s_ * slice);
+            dst[0] = make_uint4(word[0], word[1], word[2], word[3]);
+            dst[1] = make_uint4(word[4], word[5], word[6], word[7]);
         }
     }
 }
@@ -301,8 +334,9 @@ __global__ __launch_bounds__(512) void k_split_diag(int64_t M, int64_t N, int64_
 // LDS holds each k-step as two 64-byte windows per row, unpadded; the
 // 16-byte chunk q of row r sits in slot q ^ ((r >> 1) & 3), which makes the
 // 16-row fragment reads (row li, chunk lk) free of bank conflicts on gfx950.
-// Two LDS stages; the next step's global loads are in flight in registers
-// during a whole step's MFMAs.
+// Two LDS stages and one register set: a step's global loads are issued in
+// the middle of the step two before it and stored to LDS in the middle of
+// the step before it, so the stores overlap MFMAs.
 namespace i8 {
 constexpr int kWinA = kI8MT * 64, kWinB = kI8NT * 64;     // bytes of one 64-deep window
 constexpr int kStageA = 2 * kWinA, kStageB = 2 * kWinB;   // one 128-deep k-step
@@ -310,7 +344,7 @@ constexpr int kStageA = 2 * kWinA, kStageB = 2 * kWinB;   // one 128-deep k-step
 __device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^ ((r >> 1) & 3)); }
 }  // namespace i8
 
-#define MOMMS_I8_GLOAD(t_)                                                                      \
+#define MOMMS_I8_GLOAD(R, t_)                                                                   \
     do {                                                                                         \
         const int s_ = (t_) / nks;                                                               \
         int kq = (t_) - s_ * nks + kshift;                                                       \
@@ -318,28 +352,65 @@ __device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^
         const int64_t kk = (int64_t)kq * kI8KS + gcol;                                           \
         const int8_t* pa = SA + (int64_t)s_ * sa_stride + (m0 + grow) * kp + kk;                 \
         const int8_t* pb = SB + (int64_t)(d - s_) * sb_stride + (n0 + grow) * kp + kk;           \
-        g0 = *reinterpret_cast<const uint4*>(pa);                                                \
-        g1 = *reinterpret_cast<const uint4*>(pa + 64 * kp);                                      \
-        g2 = *reinterpret_cast<const uint4*>(pa + 128 * kp);                                     \
-        g3 = *reinterpret_cast<const uint4*>(pa + 192 * kp);                                     \
-        g4 = *reinterpret_cast<const uint4*>(pb);                                                \
-        g5 = *reinterpret_cast<const uint4*>(pb + 64 * kp);                                      \
-        g6 = *reinterpret_cast<const uint4*>(pb + 128 * kp);                                     \
-        g7 = *reinterpret_cast<const uint4*>(pb + 192 * kp);                                     \
+        R##0 = *reinterpret_cast<const uint4*>(pa);                                              \
+        R##1 = *reinterpret_cast<const uint4*>(pa + 64 * kp);                                    \
+        R##2 = *reinterpret_cast<const uint4*>(pa + 128 * kp);                                   \
+        R##3 = *reinterpret_cast<const uint4*>(pa + 192 * kp);                                   \
+        R##4 = *reinterpret_cast<const uint4*>(pb);                                              \
+        R##5 = *reinterpret_cast<const uint4*>(pb + 64 * kp);                                    \
+        R##6 = *reinterpret_cast<const uint4*>(pb + 128 * kp);                                   \
+        R##7 = *reinterpret_cast<const uint4*>(pb + 192 * kp);                                   \
     } while (0)
 
-#define MOMMS_I8_LSTORE(buf_)                                                                    \
+#define MOMMS_I8_LSTORE(buf_, R)                                                                 \
     do {                                                                                         \
         int8_t* la = As + (buf_) * i8::kStageA + sw;                                             \
         int8_t* lb = Bs + (buf_) * i8::kStageB + sw;                                             \
-        *reinterpret_cast<uint4*>(la) = g0;                                                      \
-        *reinterpret_cast<uint4*>(la + 64 * 64) = g1;                                            \
-        *reinterpret_cast<uint4*>(la + 128 * 64) = g2;                                           \
-        *reinterpret_cast<uint4*>(la + 192 * 64) = g3;                                           \
-        *reinterpret_cast<uint4*>(lb) = g4;                                                      \
-        *reinterpret_cast<uint4*>(lb + 64 * 64) = g5;                                            \
-        *reinterpret_cast<uint4*>(lb + 128 * 64) = g6;                                           \
-        *reinterpret_cast<uint4*>(lb + 192 * 64) = g7;                                           \
+        *reinterpret_cast<uint4*>(la) = R##0;                                                    \
+        *reinterpret_cast<uint4*>(la + 64 * 64) = R##1;                                          \
+        *reinterpret_cast<uint4*>(la + 128 * 64) = R##2;                                         \
+        *reinterpret_cast<uint4*>(la + 192 * 64) = R##3;                                         \
+        *reinterpret_cast<uint4*>(lb) = R##4;                                                    \
+        *reinterpret_cast<uint4*>(lb + 64 * 64) = R##5;                                          \
+        *reinterpret_cast<uint4*>(lb + 128 * 64) = R##6;                                         \
+        *reinterpret_cast<uint4*>(lb + 192 * 64) = R##7;                                         \
+    } while (0)
+
+// One 64-deep window of the current stage: 4 B fragments stay, the 8 A
+// fragments stream through in pairs (fewer live registers), 32 MFMAs.
+#define MOMMS_I8_WINDOW(buf_, w_)                                                                \
+    do {                                                                                         \
+        const int8_t* la = As + (buf_) * i8::kStageA + (w_) * i8::kWinA;                         \
+        const int8_t* lb = Bs + (buf_) * i8::kStageB + (w_) * i8::kWinB;                         \
+        i4 bf[4];                                                                                \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j)                                            \
+            bf[j] = *reinterpret_cast<const i4*>(lb + fb_off[j]);                                \
+        _Pragma("unroll") for (int i2 = 0; i2 < 8; i2 += 2) {                                    \
+            const i4 a0 = *reinterpret_cast<const i4*>(la + fa_off[i2]);                         \
+            const i4 a1 = *reinterpret_cast<const i4*>(la + fa_off[i2 + 1]);                     \
+            _Pragma("unroll") for (int j = 0; j < 4; ++j)                                        \
+                acc[i2][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, bf[j], acc[i2][j], 0, 0, 0); \
+            _Pragma("unroll") for (int j = 0; j < 4; ++j)                                        \
+                acc[i2 + 1][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, bf[j], acc[i2 + 1][j], 0, 0, 0); \
+            __builtin_amdgcn_sched_barrier(0);                                                   \
+        }                                                                                        \
+    } while (0)
+
+// One k-step t on LDS buffer buf_: run window 0, store step t + 1 (held in
+// the register set since the previous step) into the other buffer (last
+// read in step t - 1, before the previous barrier), issue the loads of step
+// t + 2 into the freed registers, run window 1, synchronise.  The stores
+// overlap window 1's MFMAs; each load has a whole step to land.
+#define MOMMS_I8_STEP(t_, buf_)                                                                  \
+    do {                                                                                         \
+        MOMMS_I8_WINDOW(buf_, 0);                                                                \
+        __builtin_amdgcn_sched_barrier(0);                                                       \
+        if ((t_) + 1 < total) MOMMS_I8_LSTORE((buf_) ^ 1, g);                                    \
+        __builtin_amdgcn_sched_barrier(0);                                                       \
+        MOMMS_I8_GLOAD(g, (t_) + 2 < last ? (t_) + 2 : last);                                    \
+        __builtin_amdgcn_sched_barrier(0);                                                       \
+        MOMMS_I8_WINDOW(buf_, 1);                                                                \
+        __syncthreads();                                                                         \
     } while (0)
 
 // SA and SB are deliberately not __restrict__: as provably unclobbered loads
@@ -384,33 +455,14 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
     const int kshift = ((tm + tn) & 7) % nks;
     uint4 g0, g1, g2, g3, g4, g5, g6, g7;
 
-    MOMMS_I8_GLOAD(0);
-    MOMMS_I8_LSTORE(0);
+    // Loads are unconditional (past the end they re-read the last step, in
+    // bounds): a conditional load would make every later wait a full one.
+    MOMMS_I8_GLOAD(g, 0);
+    MOMMS_I8_LSTORE(0, g);
+    MOMMS_I8_GLOAD(g, 1 < last ? 1 : last);
     __syncthreads();
-    for (int t = 0; t < total; ++t) {
-        const int cur = t & 1;
-        // Unconditional (past the end it re-reads the last step, in bounds):
-        // a conditional load would make every later wait a full one.
-        MOMMS_I8_GLOAD(t + 1 < last ? t + 1 : last);
-        __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the MFMAs
-        const int8_t* la = As + cur * i8::kStageA;
-        const int8_t* lb = Bs + cur * i8::kStageB;
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            i4 af[8], bf[4];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) af[i] = *reinterpret_cast<const i4*>(la + w * i8::kWinA + fa_off[i]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bf[j] = *reinterpret_cast<const i4*>(lb + w * i8::kWinB + fb_off[j]);
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[i][j], 0, 0, 0);
-        }
-        if (t + 1 < total) MOMMS_I8_LSTORE(cur ^ 1);
-        __syncthreads();
-    }
+    for (int t = 0; t < total; ++t) MOMMS_I8_STEP(t, t & 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the surplus prefetches
 
 #pragma unroll
     for (int i = 0; i < 8; ++i)
@@ -435,6 +487,8 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
 }
 #undef MOMMS_I8_GLOAD
 #undef MOMMS_I8_LSTORE
+#undef MOMMS_I8_WINDOW
+#undef MOMMS_I8_STEP
 
 // C = beta * C (beta == 0 writes zeros).
 __global__ __launch_bounds__(256) void k_scale(int64_t M, int64_t N, double beta, double* __restrict__ C,
@@ -549,16 +603,16 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     // s1: exponents of the rows of op(A) and the columns of op(B)
     hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, ea, m, kExpNone);
     hipLaunchKernelGGL(k_fill_int, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, eb, n, kExpNone);
-    const int64_t chunk = 1024;
+    const int64_t chunk = 1024, col_chunk = 128;   // column scans: more blocks, fewer rows each
     if (!ta)  // rows of A
         hipLaunchKernelGGL(k_rowmax_exp, dim3((unsigned)cdiv(m, 4), (unsigned)cdiv(k, chunk)), dim3(256), 0, st, A,
                            lda, m, k, chunk, ea);
     else      // A stored k x m: columns
-        hipLaunchKernelGGL(k_colmax_exp, dim3((unsigned)cdiv(m, 256), (unsigned)cdiv(k, chunk)), dim3(256), 0, st,
-                           A, lda, k, m, chunk, ea);
+        hipLaunchKernelGGL(k_colmax_exp, dim3((unsigned)cdiv(m, 256), (unsigned)cdiv(k, col_chunk)), dim3(256), 0,
+                           st, A, lda, k, m, col_chunk, ea);
     if (!tb)  // B stored k x n: columns
-        hipLaunchKernelGGL(k_colmax_exp, dim3((unsigned)cdiv(n, 256), (unsigned)cdiv(k, chunk)), dim3(256), 0, st,
-                           B, ldb, k, n, chunk, eb);
+        hipLaunchKernelGGL(k_colmax_exp, dim3((unsigned)cdiv(n, 256), (unsigned)cdiv(k, col_chunk)), dim3(256), 0,
+                           st, B, ldb, k, n, col_chunk, eb);
     else      // B stored n x k: rows
         hipLaunchKernelGGL(k_rowmax_exp, dim3((unsigned)cdiv(n, 4), (unsigned)cdiv(k, chunk)), dim3(256), 0, st, B,
                            ldb, n, k, chunk, eb);
