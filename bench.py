@@ -1,7 +1,7 @@
 """Benchmark of the MOMMS FP64 GEMM family on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--member NAME] [--size N]
-                    [--only fp64|split|batch|backward|members]
+                    [--only fp64|split|batch|backward|members|tiled]
 
 A step is one C := A B + C product in FP64 at m = n = k = 8192 (uniform
 [-1, 1] entries, beta = 1 with random C) by the selected family member
@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6
 LOWP_MFMA_PEAK_TOPS = {"bf16": 2500.0, "int8": 5000.0}   # dense, per the MI355X specification
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_f64_8192.json")
+TILED_MEMBERS = ["C0", "C3C0", "B3C0", "A3C0"]
 
 
 def parse():
@@ -36,7 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--member", default="AUTO")
     ap.add_argument("--size", type=int, default=8192)
-    ap.add_argument("--only", default="all", choices=["all", "fp64", "split", "batch", "backward", "members"])
+    ap.add_argument("--only", default="all",
+                    choices=["all", "fp64", "split", "batch", "backward", "members", "tiled"])
     ap.add_argument("--split", default="int8:8,int8:9,bf16:7",
                     help="split-precision configurations to time, as type:slices[,type:slices...]")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
@@ -99,6 +101,19 @@ def profile_members(size):
         torch.cuda.synchronize()
         order.append({"member": member, "launches": mm.member_plan(member, m, n, k)["launches"],
                       "packed": ws is not None})
+        print(json.dumps({"profiled": order[-1]}), flush=True)
+    # the register-resident members again on tile-major ("prepacked") operands
+    At, Bt = mm.to_tiled(Ad, "A"), mm.to_tiled(Bd, "B")
+    torch.cuda.synchronize()
+    marker.fill_(3.0)
+    for member in TILED_MEMBERS:
+        mm.gemm_tiled(At, Bt, m, n, k, Cd, 1.0, 1.0, member=member)
+        marker.fill_(1.0)
+        mm.gemm_tiled(At, Bt, m, n, k, Cd, 1.0, 1.0, member=member)
+        marker.fill_(2.0)
+        torch.cuda.synchronize()
+        order.append({"member": member + "/tiled", "launches": mm.member_plan(member, m, n, k)["launches"],
+                      "packed": False})
         print(json.dumps({"profiled": order[-1]}), flush=True)
     print(json.dumps({"profile_members": order, "size": size}), flush=True)
 
@@ -203,10 +218,10 @@ def bench_fp64(args):
 
 
 def kernel_source_sha():
-    """Hash of the FP64 kernel sources: stored traffic is only used while it matches."""
+    """Hash of the FP64 kernel sources (row-major and tiled): stored traffic is only used while it matches."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels_f64.hip", "gemm_f64.hip", "sched.h"):
+    for f in ("kernels_f64.hip", "gemm_f64.hip", "sched.h", "tiled.hip"):
         with open(os.path.join(ROOT, "paper_1904_05717_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -271,6 +286,42 @@ def bench_split(args, fp64_ms=None):
             "fastest_within_1e-13": None if best is None else {key: best[key] for key in (
                 "slice_type", "slices", "ms", "speedup_vs_fp64", "max_rel_err_vs_absAB")},
             "error_sample": "256 entries against the compensated FP64 oracle"}
+
+
+def bench_tiled(args):
+    """The register-resident members on tile-major ("prepacked") operands
+    against the same members on row-major operands (bit-identical results),
+    and the one-time conversion cost."""
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    m = n = k = args.size
+    A, B, C = workloads.gemm_operands(m, n, k)
+    Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
+    reps = 1 if args.profile else 5
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    At, Bt = mm.to_tiled(Ad, "A"), mm.to_tiled(Bd, "B")
+    conv = timed(lambda: (mm.to_tiled(Ad, "A", out=At), mm.to_tiled(Bd, "B", out=Bt)))
+    out = {"conversion_ms": round(conv, 3), "members": {}}
+    for member in TILED_MEMBERS:
+        row = timed(lambda: mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member))
+        til = timed(lambda: mm.gemm_tiled(At, Bt, m, n, k, Cd, 1.0, 1.0, member=member))
+        out["members"][member] = {"row_major_tflops": round(2.0 * m * n * k / row / 1e9, 2),
+                                  "tiled_tflops": round(2.0 * m * n * k / til / 1e9, 2)}
+    return out
 
 
 def bench_batch(args):
@@ -424,6 +475,20 @@ def summarize(d, size=8192):
         members[member] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_call": fb + wb,
                            "launches": launches, "bytes_per_launch": (fb + wb) / max(1, launches),
                            "model_bytes": mb, "ratio": (fb + wb) / mb}
+    # tiled runs follow after one more marker fill: segments 2 * len(FAMILY) + 1 + 2 i + 1
+    base = 2 * len(mm.FAMILY) + 1
+    for i, member in enumerate(TILED_MEMBERS):
+        if base + 2 * i + 1 >= min(len(F), len(W)):
+            break
+        fr = [r for r in F[base + 2 * i + 1] if "momms" in r["Kernel_Name"]]
+        wr = [r for r in W[base + 2 * i + 1] if "momms" in r["Kernel_Name"]]
+        fb = sum(float(r["Counter_Value"]) for r in fr) * 1024.0 * fscale
+        wb = sum(float(r["Counter_Value"]) for r in wr) * 1024.0 * wscale
+        model = mm.model_bytes(member, size, size, size, beta=1.0, packed=False)
+        mb = model["l2_read"] + model["l2_write"]
+        members[member + "/tiled"] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_call": fb + wb,
+                                      "launches": len(fr), "bytes_per_launch": (fb + wb) / max(1, len(fr)),
+                                      "model_bytes": mb, "ratio": (fb + wb) / mb}
     out = {"size": size, "kernel_source_sha": kernel_source_sha(), "fetch_scale": fscale, "write_scale": wscale,
            "copy_fetch_bytes": fvals, "copy_write_bytes": wvals, "members": members}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
@@ -448,7 +513,9 @@ def summarize(d, size=8192):
         lines.append(f"| {member} | {r['launches']} | {r['fetch_bytes']/1e9:.2f} | {r['write_bytes']/1e9:.2f} | "
                      f"{r['bytes_per_call']/1e9:.2f} | {r['model_bytes']/1e9:.2f} | {r['ratio']:.2f} |")
     lines += ["", "Model: the library's momms_model_bytes (ideal residency at the boundary between the "
-              "per-XCD L2s and the fabric; packing included for members that pack).", ""]
+              "per-XCD L2s and the fabric; packing included for members that pack).  `/tiled` rows run the "
+              "member on tile-major (\"prepacked\") operands (momms_gemm_tiled); the conversion is outside the "
+              "measured call.", ""]
     with open(os.path.join(ROOT, "profiles", f"traffic_f64_{size}.md"), "w") as fh:
         fh.write("\n".join(lines))
     ks = os.path.join(d, "kt_bench", "run_kernel_stats.csv")
@@ -484,8 +551,9 @@ def main():
         profile_members(args.size)
         return
     only = "fp64" if (args.profile and args.only == "all") else args.only
-    if only in ("split", "batch", "backward", "members"):
-        fn = {"split": bench_split, "batch": bench_batch, "backward": bench_backward, "members": bench_members}[only]
+    if only in ("split", "batch", "backward", "members", "tiled"):
+        fn = {"split": bench_split, "batch": bench_batch, "backward": bench_backward, "members": bench_members,
+              "tiled": bench_tiled}[only]
         print(json.dumps({only: fn(args)}), flush=True)
         return
     f = bench_fp64(args)
@@ -516,6 +584,7 @@ def main():
         out["batched"] = bench_batch(args)
         out["backward"] = bench_backward(args)
         out["members_8192"] = bench_members(args)
+        out["tiled_storage"] = bench_tiled(args)
     if not args.no_cpu and not args.profile:
         out["cpu_baseline"] = cpu_baseline(args.size, args.size, args.size, args.cpu_seconds)
     print(json.dumps(out), flush=True)

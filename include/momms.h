@@ -272,6 +272,36 @@ int momms_batch_destroy(momms_batch *plan);
 /* The analytic prior's register tile (64 or 128) for one problem. */
 int momms_batch_select_tile(int64_t m, int64_t n, int64_t k);
 
+/* ---------------------------------------------------------------------
+ * Tile-major ("prepacked") storage (Sec. 5.2: matrices stored so that every
+ * block the algorithm partitions them into is contiguous, which removes
+ * packing and isolates temporal from spatial locality).
+ *   op(A), m x k:  [m-tile of 128 rows][k-slab of 16][128][16]
+ *   op(B), k x n:  [n-tile of 128 columns][k][128]
+ * doubles, zero beyond the matrix (k padded to a multiple of 16, m and n to
+ * multiples of 128).  `operand` is 'A' or 'B'; rows x cols is the logical
+ * m x k (A) or k x n (B).  Buffers are device memory owned by the caller.
+ */
+/* Bytes of a tiled operand; 0 for an invalid operand or negative sizes. */
+size_t momms_tiled_size(int operand, int64_t rows, int64_t cols);
+/* T := tiled op(X), op(X) = X (trans = 0, X rows x cols with pitch ldx) or
+ * X^T (trans = 1, X stored cols x rows).  Asynchronous on `stream`.
+ * Argument numbers: 1 operand, 2 trans, 3 rows, 4 cols, 5 X, 6 ldx, 7 T. */
+int momms_to_tiled(int operand, int trans, int64_t rows, int64_t cols, const double *X, int64_t ldx,
+                   double *T, momms_stream_t stream);
+/* X := the rows x cols matrix held in tiled T (row-major, pitch ldx).
+ * Argument numbers: 1 operand, 2 rows, 3 cols, 4 T, 5 X, 6 ldx. */
+int momms_from_tiled(int operand, int64_t rows, int64_t cols, const double *T, double *X, int64_t ldx,
+                     momms_stream_t stream);
+/* C := alpha At Bt + beta C on tiled operands, C row-major (pitch ldc).
+ * family_member: MOMMS_AUTO, MOMMS_C0, MOMMS_C3C0, MOMMS_B3C0 or MOMMS_A3C0
+ * (the members that keep the C tile in registers; their loop nests and k
+ * stagger are those of momms_gemm_ex, so the result equals that call's
+ * bit for bit).  beta = 0 does not read C.  Argument numbers: 1 m, 2 n, 3 k,
+ * 4 alpha, 5 At, 6 Bt, 7 beta, 8 C, 9 ldc, 10 family_member, 11 stream. */
+int momms_gemm_tiled(int64_t m, int64_t n, int64_t k, double alpha, const double *At, const double *Bt,
+                     double beta, double *C, int64_t ldc, int family_member, momms_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -219,6 +219,56 @@ def batch_select_tile(m, n, k):
     return int(_lib.momms_batch_select_tile(m, n, k))
 
 
+def tiled_size(operand, rows, cols):
+    """Bytes of a tile-major operand ('A': rows x cols = m x k, 'B': k x n)."""
+    return int(_lib.momms_tiled_size(ord(operand), rows, cols))
+
+
+def to_tiled(X, operand, trans=False, out=None, stream=None):
+    """Tile-major copy of op(X) (float64 device tensor; op(X) = X.T if trans).
+
+    Returns a flat float64 device tensor holding the layout of
+    momms_to_tiled (A: [m/128][k/16][128][16], B: [n/128][k][128], zero-padded).
+    """
+    if operand not in ("A", "B"):
+        raise ValueError("operand must be 'A' or 'B'")
+    ld = _ld(X, "X")
+    rows, cols = (X.shape[1], X.shape[0]) if trans else (X.shape[0], X.shape[1])
+    need = tiled_size(operand, rows, cols) // 8
+    if out is None:
+        out = torch.empty(need, dtype=torch.float64, device=X.device)
+    elif out.numel() < need or out.dtype != torch.float64 or not out.is_cuda:
+        raise ValueError(f"out must be a float64 device tensor of at least {need} elements")
+    check_status(_lib.momms_to_tiled(ord(operand), int(bool(trans)), rows, cols, X.data_ptr(), ld, out.data_ptr(),
+                                     _stream_handle(stream)), "momms_to_tiled")
+    return out
+
+
+def from_tiled(T, operand, rows, cols, stream=None):
+    """The rows x cols row-major matrix held in a tile-major buffer."""
+    X = torch.empty((rows, cols), dtype=torch.float64, device=T.device)
+    check_status(_lib.momms_from_tiled(ord(operand), rows, cols, T.data_ptr(), X.data_ptr(), max(1, cols),
+                                       _stream_handle(stream)), "momms_from_tiled")
+    return X
+
+
+def gemm_tiled(At, Bt, m, n, k, C=None, alpha=1.0, beta=0.0, member="AUTO", stream=None):
+    """C := alpha * A @ B + beta * C with A, B in tile-major storage (to_tiled)."""
+    for T, op, rows, cols in ((At, "A", m, k), (Bt, "B", k, n)):
+        if not T.is_cuda or T.dtype != torch.float64 or T.numel() * 8 < tiled_size(op, rows, cols):
+            raise ValueError(f"{op} must be a tile-major float64 device buffer for {rows} x {cols}")
+    if C is None:
+        C = torch.zeros((m, n), dtype=torch.float64, device=At.device)
+        beta = 0.0
+    if tuple(C.shape) != (m, n):
+        raise ValueError(f"C has shape {tuple(C.shape)}, expected {(m, n)}")
+    ldc = _ld(C, "C")
+    st = _lib.momms_gemm_tiled(m, n, k, float(alpha), At.data_ptr(), Bt.data_ptr(), float(beta), C.data_ptr(), ldc,
+                               member_id(member), _stream_handle(stream))
+    check_status(st, "momms_gemm_tiled")
+    return C
+
+
 def model_resident(resident, m, n, k, b1, b2, beta=1.0):
     """Sec. 2.2 transfer counts: {a_reads, b_reads, c_reads, c_writes} in elements."""
     import ctypes

@@ -128,3 +128,25 @@ def test_int8_exactness_limit():
     assert mm.split_workspace_size(4, 4, 4, 9, "bf16") == 0
     assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 11, 2, 0, big, 1 << 30, None) == -14
     assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 9, 0, 0, big, 1 << 30, None) == -14
+
+
+def test_tiled_sizes_and_argument_errors():
+    # A: m x k in 128 x 16 tiles, B: k x n in 16 x 128 tiles, zero-padded.
+    assert mm.tiled_size("A", 300, 20) == 8 * 384 * 32
+    assert mm.tiled_size("B", 20, 300) == 8 * 32 * 384
+    assert mm.tiled_size("A", 0, 0) == 8 * 128 * 16
+    assert _lib.momms_tiled_size(ord("C"), 4, 4) == 0
+    assert _lib.momms_tiled_size(ord("A"), -1, 4) == 0
+    big = 1 << 20
+    assert _lib.momms_to_tiled(ord("C"), 0, 4, 4, big, 4, big, None) == -1
+    assert _lib.momms_to_tiled(ord("A"), 2, 4, 4, big, 4, big, None) == -2
+    assert _lib.momms_to_tiled(ord("A"), 0, -1, 4, big, 4, big, None) == -3
+    assert _lib.momms_to_tiled(ord("A"), 0, 4, 4, None, 4, big, None) == -5
+    assert _lib.momms_to_tiled(ord("A"), 0, 4, 8, big, 4, big, None) == -6    # ldx < cols
+    assert _lib.momms_to_tiled(ord("A"), 1, 8, 4, big, 4, big, None) == -6    # transposed: ldx < rows
+    assert _lib.momms_from_tiled(ord("B"), 4, 8, big, big, 4, None) == -6
+    f = _lib.momms_gemm_tiled
+    assert f(-1, 4, 4, 1.0, big, big, 0.0, big, 4, 0, None) == -1
+    assert f(4, 4, 4, 1.0, None, big, 0.0, big, 4, 0, None) == -5
+    assert f(4, 4, 4, 1.0, big, big, 0.0, big, 3, 0, None) == -9
+    assert f(4, 4, 4, 1.0, big, big, 0.0, big, 4, mm.MEMBERS["A2C0"], None) == -10
