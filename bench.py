@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6
 LOWP_MFMA_PEAK_TOPS = {"bf16": 2500.0, "int8": 5000.0}   # dense, per the MI355X specification
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_f64_8192.json")
-TILED_MEMBERS = ["C0", "C3C0", "B3C0", "A3C0"]
+TILED_MEMBERS = ["C0", "C3C0", "B3C0", "A3C0", "A2C0"]
 
 
 def parse():
@@ -317,7 +317,9 @@ def bench_tiled(args):
     conv = timed(lambda: (mm.to_tiled(Ad, "A", out=At), mm.to_tiled(Bd, "B", out=Bt)))
     out = {"conversion_ms": round(conv, 3), "members": {}}
     for member in TILED_MEMBERS:
-        row = timed(lambda: mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member))
+        wsb = mm.workspace_size(m, n, k, member)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda:0") if wsb else None
+        row = timed(lambda: mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws))
         til = timed(lambda: mm.gemm_tiled(At, Bt, m, n, k, Cd, 1.0, 1.0, member=member))
         out["members"][member] = {"row_major_tflops": round(2.0 * m * n * k / row / 1e9, 2),
                                   "tiled_tflops": round(2.0 * m * n * k / til / 1e9, 2)}

@@ -96,8 +96,8 @@ static void launch_a2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int
                       int64_t pk0, int64_t pn0) {
     if (grid_of(s) <= 0) return;
     if (packed) {
-        if (!a.ta) launch_a2_t<false, false, true>(a, k0, k1, s, nj, packed, CfgK::NT, pk0, pn0);
-        else launch_a2_t<true, false, true>(a, k0, k1, s, nj, packed, CfgK::NT, pk0, pn0);
+        if (!a.ta) launch_a2_t<false, false, true>(a, k0, k1, s, nj, packed, kKC, pk0, pn0);
+        else launch_a2_t<true, false, true>(a, k0, k1, s, nj, packed, kKC, pk0, pn0);
         return;
     }
     if (!a.ta && !a.tb) launch_a2_t<false, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);

@@ -302,9 +302,10 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha, 
 // every n-tile of the granule; B slices stream through two LDS buffers.  C is
 // read-modified-written once per chunk: beta applies to the chunk starting at
 // k = 0, later chunks accumulate.  With PACKED, B comes from a packed panel
-// laid out [n-tile][k][NT] (rows of NT doubles, zero-padded), whose origin is
-// (pk0, pn0) in B's coordinates; n-tiles are numbered from pn0.
-template <class CF, int KC, bool TA, bool TB, bool PACKED>
+// laid out [n-tile][k][NT] (rows of NT doubles, zero-padded, ldb rows per
+// n-tile), whose origin is (pk0, pn0) in B's coordinates; n-tiles are
+// numbered from pn0.  With TILED, A is tile-major (128 x 16 slabs).
+template <class CF, int KC, bool TA, bool TB, bool PACKED, bool TILED = false>
 __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
                                                     double alpha, const double* __restrict__ A, int64_t lda,
                                                     const double* __restrict__ B, int64_t ldb, double beta,
@@ -334,15 +335,25 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
         __syncthreads();  // previous chunk's readers of As / Bs are done
 #pragma unroll 1
         for (int c = 0; c < nsl; ++c) {
-            sa.load(A, lda, m0, kb + c * CF::KS, M, kbe, tid);
+            if (TILED) {
+                // tile-major A: 128 x 16 slabs, lda = slabs per row panel,
+                // zero beyond the matrix (m0 is a multiple of 128)
+                const int64_t kk = kb + (int64_t)c * CF::KS;
+                const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + kk % 16;
+                sa.load(P, 16, 0, 0, INT64_MAX, INT64_MAX, tid);
+            } else {
+                sa.load(A, lda, m0, kb + c * CF::KS, M, kbe, tid);
+            }
             sa.store(As + c * CF::KS, AB_LD, tid);
         }
         auto load_b = [&](int t) {
             const int j = t / nsl, sl = t - (t / nsl) * nsl;
             if (PACKED) {
-                // panel row (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j)
+                // panel row (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j);
+                // ldb is the panel height (KC for a per-chunk pack, the padded
+                // k for a tile-major B)
                 const int64_t jt = (nbeg - pn0) / CF::NT + j;
-                const double* P = B + jt * (int64_t)KC * CF::NT;
+                const double* P = B + jt * ldb * CF::NT;
                 sb.load(P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, INT64_MAX, CF::NT, tid);
             } else {
                 sb.load(B, ldb, kb + (int64_t)sl * CF::KS, nbeg + (int64_t)j * CF::NT, kbe, nend, tid);

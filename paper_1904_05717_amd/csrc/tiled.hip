@@ -34,6 +34,7 @@ constexpr int kSlabElems = kT * kSlab;
 
 typedef TileCfg<128, 128, 16, 2, 2> Cfg128;
 typedef TileCfg<64, 64, 16, 2, 2> Cfg64;
+typedef TileCfg<128, 128, 8, 2, 2> CfgK;   // the LDS-resident A-block kernel
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
@@ -231,6 +232,24 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
             }
             break;
         }
+        case MOMMS_A2C0:
+            // Goto without packing: n by nc -> k by kc -> the kernel with the
+            // A block (128 x kc slabs) in LDS and B k-slices read straight
+            // from the tile-major column panels.
+            for (int64_t jc = 0; jc < N; jc += p.nc) {
+                const int64_t je = jc + p.nc < N ? jc + p.nc : N;
+                const Sched s = sched_of(0, jc, M, je, p.mt, 1, false);
+                Sched sg = s;
+                sg.tiles_n = (int)cdiv(je - jc, (int64_t)p.nj * p.nt);
+                const int grid = sg.tiles_m * sg.tiles_n;
+                for (int64_t pc = 0; pc < K; pc += p.kc) {
+                    const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
+                    hipLaunchKernelGGL((k_a2<CfgK, kKC, false, false, true, true>), dim3(grid), dim3(CfgK::THREADS),
+                                       0, a.st, M, N, pc, pe, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc,
+                                       sg, p.nj, (int64_t)0, (int64_t)0);
+                }
+            }
+            break;
         default:
             return MOMMS_ERR_INTERNAL;
     }
@@ -315,7 +334,9 @@ int momms_gemm_tiled(int64_t m, int64_t n, int64_t k, double alpha, const double
         member = select_member(m, n, k);
         if (member != MOMMS_C0 && member != MOMMS_B3C0 && member != MOMMS_A3C0) member = MOMMS_C3C0;
     }
-    if (member != MOMMS_C0 && member != MOMMS_C3C0 && member != MOMMS_B3C0 && member != MOMMS_A3C0) return -10;
+    if (member != MOMMS_C0 && member != MOMMS_C3C0 && member != MOMMS_B3C0 && member != MOMMS_A3C0 &&
+        member != MOMMS_A2C0)
+        return -10;
     if (cdiv(m, 64) * cdiv(n, 64) >= (int64_t)INT_MAX / 2) return MOMMS_ERR_INFEASIBLE;
     if (m == 0 || n == 0) return 0;
     if ((alpha == 0.0 || k == 0) && beta == 1.0) return 0;

@@ -1,7 +1,8 @@
 """Tile-major ("prepacked") storage mode through the C ABI: conversion round
 trips are bit-exact, and the product on tiled operands equals the row-major
 product of the same member bit for bit (same loop nest, k stagger and
-micro-kernel; only the loads differ), within the FP64 bound of the oracle."""
+micro-kernel; only the loads differ; Goto reads the tiled B in place instead
+of packing it), within the FP64 bound of the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -12,7 +13,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 mm = pytest.importorskip("paper_1904_05717_amd")
 DEV = "cuda:0"
-MEMBERS = ["C0", "C3C0", "B3C0", "A3C0", "AUTO"]
+MEMBERS = ["C0", "C3C0", "B3C0", "A3C0", "A2C0", "AUTO"]
 
 
 def dev(x):
@@ -58,8 +59,12 @@ def test_equals_row_major_and_within_bound(member, shape):
     got = mm.gemm_tiled(mm.to_tiled(Ad, "A"), mm.to_tiled(Bd, "B"), m, n, k, dev(C.copy()), 1.5, -0.5,
                         member=member).cpu().numpy()
     ref_member = member if member != "AUTO" else mm.select_member(m, n, k)
-    if ref_member in ("C0", "C3C0", "B3C0", "A3C0"):
-        row = mm.gemm(Ad, Bd, dev(C.copy()), 1.5, -0.5, member=ref_member).cpu().numpy()
+    if ref_member in ("C0", "C3C0", "B3C0", "A3C0", "A2C0"):
+        # Goto on row-major operands packs B into the workspace; on tiled
+        # operands it reads the same panel layout in place
+        wsb = mm.workspace_size(m, n, k, ref_member)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=DEV) if wsb else None
+        row = mm.gemm(Ad, Bd, dev(C.copy()), 1.5, -0.5, member=ref_member, workspace=ws).cpu().numpy()
         np.testing.assert_array_equal(got, row)
     want = oracle.gemm(A, B, C, 1.5, -0.5)
     bound = oracle.error_bound(A, B, C, 1.5, -0.5, k)
