@@ -1,7 +1,7 @@
 """Benchmark of the MOMMS FP64 GEMM family on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--member NAME] [--size N]
-                    [--only fp64|split|batch|backward|members|tiled]
+                    [--only fp64|split|batch|backward|members|tiled|syrk]
 
 A step is one C := A B + C product in FP64 at m = n = k = 8192 (uniform
 [-1, 1] entries, beta = 1 with random C) by the selected family member
@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--member", default="AUTO")
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--only", default="all",
-                    choices=["all", "fp64", "split", "batch", "backward", "members", "tiled"])
+                    choices=["all", "fp64", "split", "batch", "backward", "members", "tiled", "syrk"])
     ap.add_argument("--split", default="int8:8,int8:9,bf16:7",
                     help="split-precision configurations to time, as type:slices[,type:slices...]")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
@@ -326,6 +326,40 @@ def bench_tiled(args):
     return out
 
 
+def bench_syrk(args):
+    """Symmetric rank-k update C := X X^T on the lower triangle at n = k = size
+    (C3C0 order, tiles above the diagonal skipped) against the full product
+    X X^T by the same member; rate in n (n + 1) k flops per second."""
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    n = k = args.size
+    X = torch.from_numpy(workloads.uniform((n, k), 26)).to("cuda:0")
+    Xt = X.t().contiguous()
+    C = torch.zeros((n, n), dtype=torch.float64, device="cuda:0")
+    reps = 1 if args.profile else 5
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_syrk = timed(lambda: mm.syrk(X, C, 1.0, 0.0, uplo="L", member="C3C0"))
+    t_gemm = timed(lambda: mm.gemm(X, Xt, C, 1.0, 0.0, member="C3C0"))
+    return {"n": n, "k": k, "syrk_ms": round(t_syrk, 3),
+            "syrk_tflops": round(n * (n + 1) * k / t_syrk / 1e9, 2),
+            "full_product_ms": round(t_gemm, 3), "full_product_tflops": round(2.0 * n * n * k / t_gemm / 1e9, 2),
+            "time_ratio": round(t_syrk / t_gemm, 3)}
+
+
 def bench_batch(args):
     import torch
 
@@ -553,9 +587,9 @@ def main():
         profile_members(args.size)
         return
     only = "fp64" if (args.profile and args.only == "all") else args.only
-    if only in ("split", "batch", "backward", "members", "tiled"):
+    if only in ("split", "batch", "backward", "members", "tiled", "syrk"):
         fn = {"split": bench_split, "batch": bench_batch, "backward": bench_backward, "members": bench_members,
-              "tiled": bench_tiled}[only]
+              "tiled": bench_tiled, "syrk": bench_syrk}[only]
         print(json.dumps({only: fn(args)}), flush=True)
         return
     f = bench_fp64(args)
@@ -587,6 +621,7 @@ def main():
         out["backward"] = bench_backward(args)
         out["members_8192"] = bench_members(args)
         out["tiled_storage"] = bench_tiled(args)
+        out["syrk"] = bench_syrk(args)
     if not args.no_cpu and not args.profile:
         out["cpu_baseline"] = cpu_baseline(args.size, args.size, args.size, args.cpu_seconds)
     print(json.dumps(out), flush=True)

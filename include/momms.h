@@ -303,6 +303,20 @@ int momms_from_tiled(int operand, int64_t rows, int64_t cols, const double *T, d
 int momms_gemm_tiled(int64_t m, int64_t n, int64_t k, double alpha, const double *At, const double *Bt,
                      double beta, double *C, int64_t ldc, int family_member, momms_stream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Symmetric rank-k update on the family (the paper names the other level-3
+ * BLAS as the next target, Sec. 6): C := alpha op(A) op(A)^T + beta C on the
+ * lower (uplo = 'L') or upper ('U') triangle of the n x n row-major C (pitch
+ * ldc); op(A) = A (trans = 0, n x k, pitch lda) or A^T (trans = 1, A stored
+ * k x n).  The other triangle is neither read nor written.  family_member:
+ * MOMMS_AUTO (= MOMMS_C3C0), MOMMS_C0 or MOMMS_C3C0, whose tile orders are
+ * kept with the tiles outside the triangle skipped.  beta = 0 does not read C.
+ * Argument numbers: 1 uplo, 2 trans, 3 n, 4 k, 5 alpha, 6 A, 7 lda, 8 beta,
+ * 9 C, 10 ldc, 11 family_member, 12 stream.
+ */
+int momms_syrk(int uplo, int trans, int64_t n, int64_t k, double alpha, const double *A, int64_t lda,
+               double beta, double *C, int64_t ldc, int family_member, momms_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -269,6 +269,28 @@ def gemm_tiled(At, Bt, m, n, k, C=None, alpha=1.0, beta=0.0, member="AUTO", stre
     return C
 
 
+def syrk(A, C=None, alpha=1.0, beta=0.0, uplo="L", trans=False, member="AUTO", stream=None):
+    """C := alpha * op(A) @ op(A).T + beta * C on one triangle ('L' or 'U') of C.
+
+    op(A) = A (n x k) or A.T when trans.  The other triangle of C is left
+    untouched; a new C (None) starts from zeros.
+    """
+    n, k = (A.shape[1], A.shape[0]) if trans else (A.shape[0], A.shape[1])
+    lda = _ld(A, "A")
+    if C is None:
+        C = torch.zeros((n, n), dtype=torch.float64, device=A.device)
+        beta = 0.0
+    if tuple(C.shape) != (n, n):
+        raise ValueError(f"C has shape {tuple(C.shape)}, expected {(n, n)}")
+    if uplo not in ("L", "U"):
+        raise ValueError("uplo must be 'L' or 'U'")
+    ldc = _ld(C, "C")
+    st = _lib.momms_syrk(ord(uplo), int(bool(trans)), n, k, float(alpha), A.data_ptr(), lda, float(beta),
+                         C.data_ptr(), ldc, member_id(member), _stream_handle(stream))
+    check_status(st, "momms_syrk")
+    return C
+
+
 def model_resident(resident, m, n, k, b1, b2, beta=1.0):
     """Sec. 2.2 transfer counts: {a_reads, b_reads, c_reads, c_writes} in elements."""
     import ctypes

@@ -174,8 +174,10 @@ __device__ __forceinline__ void zero_acc(d4 (&acc)[CF::BM][CF::BN]) {
 // Epilogue: C = alpha * acc + beta * C on the workgroup tile at (m0, n0);
 // beta == 0 does not read C.  Sixteen consecutive lanes write one 128-byte row
 // segment.
-template <class CF>
-__device__ __forceinline__ void store_c(const d4 (&acc)[CF::BM][CF::BN], double alpha, double beta,
+// TRI = 1 (2): store only the entries with row >= col (row <= col), the
+// triangle of a symmetric update; TRI = 0 stores the whole tile.
+template <class CF, int TRI>
+__device__ __forceinline__ void store_c_tri(const d4 (&acc)[CF::BM][CF::BN], double alpha, double beta,
                                         double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0,
                                         int64_t M, int64_t N, int wm, int wn, int lane) {
     const int li = lane & 15, lk = lane >> 4;
@@ -187,7 +189,7 @@ __device__ __forceinline__ void store_c(const d4 (&acc)[CF::BM][CF::BN], double 
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = m0 + wm * CF::WTM + i * 16 + lk + 4 * r;
                 const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
-                if (row < M && col < N) {
+                if (row < M && col < N && (TRI == 0 || (TRI == 1 ? row >= col : row <= col))) {
                     double* p = C + row * ldc + col;
                     double v = alpha * acc[i][j][r];
                     if (beta != 0.0) v += beta * (*p);
@@ -196,12 +198,19 @@ __device__ __forceinline__ void store_c(const d4 (&acc)[CF::BM][CF::BN], double 
             }
 }
 
+template <class CF>
+__device__ __forceinline__ void store_c(const d4 (&acc)[CF::BM][CF::BN], double alpha, double beta,
+                                        double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0,
+                                        int64_t M, int64_t N, int wm, int wn, int lane) {
+    store_c_tri<CF, 0>(acc, alpha, beta, C, ldc, m0, n0, M, N, wm, wn, lane);
+}
+
 // ---------------------------------------------------------------------------
 // Register-resident C tile at (m0, n0): accumulate over k in [k_begin,
 // k_end) through the double-buffered LDS stage, then C = alpha*acc + beta*C.
 // (tm, tn) only staggers the k start (see below).  Shared by k_regc and the
 // persistent batched kernel.
-template <class CF, bool TA, bool TB, bool FAST_INTERIOR = true>
+template <class CF, bool TA, bool TB, bool FAST_INTERIOR = true, int TRI = 0>
 __device__ __forceinline__ void regc_tile(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha,
                                           const double* __restrict__ A, int64_t lda,
                                           const double* __restrict__ B, int64_t ldb, double beta,
@@ -277,7 +286,7 @@ __device__ __forceinline__ void regc_tile(int64_t M, int64_t N, int64_t k_begin,
             __syncthreads();
         }
     }
-    store_c<CF>(acc, alpha, beta, C, ldc, m0, n0, M, N, wm, wn, lane);
+    store_c_tri<CF, TRI>(acc, alpha, beta, C, ldc, m0, n0, M, N, wm, wn, lane);
 }
 
 // k_regc: one C granule (MT x NT) per workgroup, accumulated in registers over

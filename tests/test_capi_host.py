@@ -150,3 +150,18 @@ def test_tiled_sizes_and_argument_errors():
     assert f(4, 4, 4, 1.0, None, big, 0.0, big, 4, 0, None) == -5
     assert f(4, 4, 4, 1.0, big, big, 0.0, big, 3, 0, None) == -9
     assert f(4, 4, 4, 1.0, big, big, 0.0, big, 4, mm.MEMBERS["B3A2C0"], None) == -10
+
+
+def test_syrk_argument_errors():
+    f = _lib.momms_syrk
+    big = 1 << 20
+    assert f(ord("X"), 0, 4, 4, 1.0, big, 4, 0.0, big, 4, 0, None) == -1
+    assert f(ord("L"), 2, 4, 4, 1.0, big, 4, 0.0, big, 4, 0, None) == -2
+    assert f(ord("L"), 0, -1, 4, 1.0, big, 4, 0.0, big, 4, 0, None) == -3
+    assert f(ord("L"), 0, 4, -1, 1.0, big, 4, 0.0, big, 4, 0, None) == -4
+    assert f(ord("L"), 0, 4, 4, 1.0, None, 4, 0.0, big, 4, 0, None) == -6
+    assert f(ord("L"), 0, 4, 8, 1.0, big, 4, 0.0, big, 4, 0, None) == -7     # lda < k
+    assert f(ord("U"), 1, 8, 4, 1.0, big, 4, 0.0, big, 8, 0, None) == -7     # transposed: lda < n
+    assert f(ord("L"), 0, 4, 4, 1.0, big, 4, 0.0, None, 4, 0, None) == -9
+    assert f(ord("L"), 0, 4, 4, 1.0, big, 4, 0.0, big, 3, 0, None) == -10
+    assert f(ord("L"), 0, 4, 4, 1.0, big, 4, 0.0, big, 4, mm.MEMBERS["A2C0"], None) == -11
