@@ -217,11 +217,15 @@ int momms_balanced_block(double M, double beta_b, double beta_c, double *mc, dou
  * whole diagonal while slices * k (k rounded up to 128) <= 2^17; larger k
  * returns MOMMS_ERR_INFEASIBLE.  Its error bound is the BF16 one with
  * 2^-(7 slices) for 2^-(9 slices), so 9 INT8 slices match 7 BF16 ones.
- * MOMMS_SLICE_FP8 is not built (-15).
+ * MOMMS_SLICE_FP8 uses slices of 4 (first) and 5 (further) bits cut by
+ * round to nearest (|d| <= 16, exact in OCP FP8 E4M3) multiplied on FP8
+ * MFMA with FP32 accumulation, exact over a whole diagonal while slices * k
+ * (k rounded up to 128) <= 2^16; larger k returns MOMMS_ERR_INFEASIBLE.  Its
+ * error bound is the BF16 one with 2^-(5 slices) for 2^-(9 slices).
  * Argument numbers: 1 transA, 2 transB, 3 m, 4 n, 5 k, 6 alpha, 7 A, 8 lda,
- * 9 B, 10 ldb, 11 beta, 12 C, 13 ldc, 14 slices (1..8 BF16, 1..10 INT8),
- * 15 slice_type
- * (MOMMS_SLICE_BF16 or MOMMS_SLICE_INT8), 16 family_member (MOMMS_AUTO, MOMMS_C0 or
+ * 9 B, 10 ldb, 11 beta, 12 C, 13 ldc, 14 slices (1..8 BF16, 1..10 INT8,
+ * 1..12 FP8), 15 slice_type (MOMMS_SLICE_BF16, MOMMS_SLICE_FP8 or
+ * MOMMS_SLICE_INT8), 16 family_member (MOMMS_AUTO, MOMMS_C0 or
  * MOMMS_C3C0: tile order of the slice products), 17 workspace (device,
  * 256-byte aligned), 18 ws_bytes (>= momms_split_workspace_size), 19 stream.
  * The workspace holds the exponents, the slices and the FP64 partial sums;

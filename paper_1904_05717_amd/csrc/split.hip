@@ -23,6 +23,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/momms.h"
 #include "plan_internal.h"
@@ -34,6 +35,8 @@ namespace split {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kB0 = 8;       // bits of the first BF16 slice
 constexpr int kB = 9;        // bits of every further slice
@@ -51,6 +54,10 @@ constexpr int64_t kI8MaxProducts = (int64_t)1 << 17;
 // 8 BF16 slices carry 8 + 7 * 9 = 71 bits and 10 INT8 slices 70: beyond the
 // 53 of a double in both cases, so larger counts add nothing.
 constexpr int kMaxSlicesBf16 = 8, kMaxSlicesI8 = 10;
+// FP8 E4M3 slices: 4 bits, then 5 (round to nearest, |d| <= 16, exact in
+// E4M3); products reach 2^8, so FP32 sums are exact while slices * k_p <= 2^16.
+constexpr int kF8B0 = 4, kF8B = 5, kMaxSlicesF8 = 12;
+constexpr int64_t kF8MaxProducts = (int64_t)1 << 16;
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
@@ -105,13 +112,24 @@ __global__ __launch_bounds__(256) void k_colmax_exp(const double* __restrict__ P
     if (mx != 0.0) atomicMax(out + c, exp_of(mx));
 }
 
+// OCP FP8 E4M3 byte (bias 7, 3 mantissa bits) of an integer |d| <= 16.
+__device__ __forceinline__ uint32_t e4m3_of_int(int d) {
+    if (d == 0) return 0u;
+    const uint32_t sgn = d < 0 ? 0x80u : 0u;
+    const int a = d < 0 ? -d : d;
+    const int e = 31 - __clz(a);                       // a in [2^e, 2^(e+1))
+    const uint32_t man = (uint32_t)(((a << 3) >> e) - 8);
+    return sgn | ((uint32_t)(e + 7) << 3) | man;
+}
+
 // Slices of the logical R x Cc matrix X, X(r, c) = P[r*ld + c] (TRANSPOSED =
 // false) or P[c*ld + r] (true), scaled per row by 2^-e[r].  Writes
 // out[s][r][c] (pitch Cp, slice stride Rp*Cp) for all r < Rp, c < Cp (zero
-// outside X): BF16 bit patterns (INT8 = false: round to nearest, 8 + 9 s
-// bits) or int8 values (INT8 = true: truncation, 7 (s + 1) bits).  64 x 64
-// tiles go through LDS so that global reads and writes are both contiguous.
-template <bool TRANSPOSED, bool INT8>
+// outside X) in the slice type KIND.  64 x 64 tiles go through LDS so that
+// global reads and writes are both contiguous.
+// KIND: 0 BF16 bit patterns (round to nearest, 8 + 9 s bits), 1 int8 values
+// (truncation, 7 (s + 1) bits), 2 FP8 E4M3 bytes (round to nearest, 4 + 5 s).
+template <bool TRANSPOSED, int KIND>
 __global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int64_t ld, int64_t R, int64_t Cc,
                                                const int* __restrict__ e, int S, void* __restrict__ outv,
                                                int64_t Rp, int64_t Cp) {
@@ -142,7 +160,7 @@ __global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int
     const int64_t slice = Rp * Cp;
     const int64_t o = gr * Cp + c0 + cb;
     for (int s_ = 0; s_ < S; ++s_) {
-        if (INT8) {
+        if (KIND == 1) {
             const int w = kI8Bits * (s_ + 1);
             const double up = ldexp(1.0, w), down = ldexp(1.0, -w);
             uint32_t word[4];
@@ -154,6 +172,23 @@ __global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int
                     const double d = trunc(rem[4 * q + b] * up);            // |d| <= 127
                     rem[4 * q + b] -= d * down;
                     x |= (uint32_t)(uint8_t)(int8_t)d << (8 * b);
+                }
+                word[q] = x;
+            }
+            *reinterpret_cast<uint4*>(static_cast<int8_t*>(outv) + o + s_ * slice) =
+                make_uint4(word[0], word[1], word[2], word[3]);
+        } else if (KIND == 2) {
+            const int w = kF8B0 + s_ * kF8B;
+            const double up = ldexp(1.0, w), down = ldexp(1.0, -w);
+            uint32_t word[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const double d = rint(rem[4 * q + b] * up);             // |d| <= 16
+                    rem[4 * q + b] -= d * down;
+                    x |= e4m3_of_int((int)d) << (8 * b);
                 }
                 word[q] = x;
             }
@@ -413,9 +448,50 @@ __device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^
         __syncthreads();                                                                         \
     } while (0)
 
+// FP8 form: one v_mfma_f32_16x16x128_f8f6f4 covers both 64-deep windows of a
+// k-step.  Only the pairing of A and B k values matters, so lane (li, lk)
+// supplies chunk lk of window 0 and chunk lk of window 1 of its row for both
+// operands (the conflict-free fragment reads of the INT8 form; checked on the
+// device against exact integer products).  Half h runs A fragments 4h..4h+3
+// against the 4 B fragments read at the start of the step.
+__device__ __forceinline__ i8v frag_f8(const int8_t* p, int win) {
+    const i4 lo = *reinterpret_cast<const i4*>(p), hi = *reinterpret_cast<const i4*>(p + win);
+    return i8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+#define MOMMS_F8_HALF(buf_, h_)                                                                  \
+    do {                                                                                         \
+        const int8_t* la = As + (buf_) * i8::kStageA;                                            \
+        _Pragma("unroll") for (int i2 = 4 * (h_); i2 < 4 * (h_) + 4; i2 += 2) {                  \
+            const i8v a0 = frag_f8(la + fa_off[i2], i8::kWinA);                                  \
+            const i8v a1 = frag_f8(la + fa_off[i2 + 1], i8::kWinA);                              \
+            _Pragma("unroll") for (int j = 0; j < 4; ++j)                                        \
+                acc[i2][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a0, bf8[j], acc[i2][j], 0, 0, 0, 0, 0, 0); \
+            _Pragma("unroll") for (int j = 0; j < 4; ++j)                                        \
+                acc[i2 + 1][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a1, bf8[j], acc[i2 + 1][j], 0, 0, 0, 0, 0, 0); \
+            __builtin_amdgcn_sched_barrier(0);                                                   \
+        }                                                                                        \
+    } while (0)
+
+#define MOMMS_F8_STEP(t_, buf_)                                                                  \
+    do {                                                                                         \
+        const int8_t* lb = Bs + (buf_) * i8::kStageB;                                            \
+        i8v bf8[4];                                                                              \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j) bf8[j] = frag_f8(lb + fb_off[j], i8::kWinB); \
+        MOMMS_F8_HALF(buf_, 0);                                                                  \
+        __builtin_amdgcn_sched_barrier(0);                                                       \
+        if ((t_) + 1 < total) MOMMS_I8_LSTORE((buf_) ^ 1, g);                                    \
+        __builtin_amdgcn_sched_barrier(0);                                                       \
+        MOMMS_I8_GLOAD(g, (t_) + 2 < last ? (t_) + 2 : last);                                    \
+        __builtin_amdgcn_sched_barrier(0);                                                       \
+        MOMMS_F8_HALF(buf_, 1);                                                                  \
+        __syncthreads();                                                                         \
+    } while (0)
+
 // SA and SB are deliberately not __restrict__: as provably unclobbered loads
-// the compiler would sink the prefetch past the barrier to its use.
-template <bool FIRST, bool LAST>
+// the compiler would sink the prefetch past the barrier to its use.  F8: the
+// slices are FP8 E4M3 and the accumulators FP32 (exact: every partial sum is
+// an integer below 2^24).
+template <bool FIRST, bool LAST, bool F8>
 __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int64_t kp, int d,
                                                        const int8_t* SA, const int8_t* SB, int64_t sa_stride,
                                                        int64_t sb_stride, int shift, const int* __restrict__ ea,
@@ -431,11 +507,11 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
     const int wm = wave >> 2, wn = wave & 3;
     const int li = lane & 15, lk = lane >> 4;
 
-    i4 acc[8][4];
+    typename std::conditional<F8, f4, i4>::type acc[8][4];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = i4{0, 0, 0, 0};
+        for (int j = 0; j < 4; ++j) acc[i][j] = {0, 0, 0, 0};
 
     // staging: thread tid moves the 16-byte chunk gq of rows grow, grow + 64,
     // grow + 128, grow + 192 of both operands (8 threads cover one row's 128
@@ -461,7 +537,11 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
     MOMMS_I8_LSTORE(0, g);
     MOMMS_I8_GLOAD(g, 1 < last ? 1 : last);
     __syncthreads();
-    for (int t = 0; t < total; ++t) MOMMS_I8_STEP(t, t & 1);
+    if constexpr (F8) {
+        for (int t = 0; t < total; ++t) MOMMS_F8_STEP(t, t & 1);
+    } else {
+        for (int t = 0; t < total; ++t) MOMMS_I8_STEP(t, t & 1);
+    }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the surplus prefetches
 
 #pragma unroll
@@ -487,6 +567,8 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
 }
 #undef MOMMS_I8_GLOAD
 #undef MOMMS_I8_LSTORE
+#undef MOMMS_F8_HALF
+#undef MOMMS_F8_STEP
 #undef MOMMS_I8_WINDOW
 #undef MOMMS_I8_STEP
 
@@ -508,12 +590,12 @@ struct Layout {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool int8) {
+static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool bytes) {
     Layout L;
-    const size_t esz = int8 ? sizeof(int8_t) : sizeof(uint16_t);
-    L.mp = rup(m > 0 ? m : 1, int8 ? kI8MT : kMT);
-    L.np = rup(n > 0 ? n : 1, int8 ? kI8NT : kMT);
-    L.kp = rup(k > 0 ? k : 1, int8 ? kI8KS : kKPad);
+    const size_t esz = bytes ? sizeof(int8_t) : sizeof(uint16_t);
+    L.mp = rup(m > 0 ? m : 1, bytes ? kI8MT : kMT);
+    L.np = rup(n > 0 ? n : 1, bytes ? kI8NT : kMT);
+    L.kp = rup(k > 0 ? k : 1, bytes ? kI8KS : kKPad);
     size_t o = 0;
     L.off_ea = o; o = align256(o + sizeof(int) * (size_t)m);
     L.off_eb = o; o = align256(o + sizeof(int) * (size_t)n);
@@ -524,11 +606,11 @@ static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool int8) {
     return L;
 }
 
-template <bool F, bool L>
+template <bool F, bool L, bool F8>
 static void launch_i8_diag(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t kp, int d, const int8_t* SA,
                            const int8_t* SB, int64_t sas, int64_t sbs, int shift, const int* ea, const int* eb,
                            double* V, int64_t ldv, double alpha, double beta, double* C, int64_t ldc, Sched s) {
-    hipLaunchKernelGGL((k_split_i8_diag<F, L>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs, shift, ea,
+    hipLaunchKernelGGL((k_split_i8_diag<F, L, F8>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs, shift, ea,
                        eb, V, ldv, alpha, beta, C, ldc, s);
 }
 
@@ -548,10 +630,12 @@ extern "C" {
 size_t momms_split_workspace_size(int64_t m, int64_t n, int64_t k, int slices, int slice_type) {
     using namespace momms::split;
     if (m < 0 || n < 0 || k < 0 || slices < 1) return 0;
-    if (slice_type == MOMMS_SLICE_BF16 ? slices > kMaxSlicesBf16
-                                       : slice_type != MOMMS_SLICE_INT8 || slices > kMaxSlicesI8)
-        return 0;
-    return layout(m, n, k, slices, slice_type == MOMMS_SLICE_INT8).total;
+    const int max_slices = slice_type == MOMMS_SLICE_BF16 ? kMaxSlicesBf16
+                           : slice_type == MOMMS_SLICE_INT8 ? kMaxSlicesI8
+                           : slice_type == MOMMS_SLICE_FP8  ? kMaxSlicesF8
+                                                            : 0;
+    if (slices > max_slices) return 0;
+    return layout(m, n, k, slices, slice_type != MOMMS_SLICE_BF16).total;
 }
 
 int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
@@ -571,15 +655,20 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     if (ldb < (tb ? (k > 1 ? k : 1) : (n > 1 ? n : 1))) return -10;
     if (m > 0 && n > 0 && C == nullptr) return -12;
     if (ldc < (n > 1 ? n : 1)) return -13;
-    if (slices < 1 || slices > kMaxSlicesI8) return -14;
-    if (slice_type != MOMMS_SLICE_BF16 && slice_type != MOMMS_SLICE_INT8) return -15;
-    const bool int8 = slice_type == MOMMS_SLICE_INT8;
-    if (!int8 && slices > kMaxSlicesBf16) return -14;
+    if (slice_type != MOMMS_SLICE_BF16 && slice_type != MOMMS_SLICE_INT8 && slice_type != MOMMS_SLICE_FP8)
+        return -15;
+    const bool f8 = slice_type == MOMMS_SLICE_FP8;
+    const bool bytes = slice_type != MOMMS_SLICE_BF16;   // INT8 and FP8 share the byte layout and kernel
+    const int max_slices = f8 ? kMaxSlicesF8 : bytes ? kMaxSlicesI8 : kMaxSlicesBf16;
+    if (slices < 1 || slices > max_slices) return -14;
     if (family_member != MOMMS_AUTO && family_member != MOMMS_C0 && family_member != MOMMS_C3C0) return -16;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return -17;
-    const Layout L = layout(m, n, k, slices, int8);
-    // INT8: every diagonal's INT32 sum must stay exact (slices * kp <= 2^17).
-    if (int8 && reads_ab && (int64_t)slices * L.kp > kI8MaxProducts) return MOMMS_ERR_INFEASIBLE;
+    const Layout L = layout(m, n, k, slices, bytes);
+    // Every diagonal's sum must stay exact: INT8 in INT32 (slices * kp <=
+    // 2^17, products up to 127^2), FP8 in FP32 (slices * kp <= 2^16, products
+    // up to 16^2, sums below 2^24).
+    if (bytes && reads_ab && (int64_t)slices * L.kp > (f8 ? kF8MaxProducts : kI8MaxProducts))
+        return MOMMS_ERR_INFEASIBLE;
     if (reads_ab && (workspace == nullptr || ws_bytes < L.total)) return -18;
     if (cdiv(m, kMT) * cdiv(n, kMT) >= (int64_t)INT_MAX / 2) return MOMMS_ERR_INFEASIBLE;
 
@@ -620,20 +709,20 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     {
         const dim3 ga((unsigned)cdiv(L.kp, 64), (unsigned)cdiv(L.mp, 64));
         const dim3 gb((unsigned)cdiv(L.kp, 64), (unsigned)cdiv(L.np, 64));
-        if (int8) {
-            if (!ta) hipLaunchKernelGGL((k_slice<false, true>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
-            else     hipLaunchKernelGGL((k_slice<true, true>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
-            if (!tb) hipLaunchKernelGGL((k_slice<true, true>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
-            else     hipLaunchKernelGGL((k_slice<false, true>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
-        } else {
-            if (!ta) hipLaunchKernelGGL((k_slice<false, false>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
-            else     hipLaunchKernelGGL((k_slice<true, false>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);
-            if (!tb) hipLaunchKernelGGL((k_slice<true, false>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
-            else     hipLaunchKernelGGL((k_slice<false, false>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);
-        }
+#define MOMMS_SLICE_LAUNCH(KIND_)                                                                                \
+    do {                                                                                                        \
+        if (!ta) hipLaunchKernelGGL((k_slice<false, KIND_>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp); \
+        else     hipLaunchKernelGGL((k_slice<true, KIND_>), ga, dim3(256), 0, st, A, lda, m, k, ea, slices, SA, L.mp, L.kp);  \
+        if (!tb) hipLaunchKernelGGL((k_slice<true, KIND_>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);  \
+        else     hipLaunchKernelGGL((k_slice<false, KIND_>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp); \
+    } while (0)
+        if (f8)         MOMMS_SLICE_LAUNCH(2);
+        else if (bytes) MOMMS_SLICE_LAUNCH(1);
+        else            MOMMS_SLICE_LAUNCH(0);
+#undef MOMMS_SLICE_LAUNCH
     }
     // s3 + s4: one launch per diagonal, smallest first.
-    const int tile_m = int8 ? kI8MT : kMT, tile_n = int8 ? kI8NT : kMT;
+    const int tile_m = bytes ? kI8MT : kMT, tile_n = bytes ? kI8NT : kMT;
     Sched s;
     s.m_off = 0;
     s.n_off = 0;
@@ -642,29 +731,23 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     s.tiles_m = (int)cdiv(m, tile_m);
     s.tiles_n = (int)cdiv(n, tile_n);
     const bool grouped = family_member != MOMMS_C0;
-    const int gm = int8 ? 4 : 8;  // tiles per group along m in the grouped order
+    const int gm = bytes ? 4 : 8;  // tiles per group along m in the grouped order
     s.group_m = grouped ? (s.tiles_m < gm ? s.tiles_m : gm) : 1;
     s.xcd = grouped ? kXcds : 1;
     const dim3 grid((unsigned)(s.tiles_m * s.tiles_n));
     const int64_t sas = L.mp * L.kp, sbs = L.np * L.kp;
     for (int d = slices - 1; d >= 0; --d) {
         const bool first = d == slices - 1, last = d == 0;
-        if (int8) {
-            const int shift = 2 * kI8Bits + d * kI8Bits;
+        if (bytes) {
+            const int shift = f8 ? 2 * kF8B0 + d * kF8B : 2 * kI8Bits + d * kI8Bits;
             const int8_t* a8 = static_cast<const int8_t*>(SA);
             const int8_t* b8 = static_cast<const int8_t*>(SB);
-            if (first && last)
-                launch_i8_diag<true, true>(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha,
-                                           beta, C, ldc, s);
-            else if (first)
-                launch_i8_diag<true, false>(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha,
-                                            beta, C, ldc, s);
-            else if (last)
-                launch_i8_diag<false, true>(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha,
-                                            beta, C, ldc, s);
-            else
-                launch_i8_diag<false, false>(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha,
-                                             beta, C, ldc, s);
+            decltype(&launch_i8_diag<true, true, false>) launch;
+            if (f8) launch = first ? (last ? launch_i8_diag<true, true, true> : launch_i8_diag<true, false, true>)
+                                   : (last ? launch_i8_diag<false, true, true> : launch_i8_diag<false, false, true>);
+            else    launch = first ? (last ? launch_i8_diag<true, true, false> : launch_i8_diag<true, false, false>)
+                                   : (last ? launch_i8_diag<false, true, false> : launch_i8_diag<false, false, false>);
+            launch(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha, beta, C, ldc, s);
             continue;
         }
         const int shift = 2 * kB0 + d * kB;

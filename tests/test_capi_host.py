@@ -114,7 +114,7 @@ def test_member_table_overrides_prior_and_validates():
     assert mm.select_member(8192, 8192, 8192) in mm.FAMILY
 
 
-def test_int8_exactness_limit():
+def test_int8_and_fp8_exactness_limits():
     # slices * k (k rounded up to 128) must stay <= 2^17 so every INT32 sum
     # is exact; beyond it the call is refused before any launch.
     f = mm._lib.momms_gemm_split
@@ -122,11 +122,17 @@ def test_int8_exactness_limit():
     assert f(0, 0, 4, 4, 16385, 1.0, big, 16385, big, 4, 0.0, big, 4, 8, 2, 0, big, 1 << 40, None) == 1002
     assert f(0, 0, 4, 4, 18689, 1.0, big, 18689, big, 4, 0.0, big, 4, 7, 2, 0, big, 1 << 40, None) == 1002
     assert mm.split_workspace_size(4, 4, 16384, 8, "int8") > 0
-    assert mm.split_workspace_size(4, 4, 4, 3, "fp8") == 0
+    assert mm.split_workspace_size(4, 4, 4, 3, "fp8") > 0
+    assert mm.split_workspace_size(4, 4, 4, 12, "fp8") > 0
+    assert mm.split_workspace_size(4, 4, 4, 13, "fp8") == 0
     assert mm.split_workspace_size(4, 4, 4, 10, "int8") > 0
     assert mm.split_workspace_size(4, 4, 4, 11, "int8") == 0
     assert mm.split_workspace_size(4, 4, 4, 9, "bf16") == 0
     assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 11, 2, 0, big, 1 << 30, None) == -14
+    # FP8: slices * k <= 2^16 keeps every FP32 sum of products up to 16^2 exact
+    assert f(0, 0, 4, 4, 8193, 1.0, big, 8193, big, 4, 0.0, big, 4, 8, 1, 0, big, 1 << 40, None) == 1002
+    assert f(0, 0, 4, 4, 8192, 1.0, big, 8192, big, 4, 0.0, big, 4, 8, 1, 0, big, 0, None) == -18
+    assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 13, 1, 0, big, 1 << 30, None) == -14
     assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 9, 0, 0, big, 1 << 30, None) == -14
 
 

@@ -118,8 +118,9 @@ def test_config3_sampled_8192():
 @pytest.mark.parametrize("S", [1, 2, 4, 7, 9, 10])
 @pytest.mark.parametrize("kind", ["uniform", "loguniform"])
 def test_int8_bit_exact_against_emulation(S, kind):
-    # 300 x 280 x 260: two 256-row and three 128-column tiles with ragged
-    # tails, k over three 128-deep slabs (ragged), so the staggered k start wraps.
+    # 300 x 280 x 260: two 256 x 256 tiles along m and along n, both with
+    # ragged tails, k over three 128-deep steps (ragged), so the staggered k
+    # start wraps.
     m, n, k = 300, 280, 260
     A, B, C = workloads.gemm_operands(m, n, k, kind=kind)
     want = se.split_gemm(A, B, S, "int8", C, 1.0, 1.0)
@@ -186,3 +187,92 @@ def test_int8_config3_sampled_8192():
     exact = oracle.gemm_entries(A, B, rows, cols)
     absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
     assert np.max(np.abs(got[rows, cols] - exact) / absab) <= 1e-13
+
+
+# FP8 slices: 4 + 5 s bit slices (round to nearest, exact in OCP E4M3) on FP8
+# MFMA with FP32 accumulation.
+
+@pytest.mark.parametrize("S", [1, 2, 3, 6, 9, 12])
+@pytest.mark.parametrize("kind", ["uniform", "loguniform"])
+def test_fp8_bit_exact_against_emulation(S, kind):
+    m, n, k = 300, 280, 260
+    A, B, C = workloads.gemm_operands(m, n, k, kind=kind)
+    want = se.split_gemm(A, B, S, "fp8", C, 1.0, 1.0)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, S, kind="fp8"), want)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (129, 7, 65), (17, 200, 3), (520, 130, 1000), (256, 128, 128)])
+@pytest.mark.parametrize("member", ["AUTO", "C0"])
+def test_fp8_ragged_shapes_bit_exact(shape, member):
+    m, n, k = shape
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = se.split_gemm(A, B, 7, "fp8", C, -1.5, 0.25)
+    np.testing.assert_array_equal(run(A, B, C, -1.5, 0.25, 7, member, kind="fp8"), want)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, True), (True, False), (True, True)])
+def test_fp8_transposed_operands_bit_exact(ta, tb):
+    m, n, k = 200, 330, 190
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = se.split_gemm(A, B, 5, "fp8", C, 1.0, 1.0)
+    got = run(A.T.copy() if ta else A, B.T.copy() if tb else B, C, 1.0, 1.0, 5, ta=ta, tb=tb, kind="fp8")
+    np.testing.assert_array_equal(got, want)
+
+
+def test_fp8_small_integers_exact_and_zero_lines():
+    # entries in [-15, 15] with a 16 in every row of A and every column of B:
+    # 2^e = 32, so the first slice holds half of each value rounded to even
+    # and the second slice the rest exactly; with three slices the diagonal
+    # s + t = 2 adds the product of the second slices, giving the integer
+    # product (two slices would drop it).
+    m, n, k = 160, 144, 300
+    rng = np.random.Generator(np.random.PCG64(11))
+    A = rng.integers(-15, 16, (m, k)).astype(np.float64)
+    B = rng.integers(-15, 16, (k, n)).astype(np.float64)
+    A[:, 0] = 16.0
+    B[0, :] = 16.0
+    C = rng.integers(-100, 101, (m, n)).astype(np.float64)
+    want = (A.astype(np.int64) @ B.astype(np.int64) + C.astype(np.int64)).astype(np.float64)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, 3, kind="fp8"), want)
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform")
+    A[5] = 0.0
+    B[:, 7] = 0.0
+    got = run(A, B, np.full((m, n), np.nan), 1.0, 0.0, 4, kind="fp8")
+    np.testing.assert_array_equal(got, se.split_gemm(A, B, 4, "fp8"))
+    assert (got[5] == 0).all() and (got[:, 7] == 0).all()
+
+
+def test_fp8_error_against_fp64_oracle():
+    m, n, k = 192, 160, 512
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = oracle.gemm(A, B)
+    absab = np.abs(A) @ np.abs(B)
+    # 12 FP8 slices carry 59 bits
+    assert np.max(np.abs(run(A, B, None, 1.0, 0.0, 12, kind="fp8") - want) / absab) <= 1e-13
+    e = se.exponents(A, 1)
+    f = se.exponents(B, 0)
+    for S in (3, 6, 9, 12):
+        got = run(A, B, None, 1.0, 0.0, S, kind="fp8")
+        tau = 2.0 ** -(5 * S)
+        bound = (S + 2) * 1.01 * tau * k * np.ldexp(1.0, e[:, None] + f[None, :]) + (S + 2) * 2.0 ** -53 * absab
+        assert np.all(np.abs(got - want) <= bound), S
+
+
+def test_fp8_sampled_8192_at_the_exactness_limit():
+    # m = n = k = 8192, signed log-uniform over [1e-8, 1e8], eight FP8 slices:
+    # 8 * 8192 = 2^16 products per diagonal, the largest exact FP32 sum.
+    m = n = k = 8192
+    S = 8
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform", with_c=False)
+    got = run(A, B, None, 1.0, 0.0, S, kind="fp8")
+    rng = np.random.Generator(np.random.PCG64(5))
+    rows = np.concatenate([rng.integers(0, m, 300), [0, m - 1, 255, 256]])
+    cols = np.concatenate([rng.integers(0, n, 300), [n - 1, 0, 128, 127]])
+    emu = se.split_gemm_entries(A, B, rows, cols, S, "fp8")
+    np.testing.assert_array_equal(got[rows, cols], emu)
+    exact = oracle.gemm_entries(A, B, rows, cols)
+    e = se.exponents(A, 1)[rows]
+    f = se.exponents(B, 0)[cols]
+    absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
+    bound = (S + 2) * 1.01 * 2.0 ** -(5 * S) * k * np.ldexp(1.0, e + f) + (S + 2) * 2.0 ** -53 * absab
+    assert np.all(np.abs(got[rows, cols] - exact) <= bound)
