@@ -4,7 +4,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The GPU library never calls it and the
 two share no code: the oracle is a plain compensated triple loop in C
 (``gemm_dot2.c``), a numpy step-by-step emulation of the split-precision
-product (``split_emul.py``) and a brute-force transfer counter for blocked loop
+product (``split_emul.py``), the exact-integer definition of the modular split
+product (``crt_emul.py``) and a brute-force transfer counter for blocked loop
 nests (``cache_sim.py``).
 
 Functions here marshal numpy arrays into the C oracle.  ``build()`` compiles it
