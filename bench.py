@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
-LOWP_MFMA_PEAK_TOPS = {"bf16": 2500.0, "fp8": 5000.0, "int8": 5000.0}   # dense, per the MI355X specification
+LOWP_MFMA_PEAK_TOPS = {"bf16": 2500.0, "fp8": 5000.0, "int8": 5000.0, "crt": 5000.0}   # dense, per the MI355X specification
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_f64_8192.json")
 TILED_MEMBERS = ["C0", "C3C0", "B3C0", "A3C0", "A2C0"]
 
@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--only", default="all",
                     choices=["all", "fp64", "split", "batch", "backward", "members", "tiled", "syrk"])
-    ap.add_argument("--split", default="int8:8,int8:9,bf16:3,bf16:4,bf16:5,bf16:6,bf16:7,fp8:3,fp8:4,fp8:5,fp8:6,fp8:7,fp8:8",
+    ap.add_argument("--split", default="crt:14,crt:15,crt:16,int8:8,int8:9,bf16:3,bf16:4,bf16:5,bf16:6,bf16:7,"
+                    "fp8:3,fp8:4,fp8:5,fp8:6,fp8:7,fp8:8",
                     help="split-precision configurations to time, as type:slices[,type:slices...]")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
@@ -271,7 +272,7 @@ def bench_split(args, fp64_ms=None):
         ms = timed(lambda: mm.gemm_split(Ad, Bd, C, slices=S, slice_type=t, workspace=ws))
         got = C.cpu().numpy()[rows, cols]
         rel = np.abs(got - exact) / absab
-        pairs = S * (S + 1) // 2
+        pairs = S if t == "crt" else S * (S + 1) // 2   # INT8 products: one per modulus, or the slice pairs
         lowp = pairs * 2.0 * m * n * k / (ms * 1e-3) / 1e12
         runs.append({"slice_type": t, "slices": S, "ms": round(ms, 3),
                      "speedup_vs_fp64": round(fp64_ms / ms, 3),

@@ -222,18 +222,38 @@ int momms_balanced_block(double M, double beta_b, double beta_c, double *mc, dou
  * MFMA with FP32 accumulation, exact over a whole diagonal while slices * k
  * (k rounded up to 128) <= 2^16; larger k returns MOMMS_ERR_INFEASIBLE.  Its
  * error bound is the BF16 one with 2^-(5 slices) for 2^-(9 slices).
+ * MOMMS_SLICE_INT8_CRT is the modular form (Ozaki, Uchino & Imamura,
+ * "Ozaki scheme II", 2025); `slices` is then the number N of moduli, the N
+ * largest pairwise coprime integers <= 256 (256, 255, 253, 251, 247, ...),
+ * with product M.  With t the largest integer <= 60 such that 2 k 4^t < M
+ * (MOMMS_ERR_INFEASIBLE if t < 1, or if k rounded up to 128 exceeds 2^17),
+ * op(A) and op(B) are rounded to integers A'_ip = rint(A_ip 2^(t-e_i)),
+ * B'_pj = rint(B_pj 2^(t-f_j)); the N products of their residues run on
+ * INT8 MFMA and the Chinese remainder theorem recovers X = A'B' exactly, so
+ *   C := fl(fl(alpha * RN(X_ij) 2^(e_i+f_j-2t)) + fl(beta * C_ij)),
+ * bit-reproducible.  Error against the exact product:
+ *   <= 2^(e_i-t-1) sum_p |op(B)_pj| + 2^(f_j-t-1) sum_p |op(A)_ip|
+ *      + k 2^(e_i+f_j-2t-2) + u |C_ij|.
+ * At k = 8192, 14 moduli give t = 48, 15 give t = 51, 16 give t = 55.
  * Argument numbers: 1 transA, 2 transB, 3 m, 4 n, 5 k, 6 alpha, 7 A, 8 lda,
  * 9 B, 10 ldb, 11 beta, 12 C, 13 ldc, 14 slices (1..8 BF16, 1..10 INT8,
- * 1..12 FP8), 15 slice_type (MOMMS_SLICE_BF16, MOMMS_SLICE_FP8 or
- * MOMMS_SLICE_INT8), 16 family_member (MOMMS_AUTO, MOMMS_C0 or
+ * 1..12 FP8, 1..16 moduli), 15 slice_type (MOMMS_SLICE_BF16, MOMMS_SLICE_FP8,
+ * MOMMS_SLICE_INT8 or MOMMS_SLICE_INT8_CRT), 16 family_member (MOMMS_AUTO, MOMMS_C0 or
  * MOMMS_C3C0: tile order of the slice products), 17 workspace (device,
  * 256-byte aligned), 18 ws_bytes (>= momms_split_workspace_size), 19 stream.
- * The workspace holds the exponents, the slices and the FP64 partial sums;
- * it must not be used concurrently by another call.
+ * The workspace holds the exponents, the slices (or residues) and the FP64
+ * partial sums (or the residues of the products); it must not be used
+ * concurrently by another call.
  */
-enum momms_slice_type { MOMMS_SLICE_BF16 = 0, MOMMS_SLICE_FP8 = 1, MOMMS_SLICE_INT8 = 2 };
+enum momms_slice_type { MOMMS_SLICE_BF16 = 0, MOMMS_SLICE_FP8 = 1, MOMMS_SLICE_INT8 = 2, MOMMS_SLICE_INT8_CRT = 3 };
 
 size_t momms_split_workspace_size(int64_t m, int64_t n, int64_t k, int slices, int slice_type);
+
+/* Modular form: the bit count t used for inner dimension k with `moduli`
+ * moduli (MOMMS_SLICE_INT8_CRT above), or MOMMS_ERR_INFEASIBLE when t < 1;
+ * if moduli_out is non-NULL it receives the moduli (host memory, `moduli`
+ * ints).  Host-only.  Errors: -1 k < 0, -2 moduli outside 1..16. */
+int momms_crt_bits(int64_t k, int moduli, int *moduli_out);
 
 int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k,
                      double alpha, const double *A, int64_t lda,

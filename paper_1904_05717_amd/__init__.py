@@ -5,6 +5,8 @@ it checks tensor dtype/device/layout, reads leading dimensions and the
 current HIP stream, and passes device pointers through.  Every arithmetic
 step runs in the library's HIP kernels; there is no CPU fallback.
 """
+import ctypes
+
 import torch
 
 from . import _lib
@@ -117,7 +119,19 @@ def select_member(m, n, k):
     return MEMBER_NAMES[_lib.momms_select_member(m, n, k)]
 
 
-SLICE_TYPES = {"bf16": 0, "fp8": 1, "int8": 2}
+SLICE_TYPES = {"bf16": 0, "fp8": 1, "int8": 2, "crt": 3}
+ERR_INFEASIBLE = 1002   # MOMMS_ERR_INFEASIBLE
+
+
+def crt_bits(k, moduli):
+    """(t, moduli list) of the modular split product at inner dimension k, or
+    (None, moduli) when `moduli` moduli are too few for k."""
+    out = (ctypes.c_int32 * 16)()
+    t = int(_lib.momms_crt_bits(int(k), int(moduli), out))
+    if t == ERR_INFEASIBLE:
+        return None, [int(out[i]) for i in range(int(moduli))]
+    check_status(min(t, 0), "momms_crt_bits")
+    return t, [int(out[i]) for i in range(int(moduli))]
 
 
 def split_workspace_size(m, n, k, slices, slice_type="bf16"):
@@ -126,7 +140,9 @@ def split_workspace_size(m, n, k, slices, slice_type="bf16"):
 
 def gemm_split(A, B, C=None, alpha=1.0, beta=0.0, slices=7, slice_type="bf16", member="AUTO", transA=False,
                transB=False, workspace=None, stream=None):
-    """FP64-accurate C := alpha op(A) op(B) + beta C from BF16 or INT8 slice products.
+    """FP64-accurate C := alpha op(A) op(B) + beta C from BF16, FP8 or INT8
+    slice products, or (slice_type "crt") from INT8 products of residues
+    modulo `slices` moduli.
 
     Same conventions as gemm().  `workspace` (uint8 device tensor of at
     least split_workspace_size bytes) is allocated through torch when None.

@@ -62,6 +62,7 @@ momms_model_bytes = _fn("momms_model_bytes", i32, [i32, i64, i64, i64, dbl, i32,
 momms_select_member = _fn("momms_select_member", i32, [i64, i64, i64])
 momms_status_string = _fn("momms_status_string", ctypes.c_char_p, [i32])
 momms_split_workspace_size = _fn("momms_split_workspace_size", sz, [i64, i64, i64, i32, i32])
+momms_crt_bits = _fn("momms_crt_bits", i32, [i64, i32, ctypes.POINTER(i32)])
 momms_gemm_split = _fn("momms_gemm_split", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64,
                                                  i32, i32, i32, vp, sz, vp])
 
@@ -94,7 +95,7 @@ EXPORTS = [
     "momms_select_member", "momms_status_string", "momms_split_workspace_size", "momms_gemm_split",
     "momms_batch_create", "momms_batch_run", "momms_batch_info", "momms_batch_destroy", "momms_batch_select_tile",
     "momms_model_resident", "momms_balanced_block", "momms_set_member_table", "momms_select_member_prior",
-    "momms_tiled_size", "momms_to_tiled", "momms_from_tiled", "momms_gemm_tiled", "momms_syrk",
+    "momms_tiled_size", "momms_to_tiled", "momms_from_tiled", "momms_gemm_tiled", "momms_syrk", "momms_crt_bits",
 ]
 
 

@@ -19,6 +19,15 @@
 //                      C = fl(fl(alpha * V 2^(e_i + f_j)) + fl(beta * C)).
 // Steps s1-s3 are exact and s4 has a fixed order, so the result is
 // reproducible bit for bit.
+//
+// INT8 and FP8 E4M3 slices run the same four steps on byte MFMAs (7-bit
+// truncated and 4/5-bit rounded slices).  The modular form (Ozaki, Uchino &
+// Imamura, "Ozaki scheme II", 2025) replaces s2-s4: the operands are rounded
+// to t-bit integers A', B' (per row / column scale 2^(t - e)), each is reduced
+// modulo N pairwise coprime moduli p_l <= 256 into int8 residues, one INT8
+// product per modulus gives A'B' mod p_l, and the Chinese remainder theorem in
+// 128-bit integers recovers X = A'B' exactly (t is chosen so that
+// 2 k 4^t < M = prod p_l); X is rounded once to FP64 and scaled back.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -36,7 +45,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef int i8v __attribute__((ext_vector_type(8)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kB0 = 8;       // bits of the first BF16 slice
 constexpr int kB = 9;        // bits of every further slice
@@ -58,6 +66,21 @@ constexpr int kMaxSlicesBf16 = 8, kMaxSlicesI8 = 10;
 // E4M3); products reach 2^8, so FP32 sums are exact while slices * k_p <= 2^16.
 constexpr int kF8B0 = 4, kF8B = 5, kMaxSlicesF8 = 12;
 constexpr int64_t kF8MaxProducts = (int64_t)1 << 16;
+// Modular form: at most 16 moduli (M < 2^126) and t <= 60 bits.
+constexpr int kMaxModuli = 16, kMaxCrtBits = 60;
+
+typedef unsigned __int128 u128;
+
+// Everything the three modular kernels need, passed by value.
+struct CrtParams {
+    int n, t;
+    int p[kMaxModuli];
+    double pd[kMaxModuli], invp[kMaxModuli];
+    uint64_t w_lo[kMaxModuli], w_hi[kMaxModuli];   // CRT weights W_l = (M/p_l) ((M/p_l)^-1 mod p_l) < M
+    double wd[kMaxModuli];                         // RN(W_l)
+    uint64_t m_lo, m_hi;                           // M
+    double inv_m;                                  // RN(1 / RN(M))
+};
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
@@ -212,6 +235,128 @@ __global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int
             uint4* dst = reinterpret_cast<uint4*>(static_cast<uint16_t*>(outv) + o + s_ * slice);
             dst[0] = make_uint4(word[0], word[1], word[2], word[3]);
             dst[1] = make_uint4(word[4], word[5], word[6], word[7]);
+        }
+    }
+}
+
+// Modular form, operand side: X(r, c) as in k_slice, x = rint(X 2^(t - e[r]))
+// (an exact integer, |x| <= 2^t), and for every modulus p_l the centred
+// residue x mod p_l in [-128, 127] (odd p_l: [-(p_l-1)/2, (p_l-1)/2]) as
+// int8, out[l][r][c] (pitch Cp, plane stride Rp*Cp), zero outside X.
+// q = rint(x / p) is off by a few units at most for |x| <= 2^60, and
+// x - q p is an exact small integer (one fma); a second pass on that
+// remainder gives the centred residue.
+template <bool TRANSPOSED>
+__global__ __launch_bounds__(256) void k_residues(const double* __restrict__ P, int64_t ld, int64_t R, int64_t Cc,
+                                                  const int* __restrict__ e, CrtParams cp,
+                                                  int8_t* __restrict__ out, int64_t Rp, int64_t Cp) {
+    __shared__ double tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int idx = tid + 256 * i;
+        int rr, cc;
+        if (TRANSPOSED) { cc = idx >> 6; rr = idx & 63; }
+        else            { rr = idx >> 6; cc = idx & 63; }
+        const int64_t gr = r0 + rr, gc = c0 + cc;
+        double v = 0.0;
+        if (gr < R && gc < Cc) v = TRANSPOSED ? P[gc * ld + gr] : P[gr * ld + gc];
+        tile[rr][cc] = v;
+    }
+    __syncthreads();
+    const int rr = tid >> 2, cb = (tid & 3) * 16;
+    const int64_t gr = r0 + rr;
+    if (gr >= Rp) return;
+    const int ee = gr < R ? exp_or_zero(e[gr]) : 0;
+    double x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = rint(ldexp(tile[rr][cb + j], cp.t - ee));
+    const int64_t plane = Rp * Cp;
+    const int64_t o = gr * Cp + c0 + cb;
+    for (int l = 0; l < cp.n; ++l) {
+        const double p = cp.pd[l], ip = cp.invp[l];
+        const double hi = (double)((cp.p[l] - 1) / 2), lo = -(double)(cp.p[l] / 2);
+        uint32_t word[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const double v = x[4 * q + b];
+                double r = fma(-rint(v * ip), p, v);
+                r = fma(-rint(r * ip), p, r);
+                if (r > hi) r -= p;
+                if (r < lo) r += p;
+                w |= (uint32_t)(uint8_t)(int8_t)(int)r << (8 * b);
+            }
+            word[q] = w;
+        }
+        *reinterpret_cast<uint4*>(out + o + l * plane) = make_uint4(word[0], word[1], word[2], word[3]);
+    }
+}
+
+// Modular form, reconstruction: for each (i, j) the residues X mod p_l of
+// the N INT8 products (uint8, plane stride `plane`, pitch ldr) give
+// S = sum_l r_l W_l = X (mod M).  S is formed modulo 2^128; a quotient
+// estimate q = floor(sum_l r_l RN(W_l) / M) is within one of floor(S / M),
+// so S - q M (modulo 2^128, read as signed) lies in [-M, 2M) and one
+// correction each way gives S mod M; values above M / 2 stand for X - M.
+// X (|X| < M / 2 < 2^125) is rounded once to FP64 (top 64 bits with a sticky
+// bit, then the exact u64 conversion), scaled by 2^(e_i + f_j - 2t), and
+// C = fl(fl(alpha T) + fl(beta C)).  Four columns per thread.
+__device__ __forceinline__ double i128_to_double_rn(__int128 x) {
+    const bool neg = x < 0;
+    const u128 u = neg ? (u128)0 - (u128)x : (u128)x;
+    const uint64_t hi = (uint64_t)(u >> 64), lo = (uint64_t)u;
+    double d;
+    if (hi == 0) {
+        d = (double)lo;
+    } else {
+        const int lz = __clzll(hi);
+        const u128 v = u << lz;
+        const uint64_t top = (uint64_t)(v >> 64) | ((uint64_t)v != 0 ? 1ull : 0ull);
+        d = ldexp((double)top, 64 - lz);
+    }
+    return neg ? -d : d;
+}
+
+__global__ __launch_bounds__(256) void k_crt_combine(int64_t M, int64_t N, const uint8_t* __restrict__ Rs,
+                                                     int64_t plane, int64_t ldr, const int* __restrict__ ea,
+                                                     const int* __restrict__ eb, CrtParams cp, double alpha,
+                                                     double beta, double* __restrict__ C, int64_t ldc) {
+    const int64_t nq = (N + 3) / 4;
+    const u128 Mm = ((u128)cp.m_hi << 64) | cp.m_lo;
+    const u128 half = Mm >> 1;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < M * nq;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g / nq, j0 = (g - i * nq) * 4;
+        u128 S[4] = {0, 0, 0, 0};
+        double Sd[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int l = 0; l < cp.n; ++l) {
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(Rs + l * plane + i * ldr + j0);
+            const u128 W = ((u128)cp.w_hi[l] << 64) | cp.w_lo[l];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t r = (w >> (8 * c)) & 0xffu;
+                S[c] += (u128)r * W;
+                Sd[c] = fma((double)r, cp.wd[l], Sd[c]);
+            }
+        }
+        const int ei = exp_or_zero(ea[i]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t j = j0 + c;
+            if (j >= N) break;
+            const uint64_t q = (uint64_t)floor(Sd[c] * cp.inv_m);
+            __int128 X = (__int128)(S[c] - (u128)q * Mm);
+            if (X < 0) X += (__int128)Mm;
+            if (X >= (__int128)Mm) X -= (__int128)Mm;
+            if ((u128)X > half) X -= (__int128)Mm;
+            const double T = ldexp(i128_to_double_rn(X), ei + exp_or_zero(eb[j]) - 2 * cp.t);
+            double o = __dmul_rn(alpha, T);
+            if (beta != 0.0) o = __dadd_rn(o, __dmul_rn(beta, C[i * ldc + j]));
+            C[i * ldc + j] = o;
         }
     }
 }
@@ -491,18 +636,31 @@ __device__ __forceinline__ i8v frag_f8(const int8_t* p, int win) {
 // the compiler would sink the prefetch past the barrier to its use.  F8: the
 // slices are FP8 E4M3 and the accumulators FP32 (exact: every partial sum is
 // an integer below 2^24).
-template <bool FIRST, bool LAST, bool F8>
+// CRT: the modular form; d = 0, blockIdx.y selects the modulus (SA, SB
+// advance by one plane each), and the epilogue stores acc mod p_l as uint8
+// into co.R (plane co.plane, pitch co.ldr) instead of the recombination.
+struct CrtOut {
+    uint8_t* R;
+    int64_t plane, ldr;
+    int p[kMaxModuli];
+};
+
+template <bool FIRST, bool LAST, bool F8, bool CRT>
 __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int64_t kp, int d,
                                                        const int8_t* SA, const int8_t* SB, int64_t sa_stride,
                                                        int64_t sb_stride, int shift, const int* __restrict__ ea,
                                                        const int* __restrict__ eb, double* __restrict__ V,
                                                        int64_t ldv, double alpha, double beta,
-                                                       double* __restrict__ C, int64_t ldc, Sched sc) {
+                                                       double* __restrict__ C, int64_t ldc, Sched sc, CrtOut co) {
     __shared__ __attribute__((aligned(16))) int8_t As[2 * i8::kStageA];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2 * i8::kStageB];
     int tm, tn;
     decode_tile(sc, blockIdx.x, tm, tn);
     const int64_t m0 = sc.m_off + (int64_t)tm * kI8MT, n0 = sc.n_off + (int64_t)tn * kI8NT;
+    if (CRT) {
+        SA += (int64_t)blockIdx.y * sa_stride;
+        SB += (int64_t)blockIdx.y * sb_stride;
+    }
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 2, wn = wave & 3;
     const int li = lane & 15, lk = lane >> 4;
@@ -543,6 +701,25 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
         for (int t = 0; t < total; ++t) MOMMS_I8_STEP(t, t & 1);
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the surplus prefetches
+
+    if constexpr (CRT) {
+        const int p = co.p[blockIdx.y];
+        uint8_t* R = co.R + (int64_t)blockIdx.y * co.plane;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + wm * 128 + i * 16 + 4 * lk + r;
+                    const int64_t col = n0 + wn * 64 + j * 16 + li;
+                    if (row >= M || col >= N) continue;
+                    int v = acc[i][j][r] % p;
+                    if (v < 0) v += p;
+                    R[row * co.ldr + col] = (uint8_t)v;
+                }
+        return;
+    }
 
 #pragma unroll
     for (int i = 0; i < 8; ++i)
@@ -590,7 +767,9 @@ struct Layout {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool bytes) {
+// crt: the modular form; the V region then holds the N residue planes of
+// the products, uint8 [N][m][np].
+static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool bytes, bool crt = false) {
     Layout L;
     const size_t esz = bytes ? sizeof(int8_t) : sizeof(uint16_t);
     L.mp = rup(m > 0 ? m : 1, bytes ? kI8MT : kMT);
@@ -601,17 +780,70 @@ static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool bytes) {
     L.off_eb = o; o = align256(o + sizeof(int) * (size_t)n);
     L.off_sa = o; o = align256(o + esz * (size_t)S * L.mp * L.kp);
     L.off_sb = o; o = align256(o + esz * (size_t)S * L.np * L.kp);
-    L.off_v = o;  o = align256(o + (S > 1 ? sizeof(double) * (size_t)m * n : 0));
+    L.off_v = o;
+    o = align256(o + (crt ? (size_t)S * m * L.np : S > 1 ? sizeof(double) * (size_t)m * n : 0));
     L.total = o;
     return L;
+}
+
+static int gcd_int(int a, int b) {
+    while (b != 0) {
+        const int r = a % b;
+        a = b;
+        b = r;
+    }
+    return a;
+}
+
+// The N largest pairwise coprime integers in [2, 256], greedily from 256
+// down; M = their product; t = the largest integer <= 60 with 2 k 4^t < M
+// (0 when not even t = 1 fits); the CRT weights.  Host only.
+static int crt_params(int N, int64_t k, CrtParams* cp) {
+    *cp = CrtParams{};
+    cp->n = N;
+    int got = 0;
+    for (int p = 256; p >= 2 && got < N; --p) {
+        bool ok = true;
+        for (int q = 0; q < got; ++q) ok = ok && gcd_int(p, cp->p[q]) == 1;
+        if (ok) cp->p[got++] = p;
+    }
+    if (got < N) return -1;
+    u128 Mm = 1;
+    for (int l = 0; l < N; ++l) Mm *= (u128)cp->p[l];
+    const u128 kk2 = 2 * (u128)(k > 0 ? k : 1);
+    int t = 0;
+    for (int c = 1; c <= kMaxCrtBits; ++c)
+        if (kk2 <= ((Mm - 1) >> (2 * c))) t = c;   // 2k 4^c <= M - 1
+    cp->t = t;
+    for (int l = 0; l < N; ++l) {
+        const int p = cp->p[l];
+        const u128 Ml = Mm / (u128)p;
+        const int a = (int)(Ml % (u128)p);
+        int inv = 0;
+        for (int x = 1; x < p; ++x)
+            if ((a * x) % p == 1) {
+                inv = x;
+                break;
+            }
+        const u128 W = Ml * (u128)inv;   // < M because inv < p
+        cp->pd[l] = (double)p;
+        cp->invp[l] = 1.0 / (double)p;
+        cp->w_lo[l] = (uint64_t)W;
+        cp->w_hi[l] = (uint64_t)(W >> 64);
+        cp->wd[l] = (double)W;
+    }
+    cp->m_lo = (uint64_t)Mm;
+    cp->m_hi = (uint64_t)(Mm >> 64);
+    cp->inv_m = 1.0 / (double)Mm;
+    return 0;
 }
 
 template <bool F, bool L, bool F8>
 static void launch_i8_diag(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t kp, int d, const int8_t* SA,
                            const int8_t* SB, int64_t sas, int64_t sbs, int shift, const int* ea, const int* eb,
                            double* V, int64_t ldv, double alpha, double beta, double* C, int64_t ldc, Sched s) {
-    hipLaunchKernelGGL((k_split_i8_diag<F, L, F8>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs, shift, ea,
-                       eb, V, ldv, alpha, beta, C, ldc, s);
+    hipLaunchKernelGGL((k_split_i8_diag<F, L, F8, false>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs,
+                       shift, ea, eb, V, ldv, alpha, beta, C, ldc, s, CrtOut{});
 }
 
 template <bool F, bool L>
@@ -630,12 +862,24 @@ extern "C" {
 size_t momms_split_workspace_size(int64_t m, int64_t n, int64_t k, int slices, int slice_type) {
     using namespace momms::split;
     if (m < 0 || n < 0 || k < 0 || slices < 1) return 0;
-    const int max_slices = slice_type == MOMMS_SLICE_BF16 ? kMaxSlicesBf16
-                           : slice_type == MOMMS_SLICE_INT8 ? kMaxSlicesI8
-                           : slice_type == MOMMS_SLICE_FP8  ? kMaxSlicesF8
-                                                            : 0;
+    const int max_slices = slice_type == MOMMS_SLICE_BF16     ? kMaxSlicesBf16
+                           : slice_type == MOMMS_SLICE_INT8     ? kMaxSlicesI8
+                           : slice_type == MOMMS_SLICE_FP8      ? kMaxSlicesF8
+                           : slice_type == MOMMS_SLICE_INT8_CRT ? kMaxModuli
+                                                                : 0;
     if (slices > max_slices) return 0;
-    return layout(m, n, k, slices, slice_type != MOMMS_SLICE_BF16).total;
+    return layout(m, n, k, slices, slice_type != MOMMS_SLICE_BF16, slice_type == MOMMS_SLICE_INT8_CRT).total;
+}
+
+int momms_crt_bits(int64_t k, int moduli, int* moduli_out) {
+    using namespace momms::split;
+    if (k < 0) return -1;
+    if (moduli < 1 || moduli > kMaxModuli) return -2;
+    CrtParams cp;
+    if (crt_params(moduli, k, &cp) != 0) return MOMMS_ERR_INTERNAL;
+    if (moduli_out != nullptr)
+        for (int l = 0; l < moduli; ++l) moduli_out[l] = cp.p[l];
+    return cp.t >= 1 ? cp.t : MOMMS_ERR_INFEASIBLE;
 }
 
 int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
@@ -655,20 +899,26 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     if (ldb < (tb ? (k > 1 ? k : 1) : (n > 1 ? n : 1))) return -10;
     if (m > 0 && n > 0 && C == nullptr) return -12;
     if (ldc < (n > 1 ? n : 1)) return -13;
-    if (slice_type != MOMMS_SLICE_BF16 && slice_type != MOMMS_SLICE_INT8 && slice_type != MOMMS_SLICE_FP8)
+    if (slice_type != MOMMS_SLICE_BF16 && slice_type != MOMMS_SLICE_INT8 && slice_type != MOMMS_SLICE_FP8 &&
+        slice_type != MOMMS_SLICE_INT8_CRT)
         return -15;
     const bool f8 = slice_type == MOMMS_SLICE_FP8;
-    const bool bytes = slice_type != MOMMS_SLICE_BF16;   // INT8 and FP8 share the byte layout and kernel
-    const int max_slices = f8 ? kMaxSlicesF8 : bytes ? kMaxSlicesI8 : kMaxSlicesBf16;
+    const bool crt = slice_type == MOMMS_SLICE_INT8_CRT;
+    const bool bytes = slice_type != MOMMS_SLICE_BF16;   // INT8, FP8 and the moduli share the byte layout
+    const int max_slices = crt ? kMaxModuli : f8 ? kMaxSlicesF8 : bytes ? kMaxSlicesI8 : kMaxSlicesBf16;
     if (slices < 1 || slices > max_slices) return -14;
     if (family_member != MOMMS_AUTO && family_member != MOMMS_C0 && family_member != MOMMS_C3C0) return -16;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return -17;
-    const Layout L = layout(m, n, k, slices, bytes);
+    const Layout L = layout(m, n, k, slices, bytes, crt);
     // Every diagonal's sum must stay exact: INT8 in INT32 (slices * kp <=
     // 2^17, products up to 127^2), FP8 in FP32 (slices * kp <= 2^16, products
-    // up to 16^2, sums below 2^24).
-    if (bytes && reads_ab && (int64_t)slices * L.kp > (f8 ? kF8MaxProducts : kI8MaxProducts))
-        return MOMMS_ERR_INFEASIBLE;
+    // up to 16^2, sums below 2^24).  Moduli: one product each, residues up to
+    // 128 in magnitude: kp <= 2^17 (a sum of 2^17 products (-128)^2 wraps in
+    // INT32, which only p = 256 can see, and 256 divides 2^32).
+    const int64_t exact_limit = f8 ? kF8MaxProducts : kI8MaxProducts;
+    if (bytes && reads_ab && (crt ? L.kp : (int64_t)slices * L.kp) > exact_limit) return MOMMS_ERR_INFEASIBLE;
+    CrtParams cp{};
+    if (crt && reads_ab && (crt_params(slices, k, &cp) != 0 || cp.t < 1)) return MOMMS_ERR_INFEASIBLE;
     if (reads_ab && (workspace == nullptr || ws_bytes < L.total)) return -18;
     if (cdiv(m, kMT) * cdiv(n, kMT) >= (int64_t)INT_MAX / 2) return MOMMS_ERR_INFEASIBLE;
 
@@ -716,9 +966,20 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
         if (!tb) hipLaunchKernelGGL((k_slice<true, KIND_>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp);  \
         else     hipLaunchKernelGGL((k_slice<false, KIND_>), gb, dim3(256), 0, st, B, ldb, n, k, eb, slices, SB, L.np, L.kp); \
     } while (0)
-        if (f8)         MOMMS_SLICE_LAUNCH(2);
-        else if (bytes) MOMMS_SLICE_LAUNCH(1);
-        else            MOMMS_SLICE_LAUNCH(0);
+        int8_t* ra = static_cast<int8_t*>(SA);
+        int8_t* rb = static_cast<int8_t*>(SB);
+        if (crt) {
+            if (!ta) hipLaunchKernelGGL((k_residues<false>), ga, dim3(256), 0, st, A, lda, m, k, ea, cp, ra, L.mp, L.kp);
+            else     hipLaunchKernelGGL((k_residues<true>), ga, dim3(256), 0, st, A, lda, m, k, ea, cp, ra, L.mp, L.kp);
+            if (!tb) hipLaunchKernelGGL((k_residues<true>), gb, dim3(256), 0, st, B, ldb, n, k, eb, cp, rb, L.np, L.kp);
+            else     hipLaunchKernelGGL((k_residues<false>), gb, dim3(256), 0, st, B, ldb, n, k, eb, cp, rb, L.np, L.kp);
+        } else if (f8) {
+            MOMMS_SLICE_LAUNCH(2);
+        } else if (bytes) {
+            MOMMS_SLICE_LAUNCH(1);
+        } else {
+            MOMMS_SLICE_LAUNCH(0);
+        }
 #undef MOMMS_SLICE_LAUNCH
     }
     // s3 + s4: one launch per diagonal, smallest first.
@@ -736,6 +997,25 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     s.xcd = grouped ? kXcds : 1;
     const dim3 grid((unsigned)(s.tiles_m * s.tiles_n));
     const int64_t sas = L.mp * L.kp, sbs = L.np * L.kp;
+    if (crt) {
+        // s3: one INT8 product per modulus (blockIdx.y), residues to R
+        CrtOut co{};
+        co.R = reinterpret_cast<uint8_t*>(ws + L.off_v);
+        co.plane = m * L.np;
+        co.ldr = L.np;
+        for (int l = 0; l < slices; ++l) co.p[l] = cp.p[l];
+        hipLaunchKernelGGL((k_split_i8_diag<true, true, false, true>), dim3(grid.x, (unsigned)slices), dim3(512), 0,
+                           st, m, n, L.kp, 0, static_cast<const int8_t*>(SA), static_cast<const int8_t*>(SB), sas,
+                           sbs, 0, ea, eb, nullptr, 0, alpha, beta, C, ldc, s, co);
+        // s4: Chinese remainder reconstruction, rounding and the C update
+        const int64_t items = m * ((n + 3) / 4);
+        int64_t blocks = cdiv(items, 256);
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)blocks), dim3(256), 0, st, m, n, co.R, co.plane, co.ldr, ea,
+                           eb, cp, alpha, beta, C, ldc);
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? 0 : (int)e;
+    }
     for (int d = slices - 1; d >= 0; --d) {
         const bool first = d == slices - 1, last = d == 0;
         if (bytes) {

@@ -171,3 +171,25 @@ def test_syrk_argument_errors():
     assert f(ord("L"), 0, 4, 4, 1.0, big, 4, 0.0, None, 4, 0, None) == -9
     assert f(ord("L"), 0, 4, 4, 1.0, big, 4, 0.0, big, 3, 0, None) == -10
     assert f(ord("L"), 0, 4, 4, 1.0, big, 4, 0.0, big, 4, mm.MEMBERS["A2C0"], None) == -11
+
+
+def test_crt_moduli_and_bits_match_the_definition():
+    # the library's host computation against the oracle's independent one
+    from oracle import crt_emul as ce
+    for N in range(1, 17):
+        for k in (1, 2, 31, 32, 260, 8192, 131072, 10 ** 6):
+            t, p = mm.crt_bits(k, N)
+            assert t == ce.bits(k, N) and p == ce.moduli(N), (N, k)
+    f = mm._lib.momms_crt_bits
+    assert f(-1, 4, None) == -1 and f(4, 0, None) == -2 and f(4, 17, None) == -2
+
+
+def test_crt_limits():
+    f = mm._lib.momms_gemm_split
+    big = 1 << 20
+    # k rounded up to 128 above 2^17: refused; too few moduli for k: refused
+    assert f(0, 0, 4, 4, 131073, 1.0, big, 131073, big, 4, 0.0, big, 4, 16, 3, 0, big, 1 << 40, None) == 1002
+    assert f(0, 0, 4, 4, 8192, 1.0, big, 8192, big, 4, 0.0, big, 4, 2, 3, 0, big, 1 << 40, None) == 1002
+    assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 17, 3, 0, big, 1 << 30, None) == -14
+    assert mm.split_workspace_size(4, 4, 4, 16, "crt") > 0
+    assert mm.split_workspace_size(4, 4, 4, 17, "crt") == 0

@@ -276,3 +276,81 @@ def test_fp8_sampled_8192_at_the_exactness_limit():
     absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
     bound = (S + 2) * 1.01 * 2.0 ** -(5 * S) * k * np.ldexp(1.0, e + f) + (S + 2) * 2.0 ** -53 * absab
     assert np.all(np.abs(got[rows, cols] - exact) <= bound)
+
+
+# Modular form: INT8 products of residues modulo N moduli, Chinese remainder
+# reconstruction; equal bit for bit to the exact-integer definition.
+from oracle import crt_emul as ce  # noqa: E402
+
+
+@pytest.mark.parametrize("N", [2, 5, 9, 14, 16])
+@pytest.mark.parametrize("kind", ["uniform", "loguniform"])
+def test_crt_bit_exact_against_definition(N, kind):
+    m, n, k = 300, 280, 260
+    A, B, C = workloads.gemm_operands(m, n, k, kind=kind)
+    want = ce.crt_gemm(A, B, N, C, 1.0, 1.0)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, N, kind="crt"), want)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (129, 7, 65), (17, 200, 3), (520, 130, 1000)])
+@pytest.mark.parametrize("member", ["AUTO", "C0"])
+def test_crt_ragged_shapes_bit_exact(shape, member):
+    m, n, k = shape
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = ce.crt_gemm(A, B, 15, C, -1.5, 0.25)
+    np.testing.assert_array_equal(run(A, B, C, -1.5, 0.25, 15, member, kind="crt"), want)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, True), (True, False), (True, True)])
+def test_crt_transposed_operands_bit_exact(ta, tb):
+    m, n, k = 200, 330, 190
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = ce.crt_gemm(A, B, 12, C, 1.0, 1.0)
+    got = run(A.T.copy() if ta else A, B.T.copy() if tb else B, C, 1.0, 1.0, 12, ta=ta, tb=tb, kind="crt")
+    np.testing.assert_array_equal(got, want)
+
+
+def test_crt_integers_exact_and_zero_lines():
+    m, n, k = 160, 144, 300
+    A, B, C = workloads.gemm_operands(m, n, k, kind="int")
+    want = (A.astype(np.int64) @ B.astype(np.int64) + C.astype(np.int64)).astype(np.float64)
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, 6, kind="crt"), want)
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform")
+    A[5] = 0.0
+    B[:, 7] = 0.0
+    got = run(A, B, np.full((m, n), np.nan), 1.0, 0.0, 14, kind="crt")
+    np.testing.assert_array_equal(got, ce.crt_gemm(A, B, 14))
+    assert (got[5] == 0).all() and (got[:, 7] == 0).all()
+
+
+def test_crt_error_against_fp64_oracle():
+    m, n, k = 192, 160, 512
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform")
+    want = oracle.gemm(A, B)
+    absab = np.abs(A) @ np.abs(B)
+    e = se.exponents(A, 1)
+    f = se.exponents(B, 0)
+    sa = np.abs(A).sum(axis=1)
+    sb = np.abs(B).sum(axis=0)
+    for N in (8, 12, 16):
+        t = ce.bits(k, N)
+        got = run(A, B, None, 1.0, 0.0, N, kind="crt")
+        bound = (np.ldexp(sb[None, :], e[:, None] - t - 1) + np.ldexp(sa[:, None], f[None, :] - t - 1)
+                 + k * np.ldexp(1.0, e[:, None] + f[None, :] - 2 * t - 2)) * 1.001 + 2.0 ** -52 * np.abs(want)
+        assert np.all(np.abs(got - want) <= bound), N
+    assert np.max(np.abs(got - want) / absab) <= 1e-13
+
+
+def test_crt_sampled_8192():
+    # m = n = k = 8192, signed log-uniform over [1e-8, 1e8], 15 moduli (t = 51)
+    m = n = k = 8192
+    N = 15
+    A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform", with_c=False)
+    got = run(A, B, None, 1.0, 0.0, N, kind="crt")
+    rng = np.random.Generator(np.random.PCG64(6))
+    rows = np.concatenate([rng.integers(0, m, 200), [0, m - 1, 255, 256]])
+    cols = np.concatenate([rng.integers(0, n, 200), [n - 1, 0, 128, 127]])
+    np.testing.assert_array_equal(got[rows, cols], ce.crt_gemm_entries(A, B, rows, cols, N))
+    exact = oracle.gemm_entries(A, B, rows, cols)
+    absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
+    assert np.max(np.abs(got[rows, cols] - exact) / absab) <= 1e-13
