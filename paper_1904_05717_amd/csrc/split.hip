@@ -68,18 +68,21 @@ constexpr int kF8B0 = 4, kF8B = 5, kMaxSlicesF8 = 12;
 constexpr int64_t kF8MaxProducts = (int64_t)1 << 16;
 // Modular form: at most 16 moduli (M < 2^126) and t <= 60 bits.
 constexpr int kMaxModuli = 16, kMaxCrtBits = 60;
+constexpr int kCrtLimbs = 5;   // 12-bit limbs of the t <= 60 bit integer operands
 
 typedef unsigned __int128 u128;
 
-// Everything the three modular kernels need, passed by value.
+// Everything the residue and reconstruction kernels need, passed by value.
 struct CrtParams {
     int n, t;
     int p[kMaxModuli];
     double pd[kMaxModuli], invp[kMaxModuli];
-    uint64_t w_lo[kMaxModuli], w_hi[kMaxModuli];   // CRT weights W_l = (M/p_l) ((M/p_l)^-1 mod p_l) < M
-    double wd[kMaxModuli];                         // RN(W_l)
-    uint64_t m_lo, m_hi;                           // M
-    double inv_m;                                  // RN(1 / RN(M))
+    float ipf[kMaxModuli], pf[kMaxModuli];                      // 1/p, p
+    float hif[kMaxModuli], lof[kMaxModuli];                     // (p - 1) / 2, -(p / 2): centred range
+    float climb[kMaxModuli][5];                                 // 2^(12 i) mod p
+    uint32_t w20[kMaxModuli][7];   // CRT weight W_l = (M/p_l) ((M/p_l)^-1 mod p_l) < M in 20-bit digits
+    float wf[kMaxModuli];          // W_l / M, rounded
+    uint64_t m_lo, m_hi;           // M
 };
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -242,52 +245,69 @@ __global__ __launch_bounds__(256) void k_slice(const double* __restrict__ P, int
 // Modular form, operand side: X(r, c) as in k_slice, x = rint(X 2^(t - e[r]))
 // (an exact integer, |x| <= 2^t), and for every modulus p_l the centred
 // residue x mod p_l in [-128, 127] (odd p_l: [-(p_l-1)/2, (p_l-1)/2]) as
-// int8, out[l][r][c] (pitch Cp, plane stride Rp*Cp), zero outside X.
-// q = rint(x / p) is off by a few units at most for |x| <= 2^60, and
-// x - q p is an exact small integer (one fma); a second pass on that
-// remainder gives the centred residue.
+// int8, out[l][r][c] (pitch Cp, a multiple of 128, plane stride Rp*Cp, Rp a
+// multiple of 32), zero outside X.
 template <bool TRANSPOSED>
 __global__ __launch_bounds__(256) void k_residues(const double* __restrict__ P, int64_t ld, int64_t R, int64_t Cc,
                                                   const int* __restrict__ e, CrtParams cp,
                                                   int8_t* __restrict__ out, int64_t Rp, int64_t Cp) {
-    __shared__ double tile[64][65];
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    // 32 x 128 tiles: each row of a plane gets whole 128-byte lines.
+    __shared__ double tile[32][129];
+    const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 128;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int idx = tid + 256 * i;
         int rr, cc;
-        if (TRANSPOSED) { cc = idx >> 6; rr = idx & 63; }
-        else            { rr = idx >> 6; cc = idx & 63; }
+        if (TRANSPOSED) { cc = idx >> 5; rr = idx & 31; }
+        else            { rr = idx >> 7; cc = idx & 127; }
         const int64_t gr = r0 + rr, gc = c0 + cc;
         double v = 0.0;
         if (gr < R && gc < Cc) v = TRANSPOSED ? P[gc * ld + gr] : P[gr * ld + gc];
         tile[rr][cc] = v;
     }
     __syncthreads();
-    const int rr = tid >> 2, cb = (tid & 3) * 16;
+    const int rr = tid >> 3, cb = (tid & 7) * 16;
     const int64_t gr = r0 + rr;
     if (gr >= Rp) return;
     const int ee = gr < R ? exp_or_zero(e[gr]) : 0;
-    double x[16];
+    // x = sum_i a_i 2^(12 i) with 12-bit limbs a_i of the sign of x
+    // (|a_i| <= 2^12), exact in FP32; then x = sum_i a_i c_il (mod p_l) with
+    // c_il = 2^(12 i) mod p_l < 256.  Every partial sum is an integer of
+    // magnitude below 2^22, so s and s - q p are exact FP32 integers for
+    // q = rint(RN(s RN(1/p))); q is the nearest integer to s / p or, within
+    // 0.003 of a tie, the next one, which one correction each way repairs.
+    float a[16][kCrtLimbs];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) x[j] = rint(ldexp(tile[rr][cb + j], cp.t - ee));
+    for (int j = 0; j < 16; ++j) {
+        double v = rint(ldexp(tile[rr][cb + j], cp.t - ee));
+#pragma unroll
+        for (int i = kCrtLimbs - 1; i >= 0; --i) {
+            const double hi = trunc(ldexp(v, -12 * i));   // exact: v is an integer below 2^60
+            a[j][i] = (float)hi;
+            v = fma(-hi, ldexp(1.0, 12 * i), v);
+        }
+    }
     const int64_t plane = Rp * Cp;
     const int64_t o = gr * Cp + c0 + cb;
     for (int l = 0; l < cp.n; ++l) {
-        const double p = cp.pd[l], ip = cp.invp[l];
-        const double hi = (double)((cp.p[l] - 1) / 2), lo = -(double)(cp.p[l] / 2);
+        const float pf = cp.pf[l], ipf = cp.ipf[l], hi = cp.hif[l], lo = cp.lof[l];
+        float c[kCrtLimbs];
+#pragma unroll
+        for (int i = 0; i < kCrtLimbs; ++i) c[i] = cp.climb[l][i];
         uint32_t word[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             uint32_t w = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const double v = x[4 * q + b];
-                double r = fma(-rint(v * ip), p, v);
-                r = fma(-rint(r * ip), p, r);
-                if (r > hi) r -= p;
-                if (r < lo) r += p;
+                const int j = 4 * q + b;
+                float sres = a[j][0];
+#pragma unroll
+                for (int i = 1; i < kCrtLimbs; ++i) sres = fmaf(a[j][i], c[i], sres);
+                float r = fmaf(-rintf(sres * ipf), pf, sres);   // within one unit of [-p/2, p/2]
+                if (r > hi) r -= pf;
+                if (r < lo) r += pf;
                 w |= (uint32_t)(uint8_t)(int8_t)(int)r << (8 * b);
             }
             word[q] = w;
@@ -296,15 +316,16 @@ __global__ __launch_bounds__(256) void k_residues(const double* __restrict__ P, 
     }
 }
 
-// Modular form, reconstruction: for each (i, j) the residues X mod p_l of
-// the N INT8 products (uint8, plane stride `plane`, pitch ldr) give
-// S = sum_l r_l W_l = X (mod M).  S is formed modulo 2^128; a quotient
-// estimate q = floor(sum_l r_l RN(W_l) / M) is within one of floor(S / M),
-// so S - q M (modulo 2^128, read as signed) lies in [-M, 2M) and one
-// correction each way gives S mod M; values above M / 2 stand for X - M.
-// X (|X| < M / 2 < 2^125) is rounded once to FP64 (top 64 bits with a sticky
-// bit, then the exact u64 conversion), scaled by 2^(e_i + f_j - 2t), and
-// C = fl(fl(alpha T) + fl(beta C)).  Four columns per thread.
+// Modular form, reconstruction: for each (i, j) the residues r_l = X mod p_l
+// of the N INT8 products (uint8 in [0, p_l), R[l][i / 4][j][i % 4]) give
+// S = sum_l r_l W_l = X (mod M).  S is summed exactly in seven 20-bit digit
+// columns with 24-bit multiplies (16 * 255 * (2^20 - 1) < 2^32) and
+// assembled modulo 2^128; q = floor(sum_l r_l RN(W_l / M)) is within one of
+// floor(S / M), so S - q M (modulo 2^128, read as signed) lies in [-M, 2M)
+// and one correction each way gives S mod M; values above M / 2 stand for
+// X - M.  X (|X| < M / 2 < 2^125) is rounded once to FP64 (top 64 bits with
+// a sticky bit, then the exact u64 conversion), scaled by 2^(e_i + f_j - 2t),
+// and C = fl(fl(alpha T) + fl(beta C)).  A thread takes 4 rows of a column.
 __device__ __forceinline__ double i128_to_double_rn(__int128 x) {
     const bool neg = x < 0;
     const u128 u = neg ? (u128)0 - (u128)x : (u128)x;
@@ -325,35 +346,44 @@ __global__ __launch_bounds__(256) void k_crt_combine(int64_t M, int64_t N, const
                                                      int64_t plane, int64_t ldr, const int* __restrict__ ea,
                                                      const int* __restrict__ eb, CrtParams cp, double alpha,
                                                      double beta, double* __restrict__ C, int64_t ldc) {
-    const int64_t nq = (N + 3) / 4;
+    const int64_t groups = (M + 3) / 4;
     const u128 Mm = ((u128)cp.m_hi << 64) | cp.m_lo;
     const u128 half = Mm >> 1;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < M * nq;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups * N;
          g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = g / nq, j0 = (g - i * nq) * 4;
-        u128 S[4] = {0, 0, 0, 0};
-        double Sd[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int l = 0; l < cp.n; ++l) {
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(Rs + l * plane + i * ldr + j0);
-            const u128 W = ((u128)cp.w_hi[l] << 64) | cp.w_lo[l];
+        const int64_t q4 = g / N, j = g - q4 * N;
+        uint32_t acc[4][7];
+        float sf[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const uint32_t r = (w >> (8 * c)) & 0xffu;
-                S[c] += (u128)r * W;
-                Sd[c] = fma((double)r, cp.wd[l], Sd[c]);
+        for (int r = 0; r < 4; ++r) {
+            sf[r] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) acc[r][c] = 0u;
+        }
+        for (int l = 0; l < cp.n; ++l) {
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(Rs + l * plane + (q4 * ldr + j) * 4);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t x = (w >> (8 * r)) & 0xffu;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) acc[r][c] += __umul24(x, cp.w20[l][c]);
+                sf[r] = fmaf((float)x, cp.wf[l], sf[r]);
             }
         }
-        const int ei = exp_or_zero(ea[i]);
+        const int ej = exp_or_zero(eb[j]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int64_t j = j0 + c;
-            if (j >= N) break;
-            const uint64_t q = (uint64_t)floor(Sd[c] * cp.inv_m);
-            __int128 X = (__int128)(S[c] - (u128)q * Mm);
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = 4 * q4 + r;
+            if (i >= M) break;
+            u128 S = 0;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) S += (u128)acc[r][c] << (20 * c);
+            const uint64_t q = (uint64_t)floorf(sf[r]);
+            __int128 X = (__int128)(S - (u128)q * Mm);
             if (X < 0) X += (__int128)Mm;
             if (X >= (__int128)Mm) X -= (__int128)Mm;
             if ((u128)X > half) X -= (__int128)Mm;
-            const double T = ldexp(i128_to_double_rn(X), ei + exp_or_zero(eb[j]) - 2 * cp.t);
+            const double T = ldexp(i128_to_double_rn(X), exp_or_zero(ea[i]) + ej - 2 * cp.t);
             double o = __dmul_rn(alpha, T);
             if (beta != 0.0) o = __dadd_rn(o, __dmul_rn(beta, C[i * ldc + j]));
             C[i * ldc + j] = o;
@@ -581,13 +611,14 @@ __device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^
 // read in step t - 1, before the previous barrier), issue the loads of step
 // t + 2 into the freed registers, run window 1, synchronise.  The stores
 // overlap window 1's MFMAs; each load has a whole step to land.
-#define MOMMS_I8_STEP(t_, buf_)                                                                  \
+#define MOMMS_I8_STEP(t_, buf_) MOMMS_I8_STEP_G(t_, buf_, MOMMS_I8_GLOAD)
+#define MOMMS_I8_STEP_G(t_, buf_, GLOAD_)                                                        \
     do {                                                                                         \
         MOMMS_I8_WINDOW(buf_, 0);                                                                \
         __builtin_amdgcn_sched_barrier(0);                                                       \
         if ((t_) + 1 < total) MOMMS_I8_LSTORE((buf_) ^ 1, g);                                    \
         __builtin_amdgcn_sched_barrier(0);                                                       \
-        MOMMS_I8_GLOAD(g, (t_) + 2 < last ? (t_) + 2 : last);                                    \
+        GLOAD_(g, (t_) + 2 < last ? (t_) + 2 : last);                                            \
         __builtin_amdgcn_sched_barrier(0);                                                       \
         MOMMS_I8_WINDOW(buf_, 1);                                                                \
         __syncthreads();                                                                         \
@@ -636,31 +667,18 @@ __device__ __forceinline__ i8v frag_f8(const int8_t* p, int win) {
 // the compiler would sink the prefetch past the barrier to its use.  F8: the
 // slices are FP8 E4M3 and the accumulators FP32 (exact: every partial sum is
 // an integer below 2^24).
-// CRT: the modular form; d = 0, blockIdx.y selects the modulus (SA, SB
-// advance by one plane each), and the epilogue stores acc mod p_l as uint8
-// into co.R (plane co.plane, pitch co.ldr) instead of the recombination.
-struct CrtOut {
-    uint8_t* R;
-    int64_t plane, ldr;
-    int p[kMaxModuli];
-};
-
-template <bool FIRST, bool LAST, bool F8, bool CRT>
+template <bool FIRST, bool LAST, bool F8>
 __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int64_t kp, int d,
                                                        const int8_t* SA, const int8_t* SB, int64_t sa_stride,
                                                        int64_t sb_stride, int shift, const int* __restrict__ ea,
                                                        const int* __restrict__ eb, double* __restrict__ V,
                                                        int64_t ldv, double alpha, double beta,
-                                                       double* __restrict__ C, int64_t ldc, Sched sc, CrtOut co) {
+                                                       double* __restrict__ C, int64_t ldc, Sched sc) {
     __shared__ __attribute__((aligned(16))) int8_t As[2 * i8::kStageA];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2 * i8::kStageB];
     int tm, tn;
     decode_tile(sc, blockIdx.x, tm, tn);
     const int64_t m0 = sc.m_off + (int64_t)tm * kI8MT, n0 = sc.n_off + (int64_t)tn * kI8NT;
-    if (CRT) {
-        SA += (int64_t)blockIdx.y * sa_stride;
-        SB += (int64_t)blockIdx.y * sb_stride;
-    }
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 2, wn = wave & 3;
     const int li = lane & 15, lk = lane >> 4;
@@ -702,24 +720,6 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the surplus prefetches
 
-    if constexpr (CRT) {
-        const int p = co.p[blockIdx.y];
-        uint8_t* R = co.R + (int64_t)blockIdx.y * co.plane;
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = m0 + wm * 128 + i * 16 + 4 * lk + r;
-                    const int64_t col = n0 + wn * 64 + j * 16 + li;
-                    if (row >= M || col >= N) continue;
-                    int v = acc[i][j][r] % p;
-                    if (v < 0) v += p;
-                    R[row * co.ldr + col] = (uint8_t)v;
-                }
-        return;
-    }
 
 #pragma unroll
     for (int i = 0; i < 8; ++i)
@@ -742,6 +742,115 @@ __global__ __launch_bounds__(512) void k_split_i8_diag(int64_t M, int64_t N, int
                 }
             }
 }
+// Modular form, s3: the N INT8 products of the residue planes as one
+// persistent launch.  Work items are (modulus l, C tile) in modulus-major
+// order; workgroup b takes items b, b + G, b + 2G, ... (G = gridDim.x, a
+// multiple of 8 no larger than the item count, so each workgroup's tiles map
+// to its own XCD in the grouped order).  The k-steps of a workgroup's items
+// form one sequence, so the two-step prefetch runs across item boundaries
+// and a tile's epilogue does not drain the pipeline.  Epilogue: acc mod p_l
+// (acc = hi 2^16 + lo, s = hi (2^16 mod p) + lo is exact in FP32, one FP32
+// quotient estimate, two corrections), four rows of one column per 32-bit
+// store into R[l][row / 4][col][row % 4] (pitch ldr columns).
+struct CrtOut {
+    uint8_t* R;
+    int64_t plane, ldr;   // bytes per modulus plane; columns per 4-row group
+    int p[kMaxModuli], c16[kMaxModuli];
+    float ipf[kMaxModuli];
+};
+
+#define MOMMS_CRT_GLOAD(R, t_)                                                                   \
+    do {                                                                                         \
+        const int it_ = (t_) / nks;                                                              \
+        const int s_ = (t_) - it_ * nks;                                                         \
+        const int j_ = (int)blockIdx.x + it_ * G;                                                \
+        const int l_ = j_ / tiles;                                                               \
+        int tm_, tn_;                                                                            \
+        decode_tile(sc, j_ - l_ * tiles, tm_, tn_);                                              \
+        int kq = s_ + ((tm_ + tn_) & 7) % nks;                                                   \
+        if (kq >= nks) kq -= nks;                                                                \
+        const int64_t kk = (int64_t)kq * kI8KS + gcol;                                           \
+        const int8_t* pa = SA + (int64_t)l_ * sa_stride + (sc.m_off + (int64_t)tm_ * kI8MT + grow) * kp + kk; \
+        const int8_t* pb = SB + (int64_t)l_ * sb_stride + (sc.n_off + (int64_t)tn_ * kI8NT + grow) * kp + kk; \
+        R##0 = *reinterpret_cast<const uint4*>(pa);                                              \
+        R##1 = *reinterpret_cast<const uint4*>(pa + 64 * kp);                                    \
+        R##2 = *reinterpret_cast<const uint4*>(pa + 128 * kp);                                   \
+        R##3 = *reinterpret_cast<const uint4*>(pa + 192 * kp);                                   \
+        R##4 = *reinterpret_cast<const uint4*>(pb);                                              \
+        R##5 = *reinterpret_cast<const uint4*>(pb + 64 * kp);                                    \
+        R##6 = *reinterpret_cast<const uint4*>(pb + 128 * kp);                                   \
+        R##7 = *reinterpret_cast<const uint4*>(pb + 192 * kp);                                   \
+    } while (0)
+
+__device__ __forceinline__ uint32_t residue_u8(int a, int p, int c16, float ipf) {
+    const int s = (a >> 16) * c16 + (a & 0xffff);   // = a (mod p), |s| < 2^24
+    int r = s - (int)floorf((float)s * ipf) * p;    // in [-p, 2p)
+    if (r < 0) r += p;
+    if (r >= p) r -= p;
+    return (uint32_t)r;
+}
+
+__global__ __launch_bounds__(512) void k_crt_gemm(int64_t M, int64_t N, int64_t kp, const int8_t* SA,
+                                                  const int8_t* SB, int64_t sa_stride, int64_t sb_stride, Sched sc,
+                                                  int tiles, int items, CrtOut co) {
+    __shared__ __attribute__((aligned(16))) int8_t As[2 * i8::kStageA];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2 * i8::kStageB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
+    const int li = lane & 15, lk = lane >> 4;
+    i4 acc[8][4];
+    const int grow = tid >> 3, gq = tid & 7, gcol = gq * 16;
+    const int sw = i8::lds_off(grow, gq & 3) + (gq >> 2) * i8::kWinA;
+    int fa_off[8], fb_off[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) fa_off[i] = i8::lds_off(wm * 128 + i * 16 + li, lk);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) fb_off[j] = i8::lds_off(wn * 64 + j * 16 + li, lk);
+
+    const int G = (int)gridDim.x;
+    const int nks = (int)(kp / kI8KS);
+    const int n_it = (items - (int)blockIdx.x + G - 1) / G;   // >= 1: G <= items
+    const int total = n_it * nks;
+    const int last = total - 1;
+    uint4 g0, g1, g2, g3, g4, g5, g6, g7;
+
+    MOMMS_CRT_GLOAD(g, 0);
+    MOMMS_I8_LSTORE(0, g);
+    MOMMS_CRT_GLOAD(g, 1 < last ? 1 : last);
+    __syncthreads();
+    int t = 0;
+    for (int it = 0; it < n_it; ++it) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = i4{0, 0, 0, 0};
+        for (int s = 0; s < nks; ++s, ++t) MOMMS_I8_STEP_G(t, t & 1, MOMMS_CRT_GLOAD);
+        const int jt = (int)blockIdx.x + it * G;
+        const int l = jt / tiles;
+        int tm, tn;
+        decode_tile(sc, jt - l * tiles, tm, tn);
+        const int64_t m0 = sc.m_off + (int64_t)tm * kI8MT, n0 = sc.n_off + (int64_t)tn * kI8NT;
+        const int p = co.p[l], c16 = co.c16[l];
+        const float ipf = co.ipf[l];
+        uint8_t* R = co.R + (int64_t)l * co.plane;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row0 = m0 + wm * 128 + i * 16 + 4 * lk;
+                const int64_t col = n0 + wn * 64 + j * 16 + li;
+                if (row0 >= M || col >= N) continue;
+                uint32_t w = 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w |= residue_u8(acc[i][j][r], p, c16, ipf) << (8 * r);
+                *reinterpret_cast<uint32_t*>(R + ((row0 >> 2) * co.ldr + col) * 4) = w;
+            }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the surplus prefetches
+}
+#undef MOMMS_CRT_GLOAD
+#undef MOMMS_I8_STEP_G
+
 #undef MOMMS_I8_GLOAD
 #undef MOMMS_I8_LSTORE
 #undef MOMMS_F8_HALF
@@ -768,7 +877,7 @@ struct Layout {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // crt: the modular form; the V region then holds the N residue planes of
-// the products, uint8 [N][m][np].
+// the products, uint8 [N][ceil(m/4)][np][4].
 static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool bytes, bool crt = false) {
     Layout L;
     const size_t esz = bytes ? sizeof(int8_t) : sizeof(uint16_t);
@@ -781,7 +890,7 @@ static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool bytes, bool cr
     L.off_sa = o; o = align256(o + esz * (size_t)S * L.mp * L.kp);
     L.off_sb = o; o = align256(o + esz * (size_t)S * L.np * L.kp);
     L.off_v = o;
-    o = align256(o + (crt ? (size_t)S * m * L.np : S > 1 ? sizeof(double) * (size_t)m * n : 0));
+    o = align256(o + (crt ? (size_t)S * (size_t)rup(m, 4) * L.np : S > 1 ? sizeof(double) * (size_t)m * n : 0));
     L.total = o;
     return L;
 }
@@ -828,13 +937,16 @@ static int crt_params(int N, int64_t k, CrtParams* cp) {
         const u128 W = Ml * (u128)inv;   // < M because inv < p
         cp->pd[l] = (double)p;
         cp->invp[l] = 1.0 / (double)p;
-        cp->w_lo[l] = (uint64_t)W;
-        cp->w_hi[l] = (uint64_t)(W >> 64);
-        cp->wd[l] = (double)W;
+        cp->ipf[l] = 1.0f / (float)p;
+        cp->pf[l] = (float)p;
+        cp->hif[l] = (float)((p - 1) / 2);
+        cp->lof[l] = -(float)(p / 2);
+        for (int i = 0; i < kCrtLimbs; ++i) cp->climb[l][i] = (float)(((u128)1 << (12 * i)) % (u128)p);
+        for (int c = 0; c < 7; ++c) cp->w20[l][c] = (uint32_t)(W >> (20 * c)) & 0xfffffu;
+        cp->wf[l] = (float)((double)W / (double)Mm);
     }
     cp->m_lo = (uint64_t)Mm;
     cp->m_hi = (uint64_t)(Mm >> 64);
-    cp->inv_m = 1.0 / (double)Mm;
     return 0;
 }
 
@@ -842,8 +954,8 @@ template <bool F, bool L, bool F8>
 static void launch_i8_diag(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t kp, int d, const int8_t* SA,
                            const int8_t* SB, int64_t sas, int64_t sbs, int shift, const int* ea, const int* eb,
                            double* V, int64_t ldv, double alpha, double beta, double* C, int64_t ldc, Sched s) {
-    hipLaunchKernelGGL((k_split_i8_diag<F, L, F8, false>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs,
-                       shift, ea, eb, V, ldv, alpha, beta, C, ldc, s, CrtOut{});
+    hipLaunchKernelGGL((k_split_i8_diag<F, L, F8>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs, shift, ea,
+                       eb, V, ldv, alpha, beta, C, ldc, s);
 }
 
 template <bool F, bool L>
@@ -969,10 +1081,12 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
         int8_t* ra = static_cast<int8_t*>(SA);
         int8_t* rb = static_cast<int8_t*>(SB);
         if (crt) {
-            if (!ta) hipLaunchKernelGGL((k_residues<false>), ga, dim3(256), 0, st, A, lda, m, k, ea, cp, ra, L.mp, L.kp);
-            else     hipLaunchKernelGGL((k_residues<true>), ga, dim3(256), 0, st, A, lda, m, k, ea, cp, ra, L.mp, L.kp);
-            if (!tb) hipLaunchKernelGGL((k_residues<true>), gb, dim3(256), 0, st, B, ldb, n, k, eb, cp, rb, L.np, L.kp);
-            else     hipLaunchKernelGGL((k_residues<false>), gb, dim3(256), 0, st, B, ldb, n, k, eb, cp, rb, L.np, L.kp);
+            const dim3 ra_g((unsigned)(L.kp / 128), (unsigned)(L.mp / 32));
+            const dim3 rb_g((unsigned)(L.kp / 128), (unsigned)(L.np / 32));
+            if (!ta) hipLaunchKernelGGL((k_residues<false>), ra_g, dim3(256), 0, st, A, lda, m, k, ea, cp, ra, L.mp, L.kp);
+            else     hipLaunchKernelGGL((k_residues<true>), ra_g, dim3(256), 0, st, A, lda, m, k, ea, cp, ra, L.mp, L.kp);
+            if (!tb) hipLaunchKernelGGL((k_residues<true>), rb_g, dim3(256), 0, st, B, ldb, n, k, eb, cp, rb, L.np, L.kp);
+            else     hipLaunchKernelGGL((k_residues<false>), rb_g, dim3(256), 0, st, B, ldb, n, k, eb, cp, rb, L.np, L.kp);
         } else if (f8) {
             MOMMS_SLICE_LAUNCH(2);
         } else if (bytes) {
@@ -998,18 +1112,29 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     const dim3 grid((unsigned)(s.tiles_m * s.tiles_n));
     const int64_t sas = L.mp * L.kp, sbs = L.np * L.kp;
     if (crt) {
-        // s3: one INT8 product per modulus (blockIdx.y), residues to R
+        // s3: one INT8 product per modulus, persistent over (modulus, tile) items
         CrtOut co{};
         co.R = reinterpret_cast<uint8_t*>(ws + L.off_v);
-        co.plane = m * L.np;
         co.ldr = L.np;
-        for (int l = 0; l < slices; ++l) co.p[l] = cp.p[l];
-        hipLaunchKernelGGL((k_split_i8_diag<true, true, false, true>), dim3(grid.x, (unsigned)slices), dim3(512), 0,
-                           st, m, n, L.kp, 0, static_cast<const int8_t*>(SA), static_cast<const int8_t*>(SB), sas,
-                           sbs, 0, ea, eb, nullptr, 0, alpha, beta, C, ldc, s, co);
+        co.plane = rup(m, 4) * L.np;
+        for (int l = 0; l < slices; ++l) {
+            co.p[l] = cp.p[l];
+            co.c16[l] = 65536 % cp.p[l];
+            co.ipf[l] = cp.ipf[l];
+        }
+        const int tiles = s.tiles_m * s.tiles_n;
+        const int items = tiles * slices;
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        int G = items < cus ? items : cus;
+        if (G >= kXcds) G -= G % kXcds;
+        hipLaunchKernelGGL(k_crt_gemm, dim3((unsigned)G), dim3(512), 0, st, m, n, L.kp,
+                           static_cast<const int8_t*>(SA), static_cast<const int8_t*>(SB), sas, sbs, s, tiles, items,
+                           co);
         // s4: Chinese remainder reconstruction, rounding and the C update
-        const int64_t items = m * ((n + 3) / 4);
-        int64_t blocks = cdiv(items, 256);
+        const int64_t work = cdiv(m, 4) * n;
+        int64_t blocks = cdiv(work, 256);
         if (blocks > 65536) blocks = 65536;
         hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)blocks), dim3(256), 0, st, m, n, co.R, co.plane, co.ldr, ea,
                            eb, cp, alpha, beta, C, ldc);
