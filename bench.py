@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--member", default="AUTO")
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--only", default="all",
-                    choices=["all", "fp64", "split", "batch", "backward", "members", "tiled", "syrk"])
+                    choices=["all", "fp64", "split", "batch", "backward", "members", "tiled", "syrk", "ooc"])
     ap.add_argument("--split", default="crt:14,crt:15,crt:16,int8:8,int8:9,bf16:3,bf16:4,bf16:5,bf16:6,bf16:7,"
                     "fp8:3,fp8:4,fp8:5,fp8:6,fp8:7,fp8:8",
                     help="split-precision configurations to time, as type:slices[,type:slices...]")
@@ -361,6 +361,64 @@ def bench_syrk(args):
             "time_ratio": round(t_syrk / t_gemm, 3)}
 
 
+def bench_ooc(args):
+    """Out-of-core product at m = n = k = 2 * size with A, B, C in pinned host
+    memory: Resident C blocks in device memory, A and B panels over PCIe.
+    Wall time around the whole call (copies in both directions included),
+    rate in 2mnk flops per second, the host traffic of the Resident C count
+    and the rate it moves at, and the plain pinned host-to-device copy rate
+    for context."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    m = n = k = 2 * args.size
+    A, B, C = workloads.gemm_operands(m, n, k)
+    Ah, Bh = torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory()
+    C0 = torch.from_numpy(C).pin_memory()
+    del A, B, C
+    Ch = torch.empty_like(C0).pin_memory()
+    probe = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0")
+    src = torch.empty(1 << 28, dtype=torch.float64).pin_memory()
+    probe.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    probe.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = src.numel() * 8 / (time.perf_counter() - t0) / 1e9
+    del probe, src
+    runs = []
+    for block in ((m, n, 2048), (m // 2, n, 2048), (m // 2, n // 2, 2048)):
+        mb, nb, kb = block
+        ws = torch.empty(mm.ooc_workspace_size(mb, nb, kb), dtype=torch.uint8, device="cuda:0")
+        cs = torch.cuda.Stream()
+        times = []
+        for _ in range(1 if args.profile else 2):
+            Ch.copy_(C0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mm.gemm_ooc(Ah, Bh, Ch, alpha=1.0, beta=1.0, block=block, workspace=ws, copy_stream=cs)
+            times.append(time.perf_counter() - t0)
+        t = min(times)
+        host_bytes = 8 * (2 * m * n + m * k * -(-n // nb) + k * n * -(-m // mb))
+        runs.append({"block": list(block), "workspace_gib": round(ws.numel() / 2 ** 30, 2), "s": round(t, 4),
+                     "tflops_pcie_inclusive": round(2.0 * m * n * k / t / 1e12, 2),
+                     "host_gb": round(host_bytes / 1e9, 2), "host_gb_per_s": round(host_bytes / t / 1e9, 1)})
+        del ws
+    rng = np.random.Generator(np.random.PCG64(12))
+    rows, cols = rng.integers(0, m, 32), rng.integers(0, n, 32)
+    want = oracle.gemm_entries(Ah.numpy(), Bh.numpy(), rows, cols, C0.numpy(), 1.0, 1.0)
+    absab = np.einsum("ij,ji->i", np.abs(Ah.numpy()[rows]), np.abs(Bh.numpy()[:, cols]))
+    err = np.abs(Ch.numpy()[rows, cols] - want) / (absab + np.abs(C0.numpy()[rows, cols]))
+    return {"m": m, "n": n, "k": k, "operands": "pinned host memory", "runs": runs,
+            "pinned_h2d_copy_gb_per_s": round(h2d, 1), "max_rel_err_32_entries": float(err.max())}
+
+
 def bench_batch(args):
     import torch
 
@@ -588,9 +646,9 @@ def main():
         profile_members(args.size)
         return
     only = "fp64" if (args.profile and args.only == "all") else args.only
-    if only in ("split", "batch", "backward", "members", "tiled", "syrk"):
+    if only in ("split", "batch", "backward", "members", "tiled", "syrk", "ooc"):
         fn = {"split": bench_split, "batch": bench_batch, "backward": bench_backward, "members": bench_members,
-              "tiled": bench_tiled, "syrk": bench_syrk}[only]
+              "tiled": bench_tiled, "syrk": bench_syrk, "ooc": bench_ooc}[only]
         print(json.dumps({only: fn(args)}), flush=True)
         return
     f = bench_fp64(args)
@@ -623,6 +681,7 @@ def main():
         out["members_8192"] = bench_members(args)
         out["tiled_storage"] = bench_tiled(args)
         out["syrk"] = bench_syrk(args)
+        out["out_of_core"] = bench_ooc(args)
     if not args.no_cpu and not args.profile:
         out["cpu_baseline"] = cpu_baseline(args.size, args.size, args.size, args.cpu_seconds)
     print(json.dumps(out), flush=True)

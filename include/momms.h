@@ -341,6 +341,32 @@ int momms_gemm_tiled(int64_t m, int64_t n, int64_t k, double alpha, const double
 int momms_syrk(int uplo, int trans, int64_t n, int64_t k, double alpha, const double *A, int64_t lda,
                double beta, double *C, int64_t ldc, int family_member, momms_stream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Out-of-core product: host memory as the level below HBM (the paper's
+ * out-of-core future work, Sec. 6; the loop levels of Sec. 3.2 with one more
+ * level).  C := alpha A B + beta C with A (m x k), B (k x n) and C (m x n)
+ * row-major in HOST memory (pinned memory lets the copies overlap the
+ * products; pageable memory works, with staged copies).  Resident C at the
+ * HBM level: C is processed in mb x nb blocks held in the device workspace
+ * while mb x kb panels of A and kb x nb panels of B are copied in; each
+ * block product runs `family_member` (MOMMS_AUTO picks per block shape).
+ * Host traffic: C 2mn (mn if beta == 0), A mk ceil(n/nb), B kn ceil(m/mb)
+ * elements.  Copies go on copy_stream, products on stream, ordered by
+ * events (two C buffers and two panel slots); the call returns once all
+ * work is enqueued, and C is complete when `stream` has drained.  beta == 0
+ * does not read C; alpha == 0 or k == 0 does not read A or B.
+ * workspace: device memory, 256-byte aligned, at least
+ * momms_ooc_workspace_size(mb, nb, kb) bytes.  Errors: -1 m, -2 n, -3 k,
+ * -5 A, -6 lda, -7 B, -8 ldb, -10 C, -11 ldc, -12 mb, -13 nb, -14 kb,
+ * -15 family_member, -16 workspace alignment, -17 workspace missing or too
+ * small; codes of momms_gemm_ex from a block product; positive HIP errors
+ * from the copies. */
+size_t momms_ooc_workspace_size(int64_t mb, int64_t nb, int64_t kb);
+int momms_gemm_ooc(int64_t m, int64_t n, int64_t k, double alpha, const double *A, int64_t lda,
+                   const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                   int64_t mb, int64_t nb, int64_t kb, int family_member,
+                   void *workspace, size_t ws_bytes, momms_stream_t stream, momms_stream_t copy_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -307,6 +307,51 @@ def syrk(A, C=None, alpha=1.0, beta=0.0, uplo="L", trans=False, member="AUTO", s
     return C
 
 
+def _ld_host(t, name):
+    if t.dim() != 2 or t.dtype != torch.float64 or t.is_cuda:
+        raise ValueError(f"{name} must be a 2-D float64 host tensor")
+    if t.is_contiguous():
+        return max(1, t.shape[1])
+    if t.stride(1) != 1 or t.stride(0) < max(1, t.shape[1]):
+        raise ValueError(f"{name} must be row-major with unit column stride")
+    return max(1, t.stride(0))
+
+
+def ooc_workspace_size(mb, nb, kb):
+    return int(_lib.momms_ooc_workspace_size(int(mb), int(nb), int(kb)))
+
+
+def gemm_ooc(A, B, C, alpha=1.0, beta=0.0, block=(8192, 8192, 2048), member="AUTO", workspace=None,
+             stream=None, copy_stream=None, device="cuda:0"):
+    """Out-of-core C := alpha * A @ B + beta * C with A, B, C float64 HOST
+    tensors (pin_memory() ones let copies overlap the products).  C is
+    processed in mb x nb blocks resident in device memory while panels of A
+    and B stream in; block = (mb, nb, kb).  Waits for the result before
+    returning."""
+    m, k = A.shape
+    kb_, n = B.shape
+    if k != kb_:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb_}")
+    if tuple(C.shape) != (m, n):
+        raise ValueError(f"C has shape {tuple(C.shape)}, expected {(m, n)}")
+    lda, ldb, ldc = _ld_host(A, "A"), _ld_host(B, "B"), _ld_host(C, "C")
+    mb, nb, kb = (int(x) for x in block)
+    need = ooc_workspace_size(mb, nb, kb)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=device)
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    if copy_stream is None:
+        copy_stream = torch.cuda.Stream(device=device)
+    st = _lib.momms_gemm_ooc(m, n, k, float(alpha), A.data_ptr(), lda, B.data_ptr(), ldb, float(beta), C.data_ptr(),
+                             ldc, mb, nb, kb, member_id(member), workspace.data_ptr(),
+                             workspace.numel() * workspace.element_size(), stream.cuda_stream,
+                             copy_stream.cuda_stream)
+    check_status(st, "momms_gemm_ooc")
+    stream.synchronize()
+    return C
+
+
 def model_resident(resident, m, n, k, b1, b2, beta=1.0):
     """Sec. 2.2 transfer counts: {a_reads, b_reads, c_reads, c_writes} in elements."""
     import ctypes

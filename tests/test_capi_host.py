@@ -193,3 +193,30 @@ def test_crt_limits():
     assert f(0, 0, 4, 4, 4, 1.0, big, 4, big, 4, 0.0, big, 4, 17, 3, 0, big, 1 << 30, None) == -14
     assert mm.split_workspace_size(4, 4, 4, 16, "crt") > 0
     assert mm.split_workspace_size(4, 4, 4, 17, "crt") == 0
+
+
+def test_ooc_argument_errors_before_any_device_call():
+    f = mm._lib.momms_gemm_ooc
+    big = 1 << 20
+    ws = mm.ooc_workspace_size(64, 64, 32)
+    assert ws >= 8 * (2 * 64 * 64 + 2 * (64 * 32 + 32 * 64))
+    args = [100, 90, 80, 1.0, big, 80, big, 90, 1.0, big, 90, 64, 64, 32, 0, 1 << 30, ws, None, None]
+
+    def call(i, v):
+        a = list(args)
+        a[i] = v
+        return f(*a)
+
+    assert call(0, -1) == -1 and call(1, -1) == -2 and call(2, -1) == -3
+    assert call(4, None) == -5 and call(5, 79) == -6 and call(6, None) == -7 and call(7, 89) == -8
+    assert call(9, None) == -10 and call(10, 89) == -11
+    assert call(11, 0) == -12 and call(12, 0) == -13 and call(13, 0) == -14
+    assert call(14, 99) == -15 and call(15, (1 << 30) + 8) == -16 and call(16, ws - 1) == -17
+    assert call(15, None) == -17
+    assert mm.ooc_workspace_size(0, 4, 4) == 0
+    # quick returns: empty C, or nothing to add with beta = 1
+    assert call(0, 0) == 0
+    a = list(args)
+    a[3] = 0.0
+    a[8] = 1.0
+    assert f(*a) == 0
