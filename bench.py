@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--member", default="AUTO")
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--only", default="all",
-                    choices=["all", "fp64", "split", "batch", "backward", "members", "tiled", "syrk", "ooc"])
+                    choices=["all", "fp64", "split", "batch", "backward", "members", "tiled", "syrk", "tri",
+                             "ooc"])
     ap.add_argument("--split", default="crt:14,crt:15,crt:16,int8:8,int8:9,bf16:3,bf16:4,bf16:5,bf16:6,bf16:7,"
                     "fp8:3,fp8:4,fp8:5,fp8:6,fp8:7,fp8:8",
                     help="split-precision configurations to time, as type:slices[,type:slices...]")
@@ -419,6 +420,51 @@ def bench_ooc(args):
             "pinned_h2d_copy_gb_per_s": round(h2d, 1), "max_rel_err_32_entries": float(err.max())}
 
 
+def bench_tri(args):
+    """Triangular solve and multiply with m = n = size (lower triangle, no
+    transposition, well-conditioned T), rate in m^2 n flops per second,
+    against the full product of the same shape."""
+    import numpy as np
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    m = n = args.size
+    A = workloads.uniform((m, m), 27) / np.sqrt(m)
+    A[np.diag_indices(m)] = 1.5
+    Ad = torch.from_numpy(A).to("cuda:0")
+    B0 = torch.from_numpy(workloads.uniform((m, n), 28)).to("cuda:0")
+    B = torch.empty_like(B0)
+    C = torch.empty_like(B0)
+    reps = 1 if args.profile else 5
+
+    def timed(fn, prep=None):
+        if prep:
+            prep()
+        fn()
+        torch.cuda.synchronize()
+        total = 0.0
+        for _ in range(reps):
+            if prep:
+                prep()
+            e0, e1 = events()
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            total += e0.elapsed_time(e1)
+        return total / reps
+
+    t_trsm = timed(lambda: mm.trsm(Ad, B, uplo="L"), prep=lambda: B.copy_(B0))
+    t_trmm = timed(lambda: mm.trmm(Ad, B0, C, uplo="L"))
+    t_gemm = timed(lambda: mm.gemm(Ad, B0, C))
+    flops = float(m) * m * n
+    return {"m": m, "n": n, "trsm_ms": round(t_trsm, 3), "trsm_tflops": round(flops / t_trsm / 1e9, 2),
+            "trmm_ms": round(t_trmm, 3), "trmm_tflops": round(flops / t_trmm / 1e9, 2),
+            "full_product_ms": round(t_gemm, 3), "full_product_tflops": round(2 * flops / t_gemm / 1e9, 2)}
+
+
 def bench_batch(args):
     import torch
 
@@ -646,9 +692,9 @@ def main():
         profile_members(args.size)
         return
     only = "fp64" if (args.profile and args.only == "all") else args.only
-    if only in ("split", "batch", "backward", "members", "tiled", "syrk", "ooc"):
+    if only in ("split", "batch", "backward", "members", "tiled", "syrk", "tri", "ooc"):
         fn = {"split": bench_split, "batch": bench_batch, "backward": bench_backward, "members": bench_members,
-              "tiled": bench_tiled, "syrk": bench_syrk, "ooc": bench_ooc}[only]
+              "tiled": bench_tiled, "syrk": bench_syrk, "tri": bench_tri, "ooc": bench_ooc}[only]
         print(json.dumps({only: fn(args)}), flush=True)
         return
     f = bench_fp64(args)
@@ -681,6 +727,7 @@ def main():
         out["members_8192"] = bench_members(args)
         out["tiled_storage"] = bench_tiled(args)
         out["syrk"] = bench_syrk(args)
+        out["triangular"] = bench_tri(args)
         out["out_of_core"] = bench_ooc(args)
     if not args.no_cpu and not args.profile:
         out["cpu_baseline"] = cpu_baseline(args.size, args.size, args.size, args.cpu_seconds)

@@ -342,6 +342,29 @@ int momms_syrk(int uplo, int trans, int64_t n, int64_t k, double alpha, const do
                double beta, double *C, int64_t ldc, int family_member, momms_stream_t stream);
 
 /* ---------------------------------------------------------------------
+ * Triangular multiply and solve (the other level-3 BLAS are the paper's
+ * next target, Sec. 6).  T is the lower (uplo 'L') or upper ('U') triangle
+ * of the m x m matrix A, with a unit diagonal when diag == 'U' (the
+ * diagonal of A is then not read; the other triangle never is); op(T) = T
+ * (trans 0) or T^T (trans 1).  B and C are m x n.  All row-major device
+ * memory; no workspace.  Both halve the triangle recursively: the
+ * off-diagonal blocks are family products (momms_gemm_ex, MOMMS_AUTO) and
+ * diagonal blocks of at most 64 rows are solved or multiplied by one
+ * substitution kernel (one thread per column of B).
+ *   momms_trmm:  C := alpha op(T) B, out of place (C must not overlap A or
+ *                B); alpha == 0 writes C = 0 without reading A or B.
+ *   momms_trsm:  B := X with op(T) X = alpha B, in place; alpha == 0 sets
+ *                B = 0 without reading A.  No singularity check: a zero on a
+ *                non-unit diagonal gives infinities or NaNs as IEEE division
+ *                does.
+ * Errors: -1 uplo, -2 trans, -3 diag, -4 m, -5 n, -7 A, -8 lda (< m),
+ * -9 B, -10 ldb (< n), -11 C, -12 ldc (< n); positive HIP errors. */
+int momms_trmm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha, const double *A,
+               int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc, momms_stream_t stream);
+int momms_trsm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha, const double *A,
+               int64_t lda, double *B, int64_t ldb, momms_stream_t stream);
+
+/* ---------------------------------------------------------------------
  * Out-of-core product: host memory as the level below HBM (the paper's
  * out-of-core future work, Sec. 6; the loop levels of Sec. 3.2 with one more
  * level).  C := alpha A B + beta C with A (m x k), B (k x n) and C (m x n)

@@ -307,6 +307,37 @@ def syrk(A, C=None, alpha=1.0, beta=0.0, uplo="L", trans=False, member="AUTO", s
     return C
 
 
+def trmm(A, B, C=None, alpha=1.0, uplo="L", trans=False, diag="N", stream=None):
+    """C := alpha * op(T) @ B with T the uplo triangle of A (unit diagonal when
+    diag == 'U'); out of place, returns C."""
+    m, n = B.shape
+    if tuple(A.shape) != (m, m):
+        raise ValueError(f"A has shape {tuple(A.shape)}, expected {(m, m)}")
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.float64, device=B.device)
+    if tuple(C.shape) != (m, n):
+        raise ValueError(f"C has shape {tuple(C.shape)}, expected {(m, n)}")
+    if uplo not in ("L", "U") or diag not in ("N", "U"):
+        raise ValueError("uplo must be 'L' or 'U' and diag 'N' or 'U'")
+    st = _lib.momms_trmm(ord(uplo), int(bool(trans)), ord(diag), m, n, float(alpha), A.data_ptr(), _ld(A, "A"),
+                         B.data_ptr(), _ld(B, "B"), C.data_ptr(), _ld(C, "C"), _stream_handle(stream))
+    check_status(st, "momms_trmm")
+    return C
+
+
+def trsm(A, B, alpha=1.0, uplo="L", trans=False, diag="N", stream=None):
+    """Solves op(T) X = alpha B in place (B becomes X); returns B."""
+    m, n = B.shape
+    if tuple(A.shape) != (m, m):
+        raise ValueError(f"A has shape {tuple(A.shape)}, expected {(m, m)}")
+    if uplo not in ("L", "U") or diag not in ("N", "U"):
+        raise ValueError("uplo must be 'L' or 'U' and diag 'N' or 'U'")
+    st = _lib.momms_trsm(ord(uplo), int(bool(trans)), ord(diag), m, n, float(alpha), A.data_ptr(), _ld(A, "A"),
+                         B.data_ptr(), _ld(B, "B"), _stream_handle(stream))
+    check_status(st, "momms_trsm")
+    return B
+
+
 def _ld_host(t, name):
     if t.dim() != 2 or t.dtype != torch.float64 or t.is_cuda:
         raise ValueError(f"{name} must be a 2-D float64 host tensor")

@@ -1,0 +1,243 @@
+// Triangular multiply and solve on the family (the other level-3 BLAS are
+// the paper's next target, Sec. 6):
+//
+//   momms_trmm: C := alpha op(T) B        (out of place)
+//   momms_trsm: B := X with op(T) X = alpha B   (in place)
+//
+// T is the lower or upper triangle of the m x m matrix A (unit diagonal when
+// asked, the diagonal of A then not read), op(T) = T or T^T, B and C are
+// m x n, all row-major.  Both halve the triangle recursively, so nearly all
+// flops run as large family products:
+//
+//   op(T) lower:  [T11 0; T21 T22]:  solve X1 with T11, B2 -= T21 X1 (product),
+//                 solve X2 with T22;   multiply C1 = T11 B1, C2 = T22 B2,
+//                 C2 += T21 B1 (product);
+//   op(T) upper:  the mirror image (second block first for the solve).
+//
+// Diagonal blocks of at most 64 rows go to one kernel: a lane owns one column
+// of B, held in LDS next to the block of op(T) (read by all lanes at one
+// address); four waves share the rows of the triangular product, or run a
+// blocked forward or backward substitution.
+#include <hip/hip_runtime.h>
+
+#include "../../include/momms.h"
+#include "plan_internal.h"
+
+namespace momms {
+namespace tri {
+
+constexpr int kBase = 64;   // rows of a diagonal block handled by the base kernel
+
+// MODE 0: solve (x := op(T)^-1 x), 1: multiply (y := alpha op(T) x, written to Y).
+// LOWER: op(T) is lower triangular.  A workgroup takes 64 columns with four
+// waves; lane c owns column c, held at xs[i][c] (lanes read consecutive
+// words).  Multiply: wave w forms rows 16w .. 16w+15, sixteen independent
+// sums.  Solve: blocked substitution over four 16-row blocks in solve
+// order; wave 0 runs the substitution inside a block (only the block's own
+// columns of op(T) remain to subtract), then all waves subtract that block's
+// contribution from the rows after it.
+template <int MODE, bool LOWER, bool UNIT>
+__global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double* __restrict__ A, int64_t lda,
+                                                  bool trans, bool upper_stored, double alpha, double* X,
+                                                  int64_t ldx, double* Y, int64_t ldy) {
+    __shared__ double Ts[kBase][kBase + 1];
+    __shared__ double xs[kBase][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // op(T) padded to 64 x 64 with the identity: rows beyond s solve to 0
+    for (int e = tid; e < kBase * kBase; e += 256) {
+        const int i = e / kBase, j = e % kBase;
+        double v = 0.0;
+        if (i < s && j < s) {
+            const int a = trans ? j : i, b = trans ? i : j;   // op(T)(i, j) = T(a, b)
+            const bool in = upper_stored ? a <= b : a >= b;
+            if (in) v = (a == b && UNIT) ? 1.0 : A[(int64_t)a * lda + b];
+        } else if (i == j) {
+            v = 1.0;
+        }
+        Ts[i][j] = v;
+    }
+    const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = col < n;   // dead lanes work on zeros and store nothing
+    for (int i = wave; i < kBase; i += 4) xs[i][lane] = (live && i < s) ? X[(int64_t)i * ldx + col] : 0.0;
+    __syncthreads();
+    if (MODE == 1) {
+        double acc[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+        const int i0 = 16 * wave;
+        // op(T) lower: row i uses j <= i; upper: j >= i.  Columns outside a
+        // row's range hold zeros in Ts, so the loop bounds only trim work.
+        const int j0 = LOWER ? 0 : i0, j1 = LOWER ? i0 + 16 : kBase;
+        for (int j = j0; j < j1; ++j) {
+            const double xj = xs[j][lane];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = fma(Ts[i0 + r][j], xj, acc[r]);
+        }
+        if (live)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (i0 + r < s) Y[(int64_t)(i0 + r) * ldy + col] = alpha * acc[r];
+        return;
+    }
+    for (int q = 0; q < 4; ++q) {
+        const int kb = LOWER ? q : 3 - q;   // block in solve order
+        const int b0 = 16 * kb;
+        if (wave == 0) {
+            for (int u = 0; u < 16; ++u) {
+                const int i = LOWER ? b0 + u : b0 + 15 - u;
+                const int j0 = LOWER ? b0 : i + 1, j1 = LOWER ? i : b0 + 16;
+                double dot = 0.0;
+                for (int j = j0; j < j1; ++j) dot = fma(Ts[i][j], xs[j][lane], dot);
+                const double r = xs[i][lane] - dot;
+                xs[i][lane] = UNIT ? r : r / Ts[i][i];
+            }
+        }
+        __syncthreads();
+        // rows still to solve: after the block (lower) or before it (upper)
+        const int r0 = LOWER ? b0 + 16 : 0, r1 = LOWER ? kBase : b0;
+        for (int i = r0 + wave; i < r1; i += 4) {
+            double dot = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) dot = fma(Ts[i][b0 + j], xs[b0 + j][lane], dot);
+            xs[i][lane] -= dot;
+        }
+        __syncthreads();
+    }
+    if (live)
+        for (int i = wave; i < s; i += 4) X[(int64_t)i * ldx + col] = xs[i][lane];
+}
+
+struct Tri {
+    bool trans, upper_stored, unit, lower_op;
+    const double* A;
+    int64_t lda, n;
+    hipStream_t st;
+};
+
+// Block (R0.., C0..) of op(A) as a product operand: pointer and trans flag.
+static inline const double* op_block(const Tri& t, int64_t R0, int64_t C0, int* transA) {
+    *transA = t.trans ? 1 : 0;
+    return t.trans ? t.A + C0 * t.lda + R0 : t.A + R0 * t.lda + C0;
+}
+
+template <int MODE>
+static int launch_base(const Tri& t, int64_t r0, int64_t s, double alpha, double* X, int64_t ldx, double* Y,
+                       int64_t ldy) {
+    const dim3 grid((unsigned)((t.n + 63) / 64));   // 64 columns per workgroup of 256 threads
+    const double* Ab = t.A + r0 * t.lda + r0;
+    if (t.lower_op) {
+        if (t.unit)
+            hipLaunchKernelGGL((k_tri_base<MODE, true, true>), grid, dim3(256), 0, t.st, (int)s, t.n, Ab, t.lda,
+                               t.trans, t.upper_stored, alpha, X, ldx, Y, ldy);
+        else
+            hipLaunchKernelGGL((k_tri_base<MODE, true, false>), grid, dim3(256), 0, t.st, (int)s, t.n, Ab, t.lda,
+                               t.trans, t.upper_stored, alpha, X, ldx, Y, ldy);
+    } else {
+        if (t.unit)
+            hipLaunchKernelGGL((k_tri_base<MODE, false, true>), grid, dim3(256), 0, t.st, (int)s, t.n, Ab, t.lda,
+                               t.trans, t.upper_stored, alpha, X, ldx, Y, ldy);
+        else
+            hipLaunchKernelGGL((k_tri_base<MODE, false, false>), grid, dim3(256), 0, t.st, (int)s, t.n, Ab, t.lda,
+                               t.trans, t.upper_stored, alpha, X, ldx, Y, ldy);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+static inline int64_t split_point(int64_t s) {   // a multiple of kBase in (0, s)
+    const int64_t h = ((s / 2 + kBase - 1) / kBase) * kBase;
+    return h < s ? h : s - kBase;
+}
+
+// Solve op(T)[r0:r0+s, r0:r0+s] X = B[r0:r0+s] in place.
+static int solve(const Tri& t, int64_t r0, int64_t s, double* B, int64_t ldb) {
+    if (s <= kBase) return launch_base<0>(t, r0, s, 1.0, B + r0 * ldb, ldb, nullptr, 0);
+    const int64_t h = split_point(s);
+    int ta, rc;
+    if (t.lower_op) {
+        if ((rc = solve(t, r0, h, B, ldb)) != 0) return rc;
+        const double* Ab = op_block(t, r0 + h, r0, &ta);
+        if ((rc = momms_gemm_ex(ta, 0, s - h, t.n, h, -1.0, Ab, t.lda, B + r0 * ldb, ldb, 1.0, B + (r0 + h) * ldb,
+                                ldb, MOMMS_AUTO, nullptr, 0, t.st)) != 0)
+            return rc;
+        return solve(t, r0 + h, s - h, B, ldb);
+    }
+    if ((rc = solve(t, r0 + h, s - h, B, ldb)) != 0) return rc;
+    const double* Ab = op_block(t, r0, r0 + h, &ta);
+    if ((rc = momms_gemm_ex(ta, 0, h, t.n, s - h, -1.0, Ab, t.lda, B + (r0 + h) * ldb, ldb, 1.0, B + r0 * ldb, ldb,
+                            MOMMS_AUTO, nullptr, 0, t.st)) != 0)
+        return rc;
+    return solve(t, r0, h, B, ldb);
+}
+
+// C[r0:r0+s] = alpha op(T)[r0:r0+s, r0:r0+s] B[r0:r0+s].
+static int multiply(const Tri& t, int64_t r0, int64_t s, double alpha, const double* B, int64_t ldb, double* C,
+                    int64_t ldc) {
+    if (s <= kBase)
+        return launch_base<1>(t, r0, s, alpha, const_cast<double*>(B) + r0 * ldb, ldb, C + r0 * ldc, ldc);
+    const int64_t h = split_point(s);
+    int ta, rc;
+    if ((rc = multiply(t, r0, h, alpha, B, ldb, C, ldc)) != 0) return rc;
+    if ((rc = multiply(t, r0 + h, s - h, alpha, B, ldb, C, ldc)) != 0) return rc;
+    if (t.lower_op) {   // C2 += alpha T21 B1
+        const double* Ab = op_block(t, r0 + h, r0, &ta);
+        return momms_gemm_ex(ta, 0, s - h, t.n, h, alpha, Ab, t.lda, B + r0 * ldb, ldb, 1.0, C + (r0 + h) * ldc,
+                             ldc, MOMMS_AUTO, nullptr, 0, t.st);
+    }
+    const double* Ab = op_block(t, r0, r0 + h, &ta);   // C1 += alpha T12 B2
+    return momms_gemm_ex(ta, 0, h, t.n, s - h, alpha, Ab, t.lda, B + (r0 + h) * ldb, ldb, 1.0, C + r0 * ldc, ldc,
+                         MOMMS_AUTO, nullptr, 0, t.st);
+}
+
+static int check_common(int uplo, int trans, int diag, int64_t m, int64_t n, int64_t lda, int64_t ldb) {
+    if (uplo != 'L' && uplo != 'U') return -1;
+    if (trans != 0 && trans != 1) return -2;
+    if (diag != 'N' && diag != 'U') return -3;
+    if (m < 0) return -4;
+    if (n < 0) return -5;
+    if (lda < (m > 1 ? m : 1)) return -8;
+    if (ldb < (n > 1 ? n : 1)) return -10;
+    return 0;
+}
+
+}  // namespace tri
+}  // namespace momms
+
+extern "C" {
+
+int momms_trmm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha, const double* A, int64_t lda,
+               const double* B, int64_t ldb, double* C, int64_t ldc, momms_stream_t stream) {
+    using namespace momms::tri;
+    int rc = check_common(uplo, trans, diag, m, n, lda, ldb);
+    if (rc != 0) return rc;
+    const bool reads = alpha != 0.0 && m > 0 && n > 0;
+    if (reads && A == nullptr) return -7;
+    if (reads && B == nullptr) return -9;
+    if (m > 0 && n > 0 && C == nullptr) return -11;
+    if (ldc < (n > 1 ? n : 1)) return -12;
+    if (m == 0 || n == 0) return 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (alpha == 0.0)   // C = 0, A and B not read
+        return momms_gemm_ex(0, 0, m, n, 0, 0.0, nullptr, 1, nullptr, n, 0.0, C, ldc, MOMMS_AUTO, nullptr, 0, st);
+    Tri t{trans != 0, uplo == 'U', diag == 'U', (uplo == 'L') != (trans != 0), A, lda, n, st};
+    return multiply(t, 0, m, alpha, B, ldb, C, ldc);
+}
+
+int momms_trsm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha, const double* A, int64_t lda,
+               double* B, int64_t ldb, momms_stream_t stream) {
+    using namespace momms::tri;
+    int rc = check_common(uplo, trans, diag, m, n, lda, ldb);
+    if (rc != 0) return rc;
+    if (alpha != 0.0 && m > 0 && n > 0 && A == nullptr) return -7;
+    if (m > 0 && n > 0 && B == nullptr) return -9;
+    if (m == 0 || n == 0) return 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (alpha != 1.0) {   // B = alpha B (alpha = 0: B = 0 and A is not read)
+        rc = momms_gemm_ex(0, 0, m, n, 0, 0.0, nullptr, 1, nullptr, n, alpha, B, ldb, MOMMS_AUTO, nullptr, 0, st);
+        if (rc != 0 || alpha == 0.0) return rc;
+    }
+    Tri t{trans != 0, uplo == 'U', diag == 'U', (uplo == 'L') != (trans != 0), A, lda, n, st};
+    return solve(t, 0, m, B, ldb);
+}
+
+}  // extern "C"

@@ -220,3 +220,24 @@ def test_ooc_argument_errors_before_any_device_call():
     a[3] = 0.0
     a[8] = 1.0
     assert f(*a) == 0
+
+
+def test_trmm_trsm_argument_errors():
+    big = 1 << 20
+    trmm, trsm = mm._lib.momms_trmm, mm._lib.momms_trsm
+    L, N = ord("L"), ord("N")
+    assert trmm(ord("X"), 0, N, 4, 4, 1.0, big, 4, big, 4, big, 4, None) == -1
+    assert trmm(L, 2, N, 4, 4, 1.0, big, 4, big, 4, big, 4, None) == -2
+    assert trmm(L, 0, ord("Z"), 4, 4, 1.0, big, 4, big, 4, big, 4, None) == -3
+    assert trmm(L, 0, N, -1, 4, 1.0, big, 4, big, 4, big, 4, None) == -4
+    assert trmm(L, 0, N, 4, -1, 1.0, big, 4, big, 4, big, 4, None) == -5
+    assert trmm(L, 0, N, 4, 4, 1.0, None, 4, big, 4, big, 4, None) == -7
+    assert trmm(L, 0, N, 4, 4, 1.0, big, 3, big, 4, big, 4, None) == -8
+    assert trmm(L, 0, N, 4, 4, 1.0, big, 4, None, 4, big, 4, None) == -9
+    assert trmm(L, 0, N, 4, 4, 1.0, big, 4, big, 3, big, 4, None) == -10
+    assert trmm(L, 0, N, 4, 4, 1.0, big, 4, big, 4, None, 4, None) == -11
+    assert trmm(L, 0, N, 4, 4, 1.0, big, 4, big, 4, big, 3, None) == -12
+    assert trsm(L, 0, N, 4, 4, 1.0, None, 4, big, 4, None) == -7
+    assert trsm(L, 0, N, 4, 4, 1.0, big, 4, None, 4, None) == -9
+    assert trsm(L, 0, N, 4, 4, 1.0, big, 4, big, 3, None) == -10
+    assert trsm(L, 0, N, 0, 4, 1.0, None, 1, None, 4, None) == 0

@@ -1,0 +1,135 @@
+"""Triangular multiply and solve on the device against their plain
+definitions (oracle/tri.py): every uplo / trans / diag combination, ragged
+recursion, exact integer systems, the triangle and diagonal that must not be
+read, alpha = 0, and a 2048-row case on sampled columns."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import tri
+
+pytestmark = pytest.mark.gpu
+mm = pytest.importorskip("paper_1904_05717_amd")
+DEV = "cuda:0"
+U = 2.0 ** -53
+COMBOS = [(u, t, d) for u in "LU" for t in (False, True) for d in "NU"]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def well_conditioned(m, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = rng.uniform(-1, 1, (m, m)) / np.sqrt(m)
+    A[np.diag_indices(m)] = rng.uniform(1, 2, m) * np.sign(rng.uniform(-1, 1, m))
+    return A
+
+
+def poisoned(A, uplo, diag):
+    """A copy with NaN wherever the operation must not read."""
+    P = A.copy()
+    m = A.shape[0]
+    other = np.triu_indices(m, 1) if uplo == "L" else np.tril_indices(m, -1)
+    P[other] = np.nan
+    if diag == "U":
+        P[np.diag_indices(m)] = np.nan
+    return P
+
+
+@pytest.mark.parametrize("uplo,trans,diag", COMBOS)
+def test_trsm_matches_substitution(uplo, trans, diag):
+    m, n = 300, 170   # recursion 300 -> 192 + 108 -> ..., ragged diagonal blocks
+    A = well_conditioned(m, 1)
+    B = np.random.Generator(np.random.PCG64(2)).uniform(-1, 1, (m, n))
+    Bd = dev(B)
+    mm.trsm(dev(poisoned(A, uplo, diag)), Bd, alpha=0.75, uplo=uplo, trans=trans, diag=diag)
+    torch.cuda.synchronize()
+    X = Bd.cpu().numpy()
+    T = tri.op_tri(A, uplo, trans, diag)
+    R = oracle.gemm(T, X, B, 1.0, -0.75)
+    assert np.all(np.abs(R) <= 4 * (m + 2) * U * (np.abs(T) @ np.abs(X) + 0.75 * np.abs(B)))
+    want = tri.trsm(A, B, uplo, trans, diag, alpha=0.75)
+    assert np.max(np.abs(X - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("uplo,trans,diag", COMBOS)
+def test_trmm_within_product_bound(uplo, trans, diag):
+    m, n = 300, 170
+    rng = np.random.Generator(np.random.PCG64(3))
+    A = rng.uniform(-1, 1, (m, m))
+    B = rng.uniform(-1, 1, (m, n))
+    C = dev(np.full((m, n), np.nan))
+    mm.trmm(dev(poisoned(A, uplo, diag)), dev(B), C, alpha=-1.25, uplo=uplo, trans=trans, diag=diag)
+    torch.cuda.synchronize()
+    T = tri.op_tri(A, uplo, trans, diag)
+    want = tri.trmm(A, B, uplo, trans, diag, alpha=-1.25)
+    tol = 2 * (m + 2) * U * 1.25 * (np.abs(T) @ np.abs(B))
+    assert np.all(np.abs(C.cpu().numpy() - want) <= tol)
+
+
+@pytest.mark.parametrize("uplo,trans", [("L", False), ("U", True), ("U", False), ("L", True)])
+def test_integer_unit_systems_exact(uplo, trans):
+    m, n = 200, 90
+    rng = np.random.Generator(np.random.PCG64(4))
+    A = rng.integers(-1, 2, (m, m)).astype(np.float64)
+    X = rng.integers(-2, 3, (m, n)).astype(np.float64)
+    T = tri.op_tri(A, uplo, trans, "U")
+    B = (T.astype(np.int64) @ X.astype(np.int64)).astype(np.float64)
+    C = dev(np.zeros((m, n)))
+    mm.trmm(dev(A), dev(X), C, uplo=uplo, trans=trans, diag="U")
+    Bd = dev(B)
+    mm.trsm(dev(A), Bd, uplo=uplo, trans=trans, diag="U")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(C.cpu().numpy(), B)
+    # every value substitution and the block updates form is a partial sum of
+    # small integers (the solution itself is X), so the solve is exact
+    np.testing.assert_array_equal(Bd.cpu().numpy(), X)
+
+
+def test_alpha_zero_and_empty():
+    m, n = 70, 30
+    A = np.full((m, m), np.nan)
+    Bd = dev(np.ones((m, n)))
+    mm.trsm(dev(A), Bd, alpha=0.0)
+    C = dev(np.full((m, n), np.nan))
+    mm.trmm(dev(A), dev(np.full((m, n), np.nan)), C, alpha=0.0)
+    torch.cuda.synchronize()
+    assert (Bd.cpu().numpy() == 0).all() and (C.cpu().numpy() == 0).all()
+    E = dev(np.zeros((0, 5)))
+    mm.trsm(dev(np.zeros((0, 0))), E)
+    mm.trmm(dev(np.zeros((0, 0))), E, dev(np.zeros((0, 5))))
+
+
+@pytest.mark.parametrize("m", [1, 63, 64, 65, 129])
+def test_block_edges(m):
+    n = 33
+    A = well_conditioned(m, 5)
+    B = np.random.Generator(np.random.PCG64(6)).uniform(-1, 1, (m, n))
+    Bd = dev(B)
+    mm.trsm(dev(A), Bd, uplo="U", trans=True)
+    C = dev(np.zeros((m, n)))
+    mm.trmm(dev(A), dev(B), C, uplo="L")
+    torch.cuda.synchronize()
+    want = tri.trsm(A, B, "U", True)
+    assert np.max(np.abs(Bd.cpu().numpy() - want)) <= 1e-12 * max(1.0, np.abs(want).max())
+    T = tri.op_tri(A, "L")
+    assert np.all(np.abs(C.cpu().numpy() - tri.trmm(A, B, "L")) <= 2 * (m + 2) * U * (np.abs(T) @ np.abs(B)))
+
+
+def test_large_sampled_columns():
+    m, n = 2048, 1024
+    A = well_conditioned(m, 7)
+    B = np.random.Generator(np.random.PCG64(8)).uniform(-1, 1, (m, n))
+    Bd = dev(B)
+    mm.trsm(dev(A), Bd, uplo="L", trans=False)
+    C = dev(np.zeros((m, n)))
+    mm.trmm(dev(A), dev(B), C, uplo="U", trans=True, alpha=2.0)
+    torch.cuda.synchronize()
+    cols = np.array([0, 1, 511, 512, 1023])
+    want = tri.trsm(A, B[:, cols], "L")
+    assert np.max(np.abs(Bd.cpu().numpy()[:, cols] - want)) <= 1e-12 * np.abs(want).max()
+    T = tri.op_tri(A, "U", True)
+    wc = tri.trmm(A, B[:, cols], "U", True, alpha=2.0)
+    assert np.all(np.abs(C.cpu().numpy()[:, cols] - wc) <= 2 * (m + 2) * U * 2.0 * (np.abs(T) @ np.abs(B[:, cols])))
