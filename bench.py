@@ -422,8 +422,9 @@ def bench_ooc(args):
 
 def bench_tri(args):
     """Triangular solve and multiply with m = n = size (lower triangle, no
-    transposition, well-conditioned T), rate in m^2 n flops per second,
-    against the full product of the same shape."""
+    transposition, well-conditioned T), rate in m^2 n flops per second; the
+    Cholesky factorization of an SPD matrix of order size (n^3 / 3 flops);
+    the full product of the same shape beside them."""
     import numpy as np
     import torch
 
@@ -456,12 +457,18 @@ def bench_tri(args):
             total += e0.elapsed_time(e1)
         return total / reps
 
+    S0 = torch.from_numpy(workloads.uniform((m, m), 29) / np.sqrt(m)).to("cuda:0")
+    S0 = S0 @ S0.t() + torch.eye(m, dtype=torch.float64, device="cuda:0")   # SPD, well conditioned
+    S = torch.empty_like(S0)
+    t_potrf = timed(lambda: mm.potrf(S), prep=lambda: S.copy_(S0))
+    del S, S0
     t_trsm = timed(lambda: mm.trsm(Ad, B, uplo="L"), prep=lambda: B.copy_(B0))
     t_trmm = timed(lambda: mm.trmm(Ad, B0, C, uplo="L"))
     t_gemm = timed(lambda: mm.gemm(Ad, B0, C))
     flops = float(m) * m * n
     return {"m": m, "n": n, "trsm_ms": round(t_trsm, 3), "trsm_tflops": round(flops / t_trsm / 1e9, 2),
             "trmm_ms": round(t_trmm, 3), "trmm_tflops": round(flops / t_trmm / 1e9, 2),
+            "potrf_ms": round(t_potrf, 3), "potrf_tflops": round(m ** 3 / 3.0 / t_potrf / 1e9, 2),
             "full_product_ms": round(t_gemm, 3), "full_product_tflops": round(2 * flops / t_gemm / 1e9, 2)}
 
 

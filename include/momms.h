@@ -364,6 +364,19 @@ int momms_trmm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha
 int momms_trsm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha, const double *A,
                int64_t lda, double *B, int64_t ldb, momms_stream_t stream);
 
+/* Cholesky factorization A = U^T U (the recursive blocked factorizations
+ * the paper names as future work, Sec. 6).  uplo must be 'U': U is written
+ * over the upper triangle of the row-major n x n device matrix A (the
+ * memory layout of LAPACK's column-major lower factor); the strictly lower
+ * triangle is never read or written.  Recursive halving onto momms_trsm and
+ * momms_syrk; diagonal blocks of at most 64 rows are factored in LDS by one
+ * workgroup.  info (device int, may be NULL) is set to 0, or to the 1-based
+ * row of the first pivot that is not positive (A not positive definite; the
+ * factorization continues with NaNs past it); read it after the stream has
+ * drained.  Errors: -1 uplo, -2 n, -3 A, -4 lda (< n); codes of momms_trsm
+ * and momms_syrk; positive HIP errors. */
+int momms_potrf(int uplo, int64_t n, double *A, int64_t lda, int *info, momms_stream_t stream);
+
 /* ---------------------------------------------------------------------
  * Out-of-core product: host memory as the level below HBM (the paper's
  * out-of-core future work, Sec. 6; the loop levels of Sec. 3.2 with one more

@@ -338,6 +338,24 @@ def trsm(A, B, alpha=1.0, uplo="L", trans=False, diag="N", stream=None):
     return B
 
 
+def potrf(A, uplo="U", stream=None):
+    """Cholesky A = U^T U in place on the upper triangle of the SPD device
+    matrix A (the strictly lower triangle is not touched).  Returns info: 0,
+    or the 1-based row of the first pivot that is not positive.  Waits for
+    the stream to read info."""
+    n = A.shape[0]
+    if tuple(A.shape) != (n, n):
+        raise ValueError("A must be square")
+    if uplo != "U":
+        raise ValueError("uplo must be 'U'")
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    rc = _lib.momms_potrf(ord(uplo), n, A.data_ptr(), _ld(A, "A"), info.data_ptr(), st.cuda_stream)
+    check_status(rc, "momms_potrf")
+    st.synchronize()
+    return int(info.item())
+
+
 def _ld_host(t, name):
     if t.dim() != 2 or t.dtype != torch.float64 or t.is_cuda:
         raise ValueError(f"{name} must be a 2-D float64 host tensor")

@@ -89,6 +89,7 @@ momms_from_tiled = _fn("momms_from_tiled", i32, [i32, i64, i64, vp, vp, i64, vp]
 momms_gemm_tiled = _fn("momms_gemm_tiled", i32, [i64, i64, i64, dbl, vp, vp, dbl, vp, i64, i32, vp])
 momms_trmm = _fn("momms_trmm", i32, [i32, i32, i32, i64, i64, dbl, vp, i64, vp, i64, vp, i64, vp])
 momms_trsm = _fn("momms_trsm", i32, [i32, i32, i32, i64, i64, dbl, vp, i64, vp, i64, vp])
+momms_potrf = _fn("momms_potrf", i32, [i32, i64, vp, i64, vp, vp])
 momms_ooc_workspace_size = _fn("momms_ooc_workspace_size", sz, [i64, i64, i64])
 momms_gemm_ooc = _fn("momms_gemm_ooc", i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i64, i64, i64, i32,
                                              vp, sz, vp, vp])
@@ -101,7 +102,7 @@ EXPORTS = [
     "momms_batch_create", "momms_batch_run", "momms_batch_info", "momms_batch_destroy", "momms_batch_select_tile",
     "momms_model_resident", "momms_balanced_block", "momms_set_member_table", "momms_select_member_prior",
     "momms_tiled_size", "momms_to_tiled", "momms_from_tiled", "momms_gemm_tiled", "momms_syrk", "momms_crt_bits",
-    "momms_ooc_workspace_size", "momms_gemm_ooc", "momms_trmm", "momms_trsm",
+    "momms_ooc_workspace_size", "momms_gemm_ooc", "momms_trmm", "momms_trsm", "momms_potrf",
 ]
 
 

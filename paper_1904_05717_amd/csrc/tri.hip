@@ -79,26 +79,39 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
                 if (i0 + r < s) Y[(int64_t)(i0 + r) * ldy + col] = alpha * acc[r];
         return;
     }
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int kb = LOWER ? q : 3 - q;   // block in solve order
         const int b0 = 16 * kb;
         if (wave == 0) {
-            for (int u = 0; u < 16; ++u) {
-                const int i = LOWER ? b0 + u : b0 + 15 - u;
-                const int j0 = LOWER ? b0 : i + 1, j1 = LOWER ? i : b0 + 16;
+            // the block's 16 unknowns in registers: only the FMAs form a chain
+            double xr[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) xr[u] = xs[b0 + u][lane];
+#pragma unroll
+            for (int uu = 0; uu < 16; ++uu) {
+                const int u = LOWER ? uu : 15 - uu;
+                const int i = b0 + u;
                 double dot = 0.0;
-                for (int j = j0; j < j1; ++j) dot = fma(Ts[i][j], xs[j][lane], dot);
-                const double r = xs[i][lane] - dot;
-                xs[i][lane] = UNIT ? r : r / Ts[i][i];
+#pragma unroll
+                for (int v = LOWER ? 0 : u + 1; v < (LOWER ? u : 16); ++v) dot = fma(Ts[i][b0 + v], xr[v], dot);
+                const double r = xr[u] - dot;
+                xr[u] = UNIT ? r : r / Ts[i][i];
+                __builtin_amdgcn_sched_barrier(0);   // keep each row's LDS reads with its FMAs
             }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) xs[b0 + u][lane] = xr[u];
         }
         __syncthreads();
         // rows still to solve: after the block (lower) or before it (upper)
+        double xb[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) xb[j] = xs[b0 + j][lane];
         const int r0 = LOWER ? b0 + 16 : 0, r1 = LOWER ? kBase : b0;
         for (int i = r0 + wave; i < r1; i += 4) {
             double dot = 0.0;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) dot = fma(Ts[i][b0 + j], xs[b0 + j][lane], dot);
+            for (int j = 0; j < 16; ++j) dot = fma(Ts[i][b0 + j], xb[j], dot);
             xs[i][lane] -= dot;
         }
         __syncthreads();

@@ -241,3 +241,13 @@ def test_trmm_trsm_argument_errors():
     assert trsm(L, 0, N, 4, 4, 1.0, big, 4, None, 4, None) == -9
     assert trsm(L, 0, N, 4, 4, 1.0, big, 4, big, 3, None) == -10
     assert trsm(L, 0, N, 0, 4, 1.0, None, 1, None, 4, None) == 0
+
+
+def test_potrf_argument_errors():
+    f = mm._lib.momms_potrf
+    big = 1 << 20
+    assert f(ord("L"), 4, big, 4, None, None) == -1
+    assert f(ord("U"), -1, big, 4, None, None) == -2
+    assert f(ord("U"), 4, None, 4, None, None) == -3
+    assert f(ord("U"), 4, big, 3, None, None) == -4
+    assert f(ord("U"), 0, None, 1, None, None) == 0

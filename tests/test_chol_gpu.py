@@ -1,0 +1,74 @@
+"""Cholesky factorization on the device against its plain definition
+(oracle/chol.py): residual bound, agreement with the row-by-row factor, exact
+integer factors, the untouched lower triangle, failing pivots, block edges."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import chol
+
+pytestmark = pytest.mark.gpu
+mm = pytest.importorskip("paper_1904_05717_amd")
+U53 = 2.0 ** -53
+
+
+def spd(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M = rng.uniform(-1, 1, (n, n))
+    return M @ M.T + n * np.eye(n)
+
+
+def factor(A):
+    P = np.triu(A) + np.tril(np.full(A.shape, np.nan), -1)   # the lower triangle must not be read
+    Ad = torch.from_numpy(P).to("cuda:0")
+    info = mm.potrf(Ad)
+    out = Ad.cpu().numpy()
+    assert np.isnan(np.tril(out, -1)[np.tril_indices(A.shape[0], -1)]).all()   # nor written
+    return np.triu(out), info
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 129, 300, 700])
+def test_factor_matches_definition(n):
+    A = spd(n, n)
+    U, info = factor(A)
+    assert info == 0
+    R = oracle.gemm(U.T.copy(), U, A, 1.0, -1.0)
+    assert np.all(np.abs(R) <= 4 * (n + 2) * U53 * (np.abs(U.T) @ np.abs(U) + np.abs(A)))
+    want, winfo = chol.potrf_upper(A)
+    assert winfo == 0
+    assert np.max(np.abs(U - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_integer_factor_exact():
+    n = 200
+    rng = np.random.Generator(np.random.PCG64(3))
+    Ut = np.triu(rng.integers(-1, 2, (n, n)).astype(np.float64), 1) + np.eye(n)
+    A = (Ut.T.astype(np.int64) @ Ut.astype(np.int64)).astype(np.float64)
+    assert np.abs(A).max() < 2 ** 20
+    U, info = factor(A)
+    assert info == 0
+    np.testing.assert_array_equal(U, Ut)
+
+
+@pytest.mark.parametrize("bad_row", [0, 37, 64, 150])
+def test_indefinite_reports_first_failing_pivot(bad_row):
+    n = 200
+    A = spd(n, 4)
+    # make the leading (bad_row + 1) minor indefinite and nothing earlier
+    A[bad_row, bad_row] = -abs(A[bad_row, bad_row]) - 1e6
+    U, info = factor(A)
+    _, want = chol.potrf_upper(A)
+    assert want == bad_row + 1
+    assert info == want
+
+
+def test_large_residual_sampled():
+    n = 2048
+    A = spd(n, 5)
+    U, info = factor(A)
+    assert info == 0
+    rows = np.array([0, 1, 63, 64, 1023, 1024, 2047])
+    R = oracle.gemm(U.T[rows].copy(), U, A[rows], 1.0, -1.0)
+    bound = 4 * (n + 2) * U53 * (np.abs(U.T[rows]) @ np.abs(U) + np.abs(A[rows]))
+    assert np.all(np.abs(R) <= bound)
