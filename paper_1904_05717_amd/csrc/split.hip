@@ -251,24 +251,34 @@ template <bool TRANSPOSED>
 __global__ __launch_bounds__(256) void k_residues(const double* __restrict__ P, int64_t ld, int64_t R, int64_t Cc,
                                                   const int* __restrict__ e, CrtParams cp,
                                                   int8_t* __restrict__ out, int64_t Rp, int64_t Cp) {
-    // 32 x 128 tiles: each row of a plane gets whole 128-byte lines.
-    __shared__ double tile[32][129];
+    // 32 x 128 tiles: each row of a plane gets whole 128-byte lines.  A
+    // stored row (TRANSPOSED = false) is already contiguous along c, so a
+    // thread reads its 16 values directly; the transposed side goes through
+    // LDS.
+    __shared__ double tile[TRANSPOSED ? 32 : 1][129];
     const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 128;
     const int tid = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int idx = tid + 256 * i;
-        int rr, cc;
-        if (TRANSPOSED) { cc = idx >> 5; rr = idx & 31; }
-        else            { rr = idx >> 7; cc = idx & 127; }
-        const int64_t gr = r0 + rr, gc = c0 + cc;
-        double v = 0.0;
-        if (gr < R && gc < Cc) v = TRANSPOSED ? P[gc * ld + gr] : P[gr * ld + gc];
-        tile[rr][cc] = v;
-    }
-    __syncthreads();
     const int rr = tid >> 3, cb = (tid & 7) * 16;
     const int64_t gr = r0 + rr;
+    double v16[16];
+    if (TRANSPOSED) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int idx = tid + 256 * i;
+            const int cc = idx >> 5, tr = idx & 31;
+            const int64_t g_r = r0 + tr, g_c = c0 + cc;
+            tile[tr][cc] = (g_r < R && g_c < Cc) ? P[g_c * ld + g_r] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v16[j] = tile[rr][cb + j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int64_t g_c = c0 + cb + j;
+            v16[j] = (gr < R && g_c < Cc) ? P[gr * ld + g_c] : 0.0;
+        }
+    }
     if (gr >= Rp) return;
     const int ee = gr < R ? exp_or_zero(e[gr]) : 0;
     // x = sum_i a_i 2^(12 i) with 12-bit limbs a_i of the sign of x
@@ -280,7 +290,7 @@ __global__ __launch_bounds__(256) void k_residues(const double* __restrict__ P, 
     float a[16][kCrtLimbs];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        double v = rint(ldexp(tile[rr][cb + j], cp.t - ee));
+        double v = rint(ldexp(v16[j], cp.t - ee));
 #pragma unroll
         for (int i = kCrtLimbs - 1; i >= 0; --i) {
             const double hi = trunc(ldexp(v, -12 * i));   // exact: v is an integer below 2^60
@@ -360,6 +370,7 @@ __global__ __launch_bounds__(256) void k_crt_combine(int64_t M, int64_t N, const
 #pragma unroll
             for (int c = 0; c < 7; ++c) acc[r][c] = 0u;
         }
+#pragma unroll 4
         for (int l = 0; l < cp.n; ++l) {
             const uint32_t w = *reinterpret_cast<const uint32_t*>(Rs + l * plane + (q4 * ldr + j) * 4);
 #pragma unroll
