@@ -42,6 +42,7 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
                                                   int64_t ldx, double* Y, int64_t ldy) {
     __shared__ double Ts[kBase][kBase + 1];
     __shared__ double xs[kBase][64];
+    __shared__ double rdiag[kBase];   // 1 / t_ii: the substitution multiplies
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // op(T) padded to 64 x 64 with the identity: rows beyond s solve to 0
     for (int e = tid; e < kBase * kBase; e += 256) {
@@ -55,6 +56,7 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
             v = 1.0;
         }
         Ts[i][j] = v;
+        if (i == j) rdiag[i] = 1.0 / v;
     }
     const int64_t col = (int64_t)blockIdx.x * 64 + lane;
     const bool live = col < n;   // dead lanes work on zeros and store nothing
@@ -92,11 +94,14 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
             for (int uu = 0; uu < 16; ++uu) {
                 const int u = LOWER ? uu : 15 - uu;
                 const int i = b0 + u;
-                double dot = 0.0;
+                double d0 = 0.0, d1 = 0.0;   // two chains: half the FMA latency
 #pragma unroll
-                for (int v = LOWER ? 0 : u + 1; v < (LOWER ? u : 16); ++v) dot = fma(Ts[i][b0 + v], xr[v], dot);
-                const double r = xr[u] - dot;
-                xr[u] = UNIT ? r : r / Ts[i][i];
+                for (int v = LOWER ? 0 : u + 1; v < (LOWER ? u : 16); ++v) {
+                    if ((v & 1) == 0) d0 = fma(Ts[i][b0 + v], xr[v], d0);
+                    else              d1 = fma(Ts[i][b0 + v], xr[v], d1);
+                }
+                const double r = xr[u] - (d0 + d1);
+                xr[u] = UNIT ? r : r * rdiag[i];
                 __builtin_amdgcn_sched_barrier(0);   // keep each row's LDS reads with its FMAs
             }
 #pragma unroll
@@ -109,10 +114,13 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
         for (int j = 0; j < 16; ++j) xb[j] = xs[b0 + j][lane];
         const int r0 = LOWER ? b0 + 16 : 0, r1 = LOWER ? kBase : b0;
         for (int i = r0 + wave; i < r1; i += 4) {
-            double dot = 0.0;
+            double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) dot = fma(Ts[i][b0 + j], xb[j], dot);
-            xs[i][lane] -= dot;
+            for (int j = 0; j < 16; j += 2) {
+                d0 = fma(Ts[i][b0 + j], xb[j], d0);
+                d1 = fma(Ts[i][b0 + j + 1], xb[j + 1], d1);
+            }
+            xs[i][lane] -= d0 + d1;
         }
         __syncthreads();
     }
