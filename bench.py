@@ -37,9 +37,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--member", default="AUTO")
     ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--shape", default=None,
+                    help="m,n,k for --profile-members / --summarize (default: the square --size)")
     ap.add_argument("--only", default="all",
                     choices=["all", "fp64", "split", "batch", "backward", "members", "tiled", "syrk", "tri",
-                             "ooc"])
+                             "ooc", "sweep"])
     ap.add_argument("--split", default="crt:14,crt:15,crt:16,int8:8,int8:9,bf16:3,bf16:4,bf16:5,bf16:6,bf16:7,"
                     "fp8:3,fp8:4,fp8:5,fp8:6,fp8:7,fp8:8",
                     help="split-precision configurations to time, as type:slices[,type:slices...]")
@@ -80,14 +82,24 @@ def copy_calibration():
           flush=True)
 
 
-def profile_members(size):
+def shape_of(args):
+    if args.shape:
+        m, n, k = (int(x) for x in args.shape.split(","))
+        return m, n, k
+    return args.size, args.size, args.size
+
+
+def shape_tag(m, n, k):
+    return str(m) if m == n == k else f"{m}x{n}x{k}"
+
+
+def profile_members(m, n, k):
     """Each member once (after one warm-up) with a 1-element fill between members."""
     import torch
 
     import paper_1904_05717_amd as mm
     import workloads
 
-    m = n = k = size
     A, B, C = workloads.gemm_operands(m, n, k)
     Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
     del A, B, C
@@ -117,7 +129,7 @@ def profile_members(size):
         order.append({"member": member + "/tiled", "launches": mm.member_plan(member, m, n, k)["launches"],
                       "packed": False})
         print(json.dumps({"profiled": order[-1]}), flush=True)
-    print(json.dumps({"profile_members": order, "size": size}), flush=True)
+    print(json.dumps({"profile_members": order, "shape": [m, n, k]}), flush=True)
 
 
 def cpu_baseline(m, n, k, target_s):
@@ -568,6 +580,62 @@ def bench_members(args):
     return res
 
 
+SWEEP_SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
+                (16384, 16384, 16384), (16384, 16384, 256), (16384, 256, 16384)]
+
+
+def bench_sweep(args):
+    """The FP64 sweep: square sizes 1024 .. 16384, the rank-k update
+    16384 x 16384 x 256 and the panel-panel product 16384 x 256 x 16384
+    (U[-1,1], beta = 1).  Every member after a warm-up, the fastest of up to
+    five calls (fewer when a call is long); the member AUTO picks; measured L2 traffic against the model where a stored traffic
+    profile of the same shape and kernels exists."""
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    out = []
+    for (m, n, k) in SWEEP_SHAPES:
+        A, B, C = workloads.gemm_operands(m, n, k)
+        Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
+        del A, B, C
+        traffic = {}
+        tj_path = os.path.join(ROOT, "profiles", f"traffic_f64_{shape_tag(m, n, k)}.json")
+        try:
+            tj = json.load(open(tj_path))
+            if tj.get("kernel_source_sha") == kernel_source_sha():
+                traffic = {mem: round(r["ratio"], 3) for mem, r in tj["members"].items()}
+        except (OSError, ValueError, KeyError):
+            pass
+        members = {}
+        for member in mm.FAMILY:
+            wsb = mm.workspace_size(m, n, k, member)
+            ws = torch.empty(wsb, dtype=torch.uint8, device="cuda:0") if wsb else None
+            mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
+            torch.cuda.synchronize()
+            times = []
+            while len(times) < 5 and sum(times) < 200.0:   # the fastest of up to 5 calls within ~0.2 s
+                e0, e1 = events()
+                e0.record()
+                mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = min(times)
+            members[member] = {"ms": round(ms, 3), "tflops": round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 2),
+                               "calls": len(times)}
+            if member in traffic:
+                members[member]["traffic_vs_model"] = traffic[member]
+            del ws
+        best = max(members, key=lambda x: members[x]["tflops"])
+        out.append({"m": m, "n": n, "k": k, "auto": mm.select_member(m, n, k), "best": best,
+                    "best_tflops": members[best]["tflops"], "members": members})
+        del Ad, Bd, Cd
+        torch.cuda.empty_cache()
+    return out
+
+
 def _csv_rows(path):
     import csv
     with open(path) as fh:
@@ -576,7 +644,7 @@ def _csv_rows(path):
     return rows
 
 
-def summarize(d, size=8192):
+def summarize(d, m=8192, n=8192, k=8192):
     """Profiles from a pass with these rocprofv3 runs (all from /tmp, TMPDIR=/tmp):
       kt_bench:      rocprofv3 --kernel-trace --stats -- python3 bench.py --profile
       fetch_members: rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --profile-members
@@ -616,9 +684,9 @@ def summarize(d, size=8192):
         wr = [r for r in W[2 * i + 1] if "momms" in r["Kernel_Name"]]
         fb = sum(float(r["Counter_Value"]) for r in fr) * 1024.0 * fscale
         wb = sum(float(r["Counter_Value"]) for r in wr) * 1024.0 * wscale
-        plan = mm.member_plan(member, size, size, size)
+        plan = mm.member_plan(member, m, n, k)
         launches = len([r for r in fr if "k_pack" not in r["Kernel_Name"]])
-        model = mm.model_bytes(member, size, size, size, beta=1.0, packed=plan["pack"] == 1)
+        model = mm.model_bytes(member, m, n, k, beta=1.0, packed=plan["pack"] == 1)
         mb = model["l2_read"] + model["l2_write"] + model["pack"]
         members[member] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_call": fb + wb,
                            "launches": launches, "bytes_per_launch": (fb + wb) / max(1, launches),
@@ -632,27 +700,30 @@ def summarize(d, size=8192):
         wr = [r for r in W[base + 2 * i + 1] if "momms" in r["Kernel_Name"]]
         fb = sum(float(r["Counter_Value"]) for r in fr) * 1024.0 * fscale
         wb = sum(float(r["Counter_Value"]) for r in wr) * 1024.0 * wscale
-        model = mm.model_bytes(member, size, size, size, beta=1.0, packed=False)
+        model = mm.model_bytes(member, m, n, k, beta=1.0, packed=False)
         mb = model["l2_read"] + model["l2_write"]
         members[member + "/tiled"] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_call": fb + wb,
                                       "launches": len(fr), "bytes_per_launch": (fb + wb) / max(1, len(fr)),
                                       "model_bytes": mb, "ratio": (fb + wb) / mb}
-    out = {"size": size, "kernel_source_sha": kernel_source_sha(), "fetch_scale": fscale, "write_scale": wscale,
+    tag = shape_tag(m, n, k)
+    sel = f"--size {m}" if m == n == k else f"--shape {m},{n},{k}"
+    out = {"size": m if m == n == k else None, "shape": [m, n, k], "kernel_source_sha": kernel_source_sha(),
+           "fetch_scale": fscale, "write_scale": wscale,
            "copy_fetch_bytes": fvals, "copy_write_bytes": wvals, "members": members}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(TRAFFIC_JSON, "w") as fh:
+    with open(os.path.join(ROOT, "profiles", f"traffic_f64_{tag}.json"), "w") as fh:
         json.dump(out, fh, indent=1)
-    lines = [f"# L2-to-fabric traffic of every family member, FP64 m=n=k={size}", "",
+    lines = [f"# L2-to-fabric traffic of every family member, FP64 m={m}, n={n}, k={k}", "",
              "Commands (run from /tmp with TMPDIR=/tmp; repo at /root/repo):", "",
              "    rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch_members -o run --output-format csv -- "
-             "python3 /root/repo/bench.py --profile-members --size 8192",
+             f"python3 /root/repo/bench.py --profile-members {sel}",
              "    rocprofv3 --pmc WRITE_SIZE -d <dir>/write_members -o run --output-format csv -- "
-             "python3 /root/repo/bench.py --profile-members --size 8192",
+             f"python3 /root/repo/bench.py --profile-members {sel}",
              "    rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch_copy -o run --output-format csv -- "
              "python3 /root/repo/bench.py --copy-calibration",
              "    rocprofv3 --pmc WRITE_SIZE -d <dir>/write_copy -o run --output-format csv -- "
              "python3 /root/repo/bench.py --copy-calibration",
-             "    python3 bench.py --summarize <dir>", "",
+             f"    python3 bench.py --summarize <dir> {sel}", "",
              f"Calibration on a plain 1 GiB device copy: FETCH_SIZE reads {1/fscale:.4f} of the bytes copied "
              f"(scale {fscale:.4f}), WRITE_SIZE {1/wscale:.4f} (scale {wscale:.4f}).", "",
              "| member | launches | fetch GB | write GB | measured GB | model GB | measured / model |",
@@ -664,10 +735,11 @@ def summarize(d, size=8192):
               "per-XCD L2s and the fabric; packing included for members that pack).  `/tiled` rows run the "
               "member on tile-major (\"prepacked\") operands (momms_gemm_tiled); the conversion is outside the "
               "measured call.", ""]
-    with open(os.path.join(ROOT, "profiles", f"traffic_f64_{size}.md"), "w") as fh:
+    with open(os.path.join(ROOT, "profiles", f"traffic_f64_{tag}.md"), "w") as fh:
         fh.write("\n".join(lines))
     ks = os.path.join(d, "kt_bench", "run_kernel_stats.csv")
-    if os.path.exists(ks):
+    if os.path.exists(ks) and m == n == k:
+        size = m
         import csv
         with open(ks) as fh:
             rows = list(csv.DictReader(fh))
@@ -687,7 +759,7 @@ def summarize(d, size=8192):
 def main():
     args = parse()
     if args.summarize:
-        summarize(args.summarize)
+        summarize(args.summarize, *shape_of(args))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -696,12 +768,13 @@ def main():
         copy_calibration()
         return
     if args.profile_members:
-        profile_members(args.size)
+        profile_members(*shape_of(args))
         return
     only = "fp64" if (args.profile and args.only == "all") else args.only
-    if only in ("split", "batch", "backward", "members", "tiled", "syrk", "tri", "ooc"):
+    if only in ("split", "batch", "backward", "members", "tiled", "syrk", "tri", "ooc", "sweep"):
         fn = {"split": bench_split, "batch": bench_batch, "backward": bench_backward, "members": bench_members,
-              "tiled": bench_tiled, "syrk": bench_syrk, "tri": bench_tri, "ooc": bench_ooc}[only]
+              "tiled": bench_tiled, "syrk": bench_syrk, "tri": bench_tri, "ooc": bench_ooc,
+              "sweep": bench_sweep}[only]
         print(json.dumps({only: fn(args)}), flush=True)
         return
     f = bench_fp64(args)
@@ -731,7 +804,7 @@ def main():
         out["split_precision"] = bench_split(args, fp64_ms=f["ms_per_step"])
         out["batched"] = bench_batch(args)
         out["backward"] = bench_backward(args)
-        out["members_8192"] = bench_members(args)
+        out["sweep"] = bench_sweep(args)
         out["tiled_storage"] = bench_tiled(args)
         out["syrk"] = bench_syrk(args)
         out["triangular"] = bench_tri(args)
