@@ -76,7 +76,6 @@ typedef unsigned __int128 u128;
 struct CrtParams {
     int n, t;
     int p[kMaxModuli];
-    double pd[kMaxModuli], invp[kMaxModuli];
     float ipf[kMaxModuli], pf[kMaxModuli];                      // 1/p, p
     float hif[kMaxModuli], lof[kMaxModuli];                     // (p - 1) / 2, -(p / 2): centred range
     float climb[kMaxModuli][5];                                 // 2^(12 i) mod p
@@ -946,8 +945,6 @@ static int crt_params(int N, int64_t k, CrtParams* cp) {
                 break;
             }
         const u128 W = Ml * (u128)inv;   // < M because inv < p
-        cp->pd[l] = (double)p;
-        cp->invp[l] = 1.0 / (double)p;
         cp->ipf[l] = 1.0f / (float)p;
         cp->pf[l] = (float)p;
         cp->hif[l] = (float)((p - 1) / 2);
