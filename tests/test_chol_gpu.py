@@ -72,3 +72,16 @@ def test_large_residual_sampled():
     R = oracle.gemm(U.T[rows].copy(), U, A[rows], 1.0, -1.0)
     bound = 4 * (n + 2) * U53 * (np.abs(U.T[rows]) @ np.abs(U) + np.abs(A[rows]))
     assert np.all(np.abs(R) <= bound)
+
+
+def test_leading_dimension_with_nan_gap():
+    n = 200
+    A = spd(n, 8)
+    big = np.full((n, n + 6), np.nan)
+    big[:, :n] = np.triu(A) + np.tril(np.full((n, n), np.nan), -1)
+    Ad = torch.from_numpy(big).to("cuda:0")
+    info = mm.potrf(Ad[:, :n])
+    out = Ad.cpu().numpy()
+    assert info == 0 and np.isnan(out[:, n:]).all()
+    want, _ = chol.potrf_upper(A)
+    assert np.max(np.abs(np.triu(out[:, :n]) - want)) <= 1e-12 * np.max(np.abs(want))

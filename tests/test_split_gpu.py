@@ -354,3 +354,30 @@ def test_crt_sampled_8192():
     exact = oracle.gemm_entries(A, B, rows, cols)
     absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
     assert np.max(np.abs(got[rows, cols] - exact) / absab) <= 1e-13
+
+
+@pytest.mark.parametrize("kind,S", [("bf16", 4), ("int8", 6), ("fp8", 6), ("crt", 14)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, True)])
+def test_split_leading_dimensions_with_nan_gaps(kind, S, ta, tb):
+    # operands and C are views into wider NaN-filled buffers: the gaps must be
+    # neither read (a NaN would spread) nor written
+    m, n, k = 150, 140, 130
+    A, B, C = workloads.gemm_operands(m, n, k, kind="loguniform")
+    if kind == "crt":
+        want = ce.crt_gemm(A, B, S, C, 2.0, 0.5)
+    else:
+        want = se.split_gemm(A, B, S, kind, C, 2.0, 0.5)
+    As = A.T.copy() if ta else A
+    Bs = B.T.copy() if tb else B
+    Abig = torch.full((As.shape[0], As.shape[1] + 7), float("nan"), dtype=torch.float64, device=DEV)
+    Bbig = torch.full((Bs.shape[0], Bs.shape[1] + 3), float("nan"), dtype=torch.float64, device=DEV)
+    Cbig = torch.full((m, n + 5), float("nan"), dtype=torch.float64, device=DEV)
+    Abig[:, :As.shape[1]] = dev(As)
+    Bbig[:, :Bs.shape[1]] = dev(Bs)
+    Cbig[:, :n] = dev(C)
+    mm.gemm_split(Abig[:, :As.shape[1]], Bbig[:, :Bs.shape[1]], Cbig[:, :n], alpha=2.0, beta=0.5, slices=S,
+                  slice_type=kind, transA=ta, transB=tb)
+    torch.cuda.synchronize()
+    got = Cbig.cpu().numpy()
+    np.testing.assert_array_equal(got[:, :n], want)
+    assert np.isnan(got[:, n:]).all(), "wrote outside the leading-dimension gap"

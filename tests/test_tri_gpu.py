@@ -133,3 +133,25 @@ def test_large_sampled_columns():
     T = tri.op_tri(A, "U", True)
     wc = tri.trmm(A, B[:, cols], "U", True, alpha=2.0)
     assert np.all(np.abs(C.cpu().numpy()[:, cols] - wc) <= 2 * (m + 2) * U * 2.0 * (np.abs(T) @ np.abs(B[:, cols])))
+
+
+def test_leading_dimensions_with_nan_gaps():
+    m, n = 150, 90
+    A = well_conditioned(m, 9)
+    B = np.random.Generator(np.random.PCG64(10)).uniform(-1, 1, (m, n))
+    Abig = torch.full((m, m + 5), float("nan"), dtype=torch.float64, device=DEV)
+    Abig[:, :m] = dev(A)
+    Bbig = torch.full((m, n + 3), float("nan"), dtype=torch.float64, device=DEV)
+    Bbig[:, :n] = dev(B)
+    Cbig = torch.full((m, n + 4), float("nan"), dtype=torch.float64, device=DEV)
+    mm.trmm(Abig[:, :m], Bbig[:, :n], Cbig[:, :n], uplo="U", trans=True)
+    mm.trsm(Abig[:, :m], Bbig[:, :n], uplo="L", trans=True, alpha=1.5)
+    torch.cuda.synchronize()
+    T = tri.op_tri(A, "U", True)
+    gc = Cbig.cpu().numpy()
+    assert np.all(np.abs(gc[:, :n] - tri.trmm(A, B, "U", True)) <= 2 * (m + 2) * U * (np.abs(T) @ np.abs(B)))
+    assert np.isnan(gc[:, n:]).all()
+    gb = Bbig.cpu().numpy()
+    want = tri.trsm(A, B, "L", True, alpha=1.5)
+    assert np.max(np.abs(gb[:, :n] - want)) <= 1e-12 * np.abs(want).max()
+    assert np.isnan(gb[:, n:]).all()
