@@ -11,8 +11,8 @@
 //
 // so the flops run as triangular solves and symmetric updates, which are
 // themselves family products.  Diagonal blocks of at most 64 rows are
-// factored by one workgroup in LDS (right-looking: pivot, scale the row,
-// update the trailing triangle).  info: 0, or the 1-based row of the first
+// factored by one wave with the block in registers (right-looking: publish
+// the pivot row, scale it, update the trailing triangle).  info: 0, or the 1-based row of the first
 // pivot that is not positive (the factorization goes on with NaNs past it).
 #include <hip/hip_runtime.h>
 
@@ -26,58 +26,46 @@ constexpr int kBase = 64;
 
 __global__ void k_set_zero(int* p) { *p = 0; }
 
-// Thread (ty, tx) of a 16 x 16 grid owns the entries (ty + 16 p, tx + 16 q)
-// of the 64 x 64 block, so no index arithmetic divides.
-__global__ __launch_bounds__(256) void k_potrf_base(int s, double* A, int64_t lda, int64_t row0, int* info) {
-    __shared__ double a[kBase][kBase + 1];
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+// One wave: lane j owns column j of the 64 x 64 block in registers (c[i] =
+// a_ij; rows below the diagonal hold values that are never written back).
+// Step k: every lane publishes its row-k entry to LDS, then with the pivot
+// d = a_kk, r = sqrt(d), lane j forms u_kj = a_kj / r and subtracts
+// u_ki u_kj (u_ki = a_ki / r from LDS) from its entries i > k.  An entry
+// below the diagonal only ever meets values below the diagonal, so no
+// masking is needed.  The padded block is the identity.
+__global__ __launch_bounds__(64) void k_potrf_base(int s, double* A, int64_t lda, int64_t row0, int* info) {
+    __shared__ double rowbuf[kBase];
+    const int j = threadIdx.x;
+    double c[kBase];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = ty + 16 * p, j = tx + 16 * q;
-            a[i][j] = (i <= j && j < s) ? A[(int64_t)i * lda + j] : 0.0;
-        }
-    __syncthreads();
-    // Step k updates the trailing triangle with the unscaled pivot row,
-    // a_ij -= a_ki a_kj / a_kk, and scales row k - 1 (read by nobody in step
-    // k): one barrier per step.  Thread 0 alone tracks the first bad pivot.
+    for (int i = 0; i < kBase; ++i) c[i] = (i <= j && j < s) ? A[(int64_t)i * lda + j] : (i == j ? 1.0 : 0.0);
     int bad = 0;
-    double dprev = 1.0;
-    for (int k = 0; k <= s; ++k) {
-        if (k > 0) {   // row k - 1 becomes u: u_kk = sqrt(d), u_kj = a_kj / sqrt(d)
-            const double r = sqrt(dprev);
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = ty + 16 * p, j = tx + 16 * q;
-                    if (i == k - 1 && j >= i) a[i][j] = j == i ? r : a[i][j] / r;
-                }
-        }
-        if (k == s) break;
-        const double d = a[k][k];
-        if (tid == 0 && !(d > 0.0) && bad == 0) bad = k + 1;
-        const double inv = 1.0 / d;
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = ty + 16 * p, j = tx + 16 * q;
-                if (i > k && i <= j) a[i][j] = fma(-a[k][i] * inv, a[k][j], a[i][j]);
-            }
-        dprev = d;
+#pragma clang loop unroll(full)
+    for (int k = 0; k < kBase; ++k) {   // fully unrolled: c stays in registers
+        rowbuf[j] = c[k];
         __syncthreads();
-    }
-    __syncthreads();
+        const double d = rowbuf[k];
+        if (j == 0 && k < s && !(d > 0.0) && bad == 0) bad = k + 1;
+        const double r = sqrt(d), rinv = 1.0 / r;
+        const double ukj = j == k ? r : c[k] * rinv;
+#pragma clang loop unroll(full)
+        for (int i0 = k + 1; i0 < kBase; i0 += 8) {   // eight rows at a time keep the loads bounded
+            double ui[8];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u < kBase) ui[u] = rowbuf[i0 + u];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = ty + 16 * p, j = tx + 16 * q;
-            if (i <= j && j < s) A[(int64_t)i * lda + j] = a[i][j];
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u < kBase) c[i0 + u] = fma(-(ui[u] * rinv), ukj, c[i0 + u]);
+            __builtin_amdgcn_sched_barrier(0);
         }
-    if (tid == 0 && bad != 0 && info != nullptr) atomicCAS(info, 0, (int)(row0 + bad));
+        c[k] = ukj;
+        __syncthreads();   // the next step rewrites rowbuf
+    }
+#pragma unroll
+    for (int i = 0; i < kBase; ++i)
+        if (i <= j && j < s) A[(int64_t)i * lda + j] = c[i];
+    if (j == 0 && bad != 0 && info != nullptr) atomicCAS(info, 0, (int)(row0 + bad));
 }
 
 static inline int64_t split_point(int64_t s) {
@@ -87,7 +75,7 @@ static inline int64_t split_point(int64_t s) {
 
 static int rec(int64_t r0, int64_t s, double* A, int64_t lda, int* info, hipStream_t st) {
     if (s <= kBase) {
-        hipLaunchKernelGGL(k_potrf_base, dim3(1), dim3(256), 0, st, (int)s, A + r0 * lda + r0, lda, r0, info);
+        hipLaunchKernelGGL(k_potrf_base, dim3(1), dim3(64), 0, st, (int)s, A + r0 * lda + r0, lda, r0, info);
         const hipError_t e = hipGetLastError();
         return e == hipSuccess ? 0 : (int)e;
     }

@@ -45,18 +45,20 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
     __shared__ double rdiag[kBase];   // 1 / t_ii: the substitution multiplies
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // op(T) padded to 64 x 64 with the identity: rows beyond s solve to 0
+    // consecutive threads read consecutive stored columns b of row a of A;
+    // op(T)(i, j) = T(a, b) with (i, j) = (a, b), or (b, a) when transposed
     for (int e = tid; e < kBase * kBase; e += 256) {
-        const int i = e / kBase, j = e % kBase;
+        const int a = e / kBase, b = e % kBase;
+        const int i = trans ? b : a, j = trans ? a : b;
         double v = 0.0;
-        if (i < s && j < s) {
-            const int a = trans ? j : i, b = trans ? i : j;   // op(T)(i, j) = T(a, b)
+        if (a < s && b < s) {
             const bool in = upper_stored ? a <= b : a >= b;
             if (in) v = (a == b && UNIT) ? 1.0 : A[(int64_t)a * lda + b];
-        } else if (i == j) {
+        } else if (a == b) {
             v = 1.0;
         }
         Ts[i][j] = v;
-        if (i == j) rdiag[i] = 1.0 / v;
+        if (a == b) rdiag[i] = 1.0 / v;
     }
     const int64_t col = (int64_t)blockIdx.x * 64 + lane;
     const bool live = col < n;   // dead lanes work on zeros and store nothing
