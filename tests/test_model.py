@@ -9,11 +9,14 @@ independent brute-force simulation and the paper's printed numbers.
   save transfers.
 * Belady's optimal replacement never needs more than the model and never
   fewer than the I/O lower bound of Sec. 2.1, 2mnk/sqrt(M) - 2M reads.
-* The paper's analysed intensities (Sec. 5.2): Goto's algorithm with
-  k_c = 192, n_c = 3000 reaches 23.26 flop/byte and B3A2C0 with a 768 x 768
-  block 64 flop/byte; the balanced blocksizes of Sec. 2.4.
+* The paper's analysed intensities (Sec. 5.2, kept in
+  tests/golden/paper_section5_2.json): Goto's algorithm with k_c = 192,
+  n_c = 3000 reaches 23.26 flop/byte and B3A2C0 with a 768 x 768 block
+  64 flop/byte; the balanced blocksizes of Sec. 2.4.
 """
+import json
 import math
+import os
 
 import pytest
 
@@ -75,11 +78,19 @@ def intensity(res, b1, b2, scale=200):
     return 2.0 * m * n * k / (8.0 * sum(c.values()))
 
 
+GOLDEN = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                     "paper_section5_2.json")))
+
+
 def test_paper_intensities():
     # Goto: the B panel k_c x n_c sits in L3 and the rest streams -> Resident B
-    assert intensity("B", 192, 3000) == pytest.approx(23.26, abs=0.01)
+    g = GOLDEN["goto_blocksizes"]
+    want = GOLDEN["goto_intensity_flop_per_byte"]
+    assert intensity("B", g["k_c"], g["n_c"]) == pytest.approx(want["value"], abs=0.5 * 10 ** -want["digits"])
     # B3A2C0: 768 x 768 block of B in L3
-    assert intensity("B", 768, 768) == pytest.approx(64.0, rel=2e-3)
+    b = GOLDEN["b3a2c0_blocks"]["l3_block_of_B"]
+    want = GOLDEN["b3a2c0_intensity_flop_per_byte"]
+    assert intensity("B", b, b) == pytest.approx(want["value"], rel=2e-3)
     # derived the same way: C3A2C0 (624 x 624 block of C) and C4A2C0 (3600)
     assert intensity("C", 624, 624) == pytest.approx(78.0, rel=2e-3)
     assert intensity("C", 3600, 3600) == pytest.approx(450.0, rel=2e-3)
