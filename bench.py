@@ -293,13 +293,33 @@ def bench_split(args, fp64_ms=None):
                      "slice_products": pairs, "lowp_tops": round(lowp, 1),
                      "lowp_frac_of_peak": round(lowp / LOWP_MFMA_PEAK_TOPS[t], 4),
                      "max_rel_err_vs_absAB": float(rel.max()), "median_rel_err_vs_absAB": float(np.median(rel))})
-    ok = [r for r in runs if r["max_rel_err_vs_absAB"] <= 1e-13]
+    # Every entry, not a sample: against the 16-moduli modular product (t = 55
+    # at k = 8192; its own error, sampled against the oracle above, is near
+    # 1e-16 of |A||B|) with |A||B| from the FP64 product of the absolute values.
+    full = None
+    if not args.profile and mm.crt_bits(k, 16)[0] is not None:
+        wsr = torch.empty(mm.split_workspace_size(m, n, k, 16, "crt"), dtype=torch.uint8, device="cuda:0")
+        ref = mm.gemm_split(Ad, Bd, torch.empty_like(C), slices=16, slice_type="crt", workspace=wsr)
+        del wsr
+        absab_d = mm.gemm(Ad.abs(), Bd.abs(), torch.empty_like(C))
+        ref_err = float((np.abs(ref[rows, cols].cpu().numpy() - exact) / absab).max())
+        for r in runs:
+            mm.gemm_split(Ad, Bd, C, slices=r["slices"], slice_type=r["slice_type"], workspace=ws)
+            diff = (C - ref).abs_()
+            r["max_rel_err_all_entries"] = float(torch.where(absab_d > 0, diff / absab_d, diff).max().item())
+            del diff
+        full = {"entries": m * n, "reference": "16-moduli modular product",
+                "reference_max_rel_err_on_sample": ref_err}
+        del ref, absab_d
+    ok = [r for r in runs if r["max_rel_err_vs_absAB"] <= 1e-13 and r.get("max_rel_err_all_entries", 0.0) <= 1e-13]
     best = min(ok, key=lambda r: r["ms"]) if ok else None
     return {"workload": f"m=n=k={m}, sign uniform, magnitude 10^U(-8,8), beta=0",
             "fp64_ms": round(fp64_ms, 3), "runs": runs,
             "fastest_within_1e-13": None if best is None else {key: best[key] for key in (
-                "slice_type", "slices", "ms", "speedup_vs_fp64", "max_rel_err_vs_absAB")},
-            "error_sample": "256 entries against the compensated FP64 oracle"}
+                "slice_type", "slices", "ms", "speedup_vs_fp64", "max_rel_err_vs_absAB") + (
+                ("max_rel_err_all_entries",) if "max_rel_err_all_entries" in best else ())},
+            "error_sample": "256 entries against the compensated FP64 oracle",
+            "error_all_entries": full}
 
 
 def bench_tiled(args):
