@@ -1,7 +1,7 @@
 """Benchmark of the MOMMS FP64 GEMM family on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--member NAME] [--size N]
-                    [--only fp64|split|batch|backward|members|tiled|syrk]
+                    [--only fp64|split|batch|backward|members|tiled|syrk|tri|ooc|sweep|lowbw]
 
 A step is one C := A B + C product in FP64 at m = n = k = 8192 (uniform
 [-1, 1] entries, beta = 1 with random C) by the selected family member
@@ -12,8 +12,10 @@ prediction next to the rocprofv3-measured traffic, the CPU oracle timed on a
 bounded sample, and the other forms of the method measured on their own
 workloads: the split-precision product (m = n = k = 8192, 16-decade data,
 speedup over the FP64 product and its error), 512 batched uneven problems,
-forward + hand-written backward at m = 4096, k = 8192, n = 2048, and every
-family member at 8192.
+forward + hand-written backward at m = 4096, k = 8192, n = 2048, every
+family member over square and shaped problems, tile-major storage, SYRK,
+TRSM/TRMM/Cholesky, the out-of-core level, and every member beside a kernel
+that takes HBM bandwidth (the varying-bandwidth experiments).
 """
 import argparse
 import json
@@ -41,7 +43,7 @@ def parse():
                     help="m,n,k for --profile-members / --summarize (default: the square --size)")
     ap.add_argument("--only", default="all",
                     choices=["all", "fp64", "split", "batch", "backward", "members", "tiled", "syrk", "tri",
-                             "ooc", "sweep"])
+                             "ooc", "sweep", "lowbw"])
     ap.add_argument("--split", default="crt:14,crt:15,crt:16,int8:8,int8:9,bf16:3,bf16:4,bf16:5,bf16:6,bf16:7,"
                     "fp8:3,fp8:4,fp8:5,fp8:6,fp8:7,fp8:8",
                     help="split-precision configurations to time, as type:slices[,type:slices...]")
@@ -600,6 +602,100 @@ def bench_members(args):
     return res
 
 
+LOWBW_SHAPES = [(4096, 4096, 4096), (8192, 8192, 8192), (16384, 16384, 256), (16384, 256, 16384)]
+LOWBW_WIDTHS = [32, 64, 128]
+
+
+def bench_lowbw(args):
+    """Low-bandwidth emulation (the varying-bandwidth experiments of Sec. 5).
+    Every family member runs alone, beside the streaming kernel on G whole
+    compute units, and beside its sleeping control on the same G compute
+    units (G = 32, 64, 128; both reserve the units the same way).  The
+    control's time is the member on 256 - G compute units at full bandwidth;
+    stream / sleep is what the bandwidth taken costs it.  The streamer's own
+    rate is measured alone (20 ms) and over each run.  Best of two calls per
+    condition; hipEvents on the product's stream."""
+    import time
+
+    import torch
+
+    import paper_1904_05717_amd as mm
+    import workloads
+
+    dev = torch.device("cuda:0")
+    hog_stream = torch.cuda.Stream(device=dev)
+    reps = 1 if args.profile else 2
+    hogs = {}
+    alone_rate = {}
+    for g in LOWBW_WIDTHS:
+        hogs[(g, "sleep")] = mm.BandwidthHog(g, "sleep", device=dev, stream=hog_stream)
+        hogs[(g, "stream")] = mm.BandwidthHog(g, "stream", nbytes=4 << 30, device=dev, stream=hog_stream)
+    s = hogs[(LOWBW_WIDTHS[0], "sleep")].concurrent_stream()   # a product stream on another hardware queue
+    for g in LOWBW_WIDTHS:
+        h = hogs[(g, "stream")]
+        h.start(max_seconds=5.0)
+        time.sleep(0.02)
+        h.stop(s)
+        alone_rate[g] = round(h.report()["GBps"], 1)
+
+    def run(member, A, B, C, ws, hog):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if hog is not None:
+            hog.start(max_seconds=5.0)
+            time.sleep(0.005)
+        try:
+            with torch.cuda.stream(s):
+                if hog is not None:
+                    hog.mark(s)
+                e0.record(s)
+                mm.gemm(A, B, C, 1.0, 1.0, member=member, workspace=ws, stream=s)
+                e1.record(s)
+        finally:
+            if hog is not None:
+                hog.stop(s)
+        rep = hog.report() if hog is not None else None
+        s.synchronize()
+        return e0.elapsed_time(e1), rep
+
+    out = {"widths": LOWBW_WIDTHS, "streamer_alone_GBps": alone_rate, "shapes": []}
+    for (m, n, k) in LOWBW_SHAPES:
+        A, B, C = workloads.gemm_operands(m, n, k)
+        Ad, Bd, Cd = (torch.from_numpy(x).to(dev) for x in (A, B, C))
+        del A, B, C
+        flops = 2.0 * m * n * k
+        rows = {}
+        for member in mm.FAMILY:
+            wsb = mm.workspace_size(m, n, k, member)
+            ws = torch.empty(wsb, dtype=torch.uint8, device=dev) if wsb else None
+            run(member, Ad, Bd, Cd, ws, None)
+            row = {"alone_ms": round(min(run(member, Ad, Bd, Cd, ws, None)[0] for _ in range(reps)), 3)}
+            for g in LOWBW_WIDTHS:
+                t_sleep = min(run(member, Ad, Bd, Cd, ws, hogs[(g, "sleep")])[0] for _ in range(reps))
+                best, rate, covered = None, None, True
+                for _ in range(reps):
+                    t, rep = run(member, Ad, Bd, Cd, ws, hogs[(g, "stream")])
+                    covered = covered and rep["covered"] and not rep["timed_out"]
+                    if best is None or t < best:
+                        best, rate = t, rep["GBps"]
+                row[str(g)] = {"sleep_ms": round(t_sleep, 3), "stream_ms": round(best, 3),
+                               "slowdown": round(best / t_sleep, 3),
+                               "tflops_stream": round(flops / (best * 1e-3) / 1e12, 2),
+                               "streamer_GBps": round(rate, 1), "covered": covered}
+            mb = mm.model_bytes(member, m, n, k, beta=1.0)
+            row["model_hbm_gb"] = round((mb["hbm_read"] + mb["hbm_write"]) / 1e9, 2)
+            row["model_l2_gb"] = round((mb["l2_read"] + mb["l2_write"]) / 1e9, 2)
+            rows[member] = row
+            del ws
+        order = {"alone": sorted(rows, key=lambda x: rows[x]["alone_ms"])[:3]}
+        for g in LOWBW_WIDTHS:
+            order[f"sleep_{g}"] = sorted(rows, key=lambda x: rows[x][str(g)]["sleep_ms"])[:3]
+            order[f"stream_{g}"] = sorted(rows, key=lambda x: rows[x][str(g)]["stream_ms"])[:3]
+        out["shapes"].append({"m": m, "n": n, "k": k, "members": rows, "fastest_three": order})
+        del Ad, Bd, Cd
+        torch.cuda.empty_cache()
+    return out
+
+
 SWEEP_SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
                 (16384, 16384, 16384), (16384, 16384, 256), (16384, 256, 16384)]
 
@@ -791,10 +887,10 @@ def main():
         profile_members(*shape_of(args))
         return
     only = "fp64" if (args.profile and args.only == "all") else args.only
-    if only in ("split", "batch", "backward", "members", "tiled", "syrk", "tri", "ooc", "sweep"):
+    if only in ("split", "batch", "backward", "members", "tiled", "syrk", "tri", "ooc", "sweep", "lowbw"):
         fn = {"split": bench_split, "batch": bench_batch, "backward": bench_backward, "members": bench_members,
               "tiled": bench_tiled, "syrk": bench_syrk, "tri": bench_tri, "ooc": bench_ooc,
-              "sweep": bench_sweep}[only]
+              "sweep": bench_sweep, "lowbw": bench_lowbw}[only]
         print(json.dumps({only: fn(args)}), flush=True)
         return
     f = bench_fp64(args)
@@ -829,6 +925,10 @@ def main():
         out["syrk"] = bench_syrk(args)
         out["triangular"] = bench_tri(args)
         out["out_of_core"] = bench_ooc(args)
+        try:
+            out["low_bandwidth"] = bench_lowbw(args)
+        except Exception as exc:   # the section reports its failure; the line above still stands
+            out["low_bandwidth"] = {"error": repr(exc)}
     if not args.no_cpu and not args.profile:
         out["cpu_baseline"] = cpu_baseline(args.size, args.size, args.size, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -403,6 +403,52 @@ int momms_gemm_ooc(int64_t m, int64_t n, int64_t k, double alpha, const double *
                    int64_t mb, int64_t nb, int64_t kb, int family_member,
                    void *workspace, size_t ws_bytes, momms_stream_t stream, momms_stream_t copy_stream);
 
+/* ---------------------------------------------------------------------
+ * Low-bandwidth emulation: the varying-bandwidth experiments of Sec. 5
+ * ("Experimental setup"; Goto's algorithm against B3A2C0 and C4A2C0 as the
+ * bandwidth to main memory drops).  The paper lowered the memory clock and
+ * channel count; here a streaming kernel on its own stream takes HBM bandwidth
+ * while a product runs on another stream.
+ *
+ * momms_lowbw_start enqueues that kernel on `stream`: `workgroups` workgroups
+ * of 1024 threads, each holding all of one compute unit's LDS, so no product
+ * workgroup shares a compute unit with it (1 <= workgroups <= the number of
+ * compute units; multiples of 8 spread it evenly over the XCDs).  mode 0
+ * streams `buf` (device memory, 16-byte aligned, at least
+ * momms_lowbw_min_bytes(workgroups) bytes, best well above the 256 MiB MALL)
+ * with non-temporal 16-byte loads, each wave round after round over its own
+ * contiguous share; it never writes `buf`.  mode 1 holds the same compute
+ * units asleep and reads nothing (buf may be NULL): the control that leaves
+ * the bandwidth and takes the same compute units.  Every workgroup polls
+ * *flag (a device 64-bit word, by atomic add: it counts the polls) every 8
+ * rounds and leaves its loop when the stop bit (bit 63) is set, when
+ * max_seconds (0 < max_seconds <= 60) of wall clock have passed since it
+ * started, or after max_rounds rounds (rounded up to a multiple of 8).
+ * The call clears *flag on `stream`, waits on the host for that
+ * clear and for `stream`'s earlier work, then enqueues the kernel and
+ * returns; run the product on another stream, then momms_lowbw_stop.
+ * rec (device, momms_lowbw_record_words(workgroups) words) receives, for
+ * each wave w, rec[4w] = rounds done (momms_lowbw_round_bytes() bytes each
+ * in mode 0), rec[4w+1] = a checksum of what it read, rec[4w+2] and
+ * rec[4w+3] = the wall clock (momms_lowbw_clock_hz() ticks per second) when
+ * it started and stopped.  Errors: -1 mode, -2 buf (missing or unaligned),
+ * -3 bytes too small, -4 workgroups, -5 flag, -6 rec, -7 max_seconds,
+ * -8 max_rounds; positive HIP errors. */
+size_t momms_lowbw_min_bytes(int workgroups);
+size_t momms_lowbw_record_words(int workgroups);
+int64_t momms_lowbw_round_bytes(void);
+int64_t momms_lowbw_clock_hz(void);
+int momms_lowbw_start(int mode, const void *buf, size_t bytes, int workgroups, unsigned long long *flag,
+                      unsigned long long *rec, double max_seconds, int64_t max_rounds, momms_stream_t stream);
+/* Enqueue on `stream` a one-thread kernel that writes the wall clock to *stamp
+ * (device, may be NULL) and then sets the stop bit of *flag by atomic or: the
+ * streamer's workgroups see it at their next poll and leave.  Errors: -1
+ * flag; positive HIP errors. */
+int momms_lowbw_stop(unsigned long long *flag, unsigned long long *stamp, momms_stream_t stream);
+/* Enqueue a one-thread kernel that writes the wall clock to *stamp, to mark
+ * where a product starts.  Errors: -1 stamp; positive HIP errors. */
+int momms_lowbw_stamp(unsigned long long *stamp, momms_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

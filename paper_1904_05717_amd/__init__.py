@@ -416,3 +416,108 @@ def balanced_block(M, beta_b, beta_c):
     check_status(_lib.momms_balanced_block(float(M), float(beta_b), float(beta_c), ctypes.byref(mc),
                                            ctypes.byref(kc)), "momms_balanced_block")
     return mc.value, kc.value
+
+
+class BandwidthHog:
+    """The streaming kernel of the low-bandwidth experiments (Sec. 5), on a stream of its own.
+
+    `workgroups` compute units are taken whole (all of their LDS).  mode
+    "stream" reads a device buffer of `nbytes` with non-temporal loads, taking
+    HBM bandwidth from a product run beside it; mode "sleep" takes the same
+    compute units and reads nothing, the control.  Use:
+
+        s = hog.concurrent_stream()
+        hog.start(); hog.mark(s); <product on stream s>; hog.stop(s); hog.report()
+
+    start() waits on the host for the hog stream's earlier work; the waves
+    leave at stop(), after max_seconds, or after max_rounds rounds.
+    """
+
+    def __init__(self, workgroups, mode="stream", nbytes=4 << 30, device="cuda:0", stream=None):
+        if mode not in ("stream", "sleep"):
+            raise ValueError("mode is 'stream' or 'sleep'")
+        self.workgroups, self.mode = int(workgroups), mode
+        self.device = torch.device(device)
+        need = _lib.momms_lowbw_min_bytes(self.workgroups)
+        if need == 0:
+            raise ValueError("workgroups must be positive")
+        self.buf = None
+        if mode == "stream":
+            if nbytes < need:
+                raise ValueError(f"the buffer needs at least {need} bytes for {workgroups} workgroups")
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.flag = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.rec = torch.zeros(_lib.momms_lowbw_record_words(self.workgroups), dtype=torch.int64, device=self.device)
+        self.stamps = torch.zeros(2, dtype=torch.int64, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.max_seconds = None
+
+    def concurrent_stream(self, tries=8, wait_s=0.05):
+        """A new stream whose work runs while this hog's stream is busy.
+
+        HIP multiplexes streams onto a few hardware queues, and two streams on
+        one queue run one after the other: a product enqueued there would start
+        only after the hog had ended.  Each candidate stream is tried beside a
+        short sleeping hog (one workgroup, at most 0.25 s): it is kept if a
+        stamp enqueued on it completes while that hog still runs."""
+        import time
+        for _ in range(tries):
+            cand = torch.cuda.Stream(device=self.device)
+            torch.cuda.current_stream(self.device).synchronize()
+            check_status(_lib.momms_lowbw_start(1, None, 0, 1, self.flag.data_ptr(), self.rec.data_ptr(), 0.25,
+                                                1 << 40, self.stream.cuda_stream), "momms_lowbw_start")
+            check_status(_lib.momms_lowbw_stamp(self.stamps.data_ptr(), cand.cuda_stream), "momms_lowbw_stamp")
+            ev = torch.cuda.Event()
+            ev.record(cand)
+            t0, ok = time.perf_counter(), False
+            while time.perf_counter() - t0 < wait_s:
+                if ev.query():
+                    ok = True
+                    break
+                time.sleep(0.0005)
+            check_status(_lib.momms_lowbw_stop(self.flag.data_ptr(), None, cand.cuda_stream), "momms_lowbw_stop")
+            self.stream.synchronize()
+            cand.synchronize()
+            if ok:
+                return cand
+        raise MommsError("no stream found whose work runs beside the hog's stream")
+
+    def start(self, max_seconds=5.0, max_rounds=1 << 40):
+        buf_ptr = self.buf.data_ptr() if self.buf is not None else None
+        nbytes = self.buf.numel() if self.buf is not None else 0
+        self.rec.zero_()
+        self.stamps.zero_()
+        torch.cuda.current_stream(self.device).synchronize()   # the clears above, before the hog stream starts
+        self.max_seconds = float(max_seconds)
+        check_status(_lib.momms_lowbw_start(0 if self.mode == "stream" else 1, buf_ptr, nbytes, self.workgroups,
+                                            self.flag.data_ptr(), self.rec.data_ptr(), self.max_seconds,
+                                            int(max_rounds), self.stream.cuda_stream), "momms_lowbw_start")
+
+    def mark(self, stream=None):
+        """Stamp the wall clock on `stream` where the product starts."""
+        check_status(_lib.momms_lowbw_stamp(self.stamps.data_ptr(), _stream_handle(stream)), "momms_lowbw_stamp")
+
+    def stop(self, stream=None):
+        """Enqueue the stop on `stream` (after the product)."""
+        check_status(_lib.momms_lowbw_stop(self.flag.data_ptr(), self.stamps.data_ptr() + 8, _stream_handle(stream)),
+                     "momms_lowbw_stop")
+
+    def report(self):
+        """Wait for the hog; its rounds, bytes, rate and whether it covered mark() .. stop()."""
+        self.stream.synchronize()
+        torch.cuda.synchronize(self.device)
+        hz = float(_lib.momms_lowbw_clock_hz())
+        rec = self.rec.view(-1, 4).cpu()
+        mark, stop = (int(x) for x in self.stamps.cpu())
+        rounds, t0, t1 = rec[:, 0], rec[:, 2], rec[:, 3]
+        nbytes = int(rounds.sum()) * _lib.momms_lowbw_round_bytes() if self.mode == "stream" else 0
+        span = (int(t1.max()) - int(t0.min())) / hz
+        return {
+            "mode": self.mode, "workgroups": self.workgroups, "waves": int(rec.shape[0]),
+            "mark": mark, "stop": stop, "start_first": int(t0.min()), "start_last": int(t0.max()),
+            "end_first": int(t1.min()), "end_last": int(t1.max()), "clock_hz": hz,
+            "bytes": nbytes, "seconds": span, "GBps": nbytes / span / 1e9 if span > 0 else 0.0,
+            "min_rounds": int(rounds.min()),
+            "covered": bool(mark > 0 and stop > 0 and int(t0.max()) <= mark and int(t1.min()) >= stop),
+            "timed_out": bool((t1 - t0).max() / hz >= 0.99 * self.max_seconds),
+        }

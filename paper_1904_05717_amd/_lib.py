@@ -94,6 +94,13 @@ momms_ooc_workspace_size = _fn("momms_ooc_workspace_size", sz, [i64, i64, i64])
 momms_gemm_ooc = _fn("momms_gemm_ooc", i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i64, i64, i64, i32,
                                              vp, sz, vp, vp])
 momms_syrk = _fn("momms_syrk", i32, [i32, i32, i64, i64, dbl, vp, i64, dbl, vp, i64, i32, vp])
+momms_lowbw_min_bytes = _fn("momms_lowbw_min_bytes", sz, [i32])
+momms_lowbw_record_words = _fn("momms_lowbw_record_words", sz, [i32])
+momms_lowbw_round_bytes = _fn("momms_lowbw_round_bytes", i64, [])
+momms_lowbw_clock_hz = _fn("momms_lowbw_clock_hz", i64, [])
+momms_lowbw_start = _fn("momms_lowbw_start", i32, [i32, vp, sz, i32, vp, vp, dbl, i64, vp])
+momms_lowbw_stop = _fn("momms_lowbw_stop", i32, [vp, vp, vp])
+momms_lowbw_stamp = _fn("momms_lowbw_stamp", i32, [vp, vp])
 
 EXPORTS = [
     "momms_gemm", "momms_gemm_ex", "momms_workspace_size", "momms_set_stream", "momms_num_members",
@@ -103,6 +110,8 @@ EXPORTS = [
     "momms_model_resident", "momms_balanced_block", "momms_set_member_table", "momms_select_member_prior",
     "momms_tiled_size", "momms_to_tiled", "momms_from_tiled", "momms_gemm_tiled", "momms_syrk", "momms_crt_bits",
     "momms_ooc_workspace_size", "momms_gemm_ooc", "momms_trmm", "momms_trsm", "momms_potrf",
+    "momms_lowbw_min_bytes", "momms_lowbw_record_words", "momms_lowbw_round_bytes", "momms_lowbw_clock_hz",
+    "momms_lowbw_start", "momms_lowbw_stop", "momms_lowbw_stamp",
 ]
 
 

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmomms.so")
-SOURCES = ["gemm_f64.hip", "split.hip", "batch.hip", "tiled.hip", "syrk.hip", "tri.hip", "chol.hip", "ooc.hip", "plan.cpp"]
+SOURCES = ["gemm_f64.hip", "split.hip", "batch.hip", "tiled.hip", "syrk.hip", "tri.hip", "chol.hip", "ooc.hip", "lowbw.hip", "plan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -251,3 +251,27 @@ def test_potrf_argument_errors():
     assert f(ord("U"), 4, None, 4, None, None) == -3
     assert f(ord("U"), 4, big, 3, None, None) == -4
     assert f(ord("U"), 0, None, 1, None, None) == 0
+
+
+def test_lowbw_sizes_and_argument_errors():
+    L = mm._lib
+    assert L.momms_lowbw_round_bytes() == 16384
+    assert L.momms_lowbw_min_bytes(4) == 4 * 16 * 16384 and L.momms_lowbw_min_bytes(0) == 0
+    assert L.momms_lowbw_record_words(4) == 4 * 16 * 4 and L.momms_lowbw_record_words(-1) == 0
+    f = L.momms_lowbw_start
+    buf, flag, rec = 1 << 20, 1 << 21, 1 << 22    # never dereferenced: every case fails its checks first
+    need = L.momms_lowbw_min_bytes(8)
+    assert f(2, buf, need, 8, flag, rec, 1.0, 100, None) == -1
+    assert f(0, None, need, 8, flag, rec, 1.0, 100, None) == -2
+    assert f(0, buf + 8, need, 8, flag, rec, 1.0, 100, None) == -2
+    assert f(0, buf, need - 1, 8, flag, rec, 1.0, 100, None) == -3
+    assert f(0, buf, need, 0, flag, rec, 1.0, 100, None) == -4
+    assert f(0, buf, need, 8, None, rec, 1.0, 100, None) == -5
+    assert f(1, None, 0, 8, flag, None, 1.0, 100, None) == -6
+    assert f(1, None, 0, 8, flag, rec, 0.0, 100, None) == -7
+    assert f(1, None, 0, 8, flag, rec, 61.0, 100, None) == -7
+    assert f(1, None, 0, 8, flag, rec, 1.0, 0, None) == -8
+    assert L.momms_lowbw_stop(None, None, None) == -1
+    assert L.momms_lowbw_stamp(None, None) == -1
+    with pytest.raises(ValueError):
+        mm.BandwidthHog(8, mode="copy")
