@@ -369,8 +369,8 @@ int momms_trsm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha
  * over the upper triangle of the row-major n x n device matrix A (the
  * memory layout of LAPACK's column-major lower factor); the strictly lower
  * triangle is never read or written.  Recursive halving onto momms_trsm and
- * momms_syrk; diagonal blocks of at most 64 rows are factored in LDS by one
- * workgroup.  info (device int, may be NULL) is set to 0, or to the 1-based
+ * momms_syrk; diagonal blocks of at most 128 rows are factored in registers
+ * by one workgroup.  info (device int, may be NULL) is set to 0, or to the 1-based
  * row of the first pivot that is not positive (A not positive definite; the
  * factorization continues with NaNs past it); read it after the stream has
  * drained.  Errors: -1 uplo, -2 n, -3 A, -4 lda (< n); codes of momms_trsm

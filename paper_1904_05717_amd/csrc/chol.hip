@@ -10,9 +10,9 @@
 //                      U22 = chol(A22)
 //
 // so the flops run as triangular solves and symmetric updates, which are
-// themselves family products.  Diagonal blocks of at most 64 rows are
-// factored by one wave with the block in registers (right-looking: publish
-// the pivot row, scale it, update the trailing triangle).  info: 0, or the 1-based row of the first
+// themselves family products.  Diagonal blocks of at most 128 rows are
+// factored by one workgroup with the block in registers (right-looking:
+// publish the pivot row, scale it, update the trailing triangle).  info: 0, or the 1-based row of the first
 // pivot that is not positive (the factorization goes on with NaNs past it).
 #include <hip/hip_runtime.h>
 
@@ -22,60 +22,103 @@
 namespace momms {
 namespace chol {
 
-constexpr int kBase = 64;
+constexpr int kBase = 128;   // diagonal blocks factored by one kernel
+constexpr int kLeaf = 64;    // the recursion still splits at multiples of 64
 
 __global__ void k_set_zero(int* p) { *p = 0; }
 
-// One wave: lane j owns column j of the 64 x 64 block in registers (c[i] =
-// a_ij; rows below the diagonal hold values that are never written back).
-// Step k: every lane publishes its row-k entry to LDS, then with the pivot
-// d = a_kk, r = sqrt(d), lane j forms u_kj = a_kj / r and subtracts
-// u_ki u_kj (u_ki = a_ki / r from LDS) from its entries i > k.  An entry
-// below the diagonal only ever meets values below the diagonal, so no
-// masking is needed.  The padded block is the identity.
-__global__ __launch_bounds__(64) void k_potrf_base(int s, double* A, int64_t lda, int64_t row0, int* info) {
-    __shared__ double rowbuf[kBase];
-    const int j = threadIdx.x;
-    double c[kBase];
-#pragma unroll
-    for (int i = 0; i < kBase; ++i) c[i] = (i <= j && j < s) ? A[(int64_t)i * lda + j] : (i == j ? 1.0 : 0.0);
-    int bad = 0;
-#pragma clang loop unroll(full)
-    for (int k = 0; k < kBase; ++k) {   // fully unrolled: c stays in registers
-        rowbuf[j] = c[k];
-        __syncthreads();
-        const double d = rowbuf[k];
-        if (j == 0 && k < s && !(d > 0.0) && bad == 0) bad = k + 1;
-        const double r = sqrt(d), rinv = 1.0 / r;
-        const double ukj = j == k ? r : c[k] * rinv;
-#pragma clang loop unroll(full)
-        for (int i0 = k + 1; i0 < kBase; i0 += 8) {   // eight rows at a time keep the loads bounded
-            double ui[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i0 + u < kBase) ui[u] = rowbuf[i0 + u];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i0 + u < kBase) c[i0 + u] = fma(-(ui[u] * rinv), ukj, c[i0 + u]);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        c[k] = ukj;
-        __syncthreads();   // the next step rewrites rowbuf
-    }
-#pragma unroll
-    for (int i = 0; i < kBase; ++i)
-        if (i <= j && j < s) A[(int64_t)i * lda + j] = c[i];
-    if (j == 0 && bad != 0 && info != nullptr) atomicCAS(info, 0, (int)(row0 + bad));
+// 1 / sqrt(d) from the hardware estimate and two Newton steps (each squares
+// the relative error), and sqrt(d) = d / sqrt(d).
+__device__ __forceinline__ void rsqrt_sqrt(double d, double& rinv, double& r) {
+    double y = __builtin_amdgcn_rsq(d);
+    double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    rinv = y;
+    r = d * y;
 }
 
-static inline int64_t split_point(int64_t s) {
-    const int64_t h = ((s / 2 + kBase - 1) / kBase) * kBase;
-    return h < s ? h : s - kBase;
+// The update of one wave at pivot K: rows LO .. LO+R-1 of column J are in
+// c[0 .. R-1].  u_kJ = a_kJ / sqrt(a_kk) (sqrt(a_kk) on the diagonal), and
+// a_iJ -= a_ki u_kJ / sqrt(a_kk) for the rows i > K.  K is a constant once
+// the caller's loop is unrolled, which keeps c in registers.
+template <int LO, int R>
+__device__ __forceinline__ void pivot_update(double (&c)[64], const double* row, int J, int K, int s, int& bad) {
+    // every LDS read of the step first: the pivot, this lane's entry of row K
+    // and the entries a_ki of the rows i > K this wave holds
+    const double d = row[K], akj = row[J];
+    double a[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+        if (LO + i > K) a[i] = row[LO + i];
+    if (K < s && !(d > 0.0) && bad == 0) bad = K + 1;
+    double rinv, r;
+    rsqrt_sqrt(d, rinv, r);
+    const double ukj = J == K ? r : akj * rinv;
+    if (K >= LO && K < LO + R) c[K - LO] = ukj;
+    const double sc = ukj * rinv;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+        if (LO + i > K) c[i] = fma(-a[i], sc, c[i]);
+}
+
+// A diagonal block of order s <= 128 factored by one workgroup of four waves,
+// the block in registers: wave 0 holds rows 0..63 of columns 0..63, wave 1
+// rows 0..63 of columns 64..127, waves 2 and 3 rows 64..95 and 96..127 of
+// columns 64..127 (lane j owns one column).  Entries below the diagonal are
+// carried along and never written back; the padded block is the identity.
+// Row k is published by the wave that holds it, into one of two alternating
+// row buffers, so one barrier per pivot suffices.
+__global__ __launch_bounds__(256) void k_potrf_base(int s, double* A, int64_t lda, int64_t row0, int* info) {
+    __shared__ double rowbuf[2][kBase];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int J = wave == 0 ? lane : 64 + lane;
+    const int lo = wave < 2 ? 0 : (wave == 2 ? 64 : 96);
+    const int nr = wave < 2 ? 64 : 32;
+    double c[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        const int row = lo + i;
+        const bool in = i < nr && row <= J && J < s;
+        const double v = A[in ? (int64_t)row * lda + J : 0];
+        c[i] = in ? v : (row == J ? 1.0 : 0.0);
+    }
+    int bad = 0;
+#pragma clang loop unroll(full)
+    for (int K = 0; K < kBase; ++K) {
+        double* row = rowbuf[K & 1];
+        if (K < 64) {
+            if (wave < 2) row[J] = c[K];
+        } else if (K < 96) {
+            if (wave == 2) row[J] = c[K - 64];
+        } else {
+            if (wave == 3) row[J] = c[K - 96];
+        }
+        __syncthreads();
+        if (wave < 2)
+            pivot_update<0, 64>(c, row, J, K, s, bad);
+        else if (wave == 2)
+            pivot_update<64, 32>(c, row, J, K, s, bad);
+        else
+            pivot_update<96, 32>(c, row, J, K, s, bad);
+    }
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        const int row = lo + i;
+        if (i < nr && row <= J && J < s) A[(int64_t)row * lda + J] = c[i];
+    }
+    if (threadIdx.x == 0 && bad != 0 && info != nullptr) atomicCAS(info, 0, (int)(row0 + bad));
+}
+
+static inline int64_t split_point(int64_t s) {   // s > kBase: a multiple of kLeaf in (0, s)
+    const int64_t h = ((s / 2 + kLeaf - 1) / kLeaf) * kLeaf;
+    return h < s ? h : s - kLeaf;
 }
 
 static int rec(int64_t r0, int64_t s, double* A, int64_t lda, int* info, hipStream_t st) {
     if (s <= kBase) {
-        hipLaunchKernelGGL(k_potrf_base, dim3(1), dim3(64), 0, st, (int)s, A + r0 * lda + r0, lda, r0, info);
+        hipLaunchKernelGGL(k_potrf_base, dim3(1), dim3(256), 0, st, (int)s, A + r0 * lda + r0, lda, r0, info);
         const hipError_t e = hipGetLastError();
         return e == hipSuccess ? 0 : (int)e;
     }

@@ -44,25 +44,41 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
     __shared__ double xs[kBase][64];
     __shared__ double rdiag[kBase];   // 1 / t_ii: the substitution multiplies
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // op(T) padded to 64 x 64 with the identity: rows beyond s solve to 0
-    // consecutive threads read consecutive stored columns b of row a of A;
-    // op(T)(i, j) = T(a, b) with (i, j) = (a, b), or (b, a) when transposed
-    for (int e = tid; e < kBase * kBase; e += 256) {
-        const int a = e / kBase, b = e % kBase;
-        const int i = trans ? b : a, j = trans ? a : b;
-        double v = 0.0;
-        if (a < s && b < s) {
-            const bool in = upper_stored ? a <= b : a >= b;
-            if (in) v = (a == b && UNIT) ? 1.0 : A[(int64_t)a * lda + b];
-        } else if (a == b) {
-            v = 1.0;
-        }
-        Ts[i][j] = v;
-        if (a == b) rdiag[i] = 1.0 / v;
+    // op(T) padded to 64 x 64 with the identity: rows beyond s solve to 0.
+    // Consecutive threads read consecutive stored columns b of row a of A;
+    // op(T)(i, j) = T(a, b) with (i, j) = (a, b), or (b, a) when transposed.
+    // Every load is issued before any is used: an entry outside the triangle
+    // (or past s) reads A[0] and is replaced by 0 or 1 afterwards, so the 16
+    // loads of T and the 16 of X per thread are all in flight at once.
+    constexpr int kPer = kBase * kBase / 256;
+    double tv[kPer], xv[kBase / 4];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = tid + 256 * q, a = e / kBase, b = e % kBase;
+        const bool read = a < s && b < s && (upper_stored ? a <= b : a >= b) && !(UNIT && a == b);
+        tv[q] = A[read ? (int64_t)a * lda + b : 0];
     }
     const int64_t col = (int64_t)blockIdx.x * 64 + lane;
     const bool live = col < n;   // dead lanes work on zeros and store nothing
-    for (int i = wave; i < kBase; i += 4) xs[i][lane] = (live && i < s) ? X[(int64_t)i * ldx + col] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kBase / 4; ++q) {
+        const int i = wave + 4 * q;
+        xv[q] = X[(live && i < s) ? (int64_t)i * ldx + col : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = tid + 256 * q, a = e / kBase, b = e % kBase;
+        const int i = trans ? b : a, j = trans ? a : b;
+        const bool read = a < s && b < s && (upper_stored ? a <= b : a >= b) && !(UNIT && a == b);
+        const double v = read ? tv[q] : (a == b ? 1.0 : 0.0);
+        Ts[i][j] = v;
+        if (a == b) rdiag[i] = 1.0 / v;
+    }
+#pragma unroll
+    for (int q = 0; q < kBase / 4; ++q) {
+        const int i = wave + 4 * q;
+        xs[i][lane] = (live && i < s) ? xv[q] : 0.0;
+    }
     __syncthreads();
     if (MODE == 1) {
         double acc[16];
@@ -88,23 +104,39 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
         const int kb = LOWER ? q : 3 - q;   // block in solve order
         const int b0 = 16 * kb;
         if (wave == 0) {
-            // the block's 16 unknowns in registers: only the FMAs form a chain
-            double xr[16];
+            // The block's 16 unknowns in registers, solved right-looking: at
+            // pivot u, x_u = b_u / t_uu, then x_u is subtracted from the rows
+            // after u.  The pivot's column of T comes from LDS one step ahead,
+            // so a step waits only on its own multiply and FMAs.
+            double xr[16], rd[16], tc[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) xr[u] = xs[b0 + u][lane];
+            for (int u = 0; u < 16; ++u) {
+                xr[u] = xs[b0 + u][lane];
+                rd[u] = rdiag[b0 + u];
+            }
+            {
+                const int u = LOWER ? 0 : 15;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) tc[i] = Ts[b0 + i][b0 + u];
+            }
 #pragma unroll
             for (int uu = 0; uu < 16; ++uu) {
                 const int u = LOWER ? uu : 15 - uu;
-                const int i = b0 + u;
-                double d0 = 0.0, d1 = 0.0;   // two chains: half the FMA latency
+                double tn[16];
+                if (uu < 15) {
+                    const int un = LOWER ? u + 1 : u - 1;
 #pragma unroll
-                for (int v = LOWER ? 0 : u + 1; v < (LOWER ? u : 16); ++v) {
-                    if ((v & 1) == 0) d0 = fma(Ts[i][b0 + v], xr[v], d0);
-                    else              d1 = fma(Ts[i][b0 + v], xr[v], d1);
+                    for (int i = 0; i < 16; ++i) tn[i] = Ts[b0 + i][b0 + un];
                 }
-                const double r = xr[u] - (d0 + d1);
-                xr[u] = UNIT ? r : r * rdiag[i];
-                __builtin_amdgcn_sched_barrier(0);   // keep each row's LDS reads with its FMAs
+                const double x = UNIT ? xr[u] : xr[u] * rd[u];
+                xr[u] = x;
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (LOWER ? i > u : i < u) xr[i] = fma(-tc[i], x, xr[i]);
+                __builtin_amdgcn_sched_barrier(0);   // one pivot at a time: the loads stay one step ahead
+                if (uu < 15)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) tc[i] = tn[i];
             }
 #pragma unroll
             for (int u = 0; u < 16; ++u) xs[b0 + u][lane] = xr[u];
