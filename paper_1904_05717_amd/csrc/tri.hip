@@ -28,86 +28,63 @@ namespace tri {
 
 constexpr int kBase = 64;   // rows of a diagonal block handled by the base kernel
 
-// MODE 0: solve (x := op(T)^-1 x), 1: multiply (y := alpha op(T) x, written to Y).
-// LOWER: op(T) is lower triangular.  A workgroup takes 64 columns with four
-// waves; lane c owns column c, held at xs[i][c] (lanes read consecutive
-// words).  Multiply: wave w forms rows 16w .. 16w+15, sixteen independent
-// sums.  Solve: blocked substitution over four 16-row blocks in solve
-// order; wave 0 runs the substitution inside a block (only the block's own
-// columns of op(T) remain to subtract), then all waves subtract that block's
-// contribution from the rows after it.
-template <int MODE, bool LOWER, bool UNIT>
-__global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double* __restrict__ A, int64_t lda,
-                                                  bool trans, bool upper_stored, double alpha, double* X,
-                                                  int64_t ldx, double* Y, int64_t ldy) {
-    __shared__ double Ts[kBase][kBase + 1];
-    __shared__ double xs[kBase][64];
-    __shared__ double rdiag[kBase];   // 1 / t_ii: the substitution multiplies
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // op(T) padded to 64 x 64 with the identity: rows beyond s solve to 0.
-    // Consecutive threads read consecutive stored columns b of row a of A;
-    // op(T)(i, j) = T(a, b) with (i, j) = (a, b), or (b, a) when transposed.
-    // Every load is issued before any is used: an entry outside the triangle
-    // (or past s) reads A[0] and is replaced by 0 or 1 afterwards, so the 16
-    // loads of T and the 16 of X per thread are all in flight at once.
-    constexpr int kPer = kBase * kBase / 256;
-    double tv[kPer], xv[kBase / 4];
+// The 64 x 64 block of op(T) at op rows R0.., columns C0.. of the s x s
+// triangle (A points at its first entry).  Stored entries are read with
+// consecutive threads on consecutive stored columns b of a stored row a; the
+// op entry is (i, j) = (a, b), or (b, a) when transposed.  Loads and LDS
+// stores are split so a kernel can issue every load before it uses any: an
+// entry outside the triangle or past s reads A[0] and is replaced by 0 (1 on
+// the diagonal past s, and on the diagonal when UNIT).
+struct OpBlock {
+    int sa0, sb0;   // the stored block's first row and column
+};
+
+__device__ __forceinline__ OpBlock op_block_at(bool trans, int R0, int C0) {
+    return trans ? OpBlock{C0, R0} : OpBlock{R0, C0};
+}
+
+template <bool UNIT>
+__device__ __forceinline__ bool op_read(int ga, int gb, int s, bool upper_stored) {
+    return ga < s && gb < s && (upper_stored ? ga <= gb : ga >= gb) && !(UNIT && ga == gb);
+}
+
+template <bool UNIT>
+__device__ __forceinline__ void op_load(double (&tv)[16], const double* A, int64_t lda, int s, bool upper_stored,
+                                        OpBlock blk, int tid) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int e = tid + 256 * q, a = e / kBase, b = e % kBase;
-        const bool read = a < s && b < s && (upper_stored ? a <= b : a >= b) && !(UNIT && a == b);
-        tv[q] = A[read ? (int64_t)a * lda + b : 0];
+    for (int q = 0; q < 16; ++q) {
+        const int e = tid + 256 * q, ga = blk.sa0 + e / kBase, gb = blk.sb0 + e % kBase;
+        tv[q] = A[op_read<UNIT>(ga, gb, s, upper_stored) ? (int64_t)ga * lda + gb : 0];
     }
-    const int64_t col = (int64_t)blockIdx.x * 64 + lane;
-    const bool live = col < n;   // dead lanes work on zeros and store nothing
+}
+
+template <bool UNIT>
+__device__ __forceinline__ void op_store(double (*Ts)[kBase + 1], double* rdiag, const double (&tv)[16], int s,
+                                         bool trans, bool upper_stored, OpBlock blk, int tid) {
 #pragma unroll
-    for (int q = 0; q < kBase / 4; ++q) {
-        const int i = wave + 4 * q;
-        xv[q] = X[(live && i < s) ? (int64_t)i * ldx + col : 0];
-    }
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int e = tid + 256 * q, a = e / kBase, b = e % kBase;
+    for (int q = 0; q < 16; ++q) {
+        const int e = tid + 256 * q, a = e / kBase, b = e % kBase, ga = blk.sa0 + a, gb = blk.sb0 + b;
         const int i = trans ? b : a, j = trans ? a : b;
-        const bool read = a < s && b < s && (upper_stored ? a <= b : a >= b) && !(UNIT && a == b);
-        const double v = read ? tv[q] : (a == b ? 1.0 : 0.0);
+        const double v = op_read<UNIT>(ga, gb, s, upper_stored) ? tv[q] : (ga == gb ? 1.0 : 0.0);
         Ts[i][j] = v;
-        if (a == b) rdiag[i] = 1.0 / v;
+        if (rdiag != nullptr && ga == gb) rdiag[i] = 1.0 / v;
     }
-#pragma unroll
-    for (int q = 0; q < kBase / 4; ++q) {
-        const int i = wave + 4 * q;
-        xs[i][lane] = (live && i < s) ? xv[q] : 0.0;
-    }
-    __syncthreads();
-    if (MODE == 1) {
-        double acc[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-        const int i0 = 16 * wave;
-        // op(T) lower: row i uses j <= i; upper: j >= i.  Columns outside a
-        // row's range hold zeros in Ts, so the loop bounds only trim work.
-        const int j0 = LOWER ? 0 : i0, j1 = LOWER ? i0 + 16 : kBase;
-        for (int j = j0; j < j1; ++j) {
-            const double xj = xs[j][lane];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = fma(Ts[i0 + r][j], xj, acc[r]);
-        }
-        if (live)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (i0 + r < s) Y[(int64_t)(i0 + r) * ldy + col] = alpha * acc[r];
-        return;
-    }
+}
+
+// Solve the 64-row block of op(T) in Ts (1 / diagonal in rdiag) against the
+// 64 columns in xs, in place: four 16-row blocks in solve order.  Wave 0 works
+// each 16-row block right-looking in registers (x_u = b_u / t_uu, then x_u is
+// subtracted from the block's later rows, the next pivot's column of op(T)
+// read from LDS one step ahead); then all four waves subtract the block from
+// the rows still to solve.  Callers synchronize before; it ends synchronized.
+template <bool LOWER, bool UNIT>
+__device__ __forceinline__ void solve_block(const double (*Ts)[kBase + 1], const double* rdiag, double (*xs)[64],
+                                            int lane, int wave) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int kb = LOWER ? q : 3 - q;   // block in solve order
         const int b0 = 16 * kb;
         if (wave == 0) {
-            // The block's 16 unknowns in registers, solved right-looking: at
-            // pivot u, x_u = b_u / t_uu, then x_u is subtracted from the rows
-            // after u.  The pivot's column of T comes from LDS one step ahead,
-            // so a step waits only on its own multiply and FMAs.
             double xr[16], rd[16], tc[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
@@ -158,6 +135,59 @@ __global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double
         }
         __syncthreads();
     }
+}
+
+// MODE 0: solve (x := op(T)^-1 x), 1: multiply (y := alpha op(T) x, written to Y).
+// LOWER: op(T) is lower triangular.  A workgroup takes 64 columns with four
+// waves; lane c owns column c, held at xs[i][c] (lanes read consecutive
+// words).  Multiply: wave w forms rows 16w .. 16w+15, sixteen independent
+// sums.  Solve: solve_block.  All 32 loads per thread (16 of op(T), 16 of
+// x) are in flight before the first is used.
+template <int MODE, bool LOWER, bool UNIT>
+__global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double* __restrict__ A, int64_t lda,
+                                                  bool trans, bool upper_stored, double alpha, double* X,
+                                                  int64_t ldx, double* Y, int64_t ldy) {
+    __shared__ double Ts[kBase][kBase + 1];
+    __shared__ double xs[kBase][64];
+    __shared__ double rdiag[kBase];   // 1 / t_ii: the substitution multiplies
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const OpBlock blk = op_block_at(trans, 0, 0);
+    double tv[16], xv[16];
+    op_load<UNIT>(tv, A, lda, s, upper_stored, blk, tid);
+    const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = col < n;   // dead lanes work on zeros and store nothing
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = wave + 4 * q;
+        xv[q] = X[(live && i < s) ? (int64_t)i * ldx + col : 0];
+    }
+    op_store<UNIT>(Ts, rdiag, tv, s, trans, upper_stored, blk, tid);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = wave + 4 * q;
+        xs[i][lane] = (live && i < s) ? xv[q] : 0.0;
+    }
+    __syncthreads();
+    if (MODE == 1) {
+        double acc[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+        const int i0 = 16 * wave;
+        // op(T) lower: row i uses j <= i; upper: j >= i.  Columns outside a
+        // row's range hold zeros in Ts, so the loop bounds only trim work.
+        const int j0 = LOWER ? 0 : i0, j1 = LOWER ? i0 + 16 : kBase;
+        for (int j = j0; j < j1; ++j) {
+            const double xj = xs[j][lane];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = fma(Ts[i0 + r][j], xj, acc[r]);
+        }
+        if (live)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (i0 + r < s) Y[(int64_t)(i0 + r) * ldy + col] = alpha * acc[r];
+        return;
+    }
+    solve_block<LOWER, UNIT>(Ts, rdiag, xs, lane, wave);
     if (live)
         for (int i = wave; i < s; i += 4) X[(int64_t)i * ldx + col] = xs[i][lane];
 }

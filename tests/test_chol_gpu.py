@@ -28,7 +28,7 @@ def factor(A):
     return np.triu(out), info
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 129, 300, 700])
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 96, 127, 128, 129, 192, 257, 300, 700])
 def test_factor_matches_definition(n):
     A = spd(n, n)
     U, info = factor(A)
@@ -51,7 +51,7 @@ def test_integer_factor_exact():
     np.testing.assert_array_equal(U, Ut)
 
 
-@pytest.mark.parametrize("bad_row", [0, 37, 64, 150])
+@pytest.mark.parametrize("bad_row", [0, 37, 64, 100, 127, 128, 150])
 def test_indefinite_reports_first_failing_pivot(bad_row):
     n = 200
     A = spd(n, 4)

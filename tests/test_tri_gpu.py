@@ -102,7 +102,7 @@ def test_alpha_zero_and_empty():
     mm.trmm(dev(np.zeros((0, 0))), E, dev(np.zeros((0, 5))))
 
 
-@pytest.mark.parametrize("m", [1, 63, 64, 65, 129])
+@pytest.mark.parametrize("m", [1, 63, 64, 65, 96, 127, 128, 129, 192, 257])
 def test_block_edges(m):
     n = 33
     A = well_conditioned(m, 5)
@@ -116,6 +116,20 @@ def test_block_edges(m):
     assert np.max(np.abs(Bd.cpu().numpy() - want)) <= 1e-12 * max(1.0, np.abs(want).max())
     T = tri.op_tri(A, "L")
     assert np.all(np.abs(C.cpu().numpy() - tri.trmm(A, B, "L")) <= 2 * (m + 2) * U * (np.abs(T) @ np.abs(B)))
+
+
+@pytest.mark.parametrize("uplo,trans,diag", COMBOS)
+@pytest.mark.parametrize("m", [65, 100, 128])
+def test_two_block_solve_every_combination(m, uplo, trans, diag):
+    """Solves just past one diagonal block: two blocks and the product between them."""
+    n = 70
+    A = well_conditioned(m, 11)
+    B = np.random.Generator(np.random.PCG64(12)).uniform(-1, 1, (m, n))
+    Bd = dev(B)
+    mm.trsm(dev(A), Bd, alpha=0.5, uplo=uplo, trans=trans, diag=diag)
+    torch.cuda.synchronize()
+    want = tri.trsm(A, B, uplo, trans, diag, alpha=0.5)
+    assert np.max(np.abs(Bd.cpu().numpy() - want)) <= 1e-12 * max(1.0, np.abs(want).max())
 
 
 def test_large_sampled_columns():
