@@ -604,6 +604,7 @@ def bench_members(args):
 
 LOWBW_SHAPES = [(4096, 4096, 4096), (8192, 8192, 8192), (16384, 16384, 256), (16384, 256, 16384)]
 LOWBW_WIDTHS = [32, 64, 128]
+LOWBW_CURVE = {"size": 8192, "members": ["A2C0", "B3A2C0", "C4A2C0", "C3C0"], "widths": [16, 48, 96, 160, 192]}
 
 
 def bench_lowbw(args):
@@ -614,7 +615,10 @@ def bench_lowbw(args):
     control's time is the member on 256 - G compute units at full bandwidth;
     stream / sleep is what the bandwidth taken costs it.  The streamer's own
     rate is measured alone (20 ms) and over each run.  Best of two calls per
-    condition; hipEvents on the product's stream."""
+    condition; hipEvents on the product's stream.  `curve`: Goto, B3A2C0,
+    C4A2C0 and C3C0 at 8192^3 over more streamer widths (one streaming call
+    each at the extra widths), the analogue of the paper's performance
+    against bandwidth."""
     import time
 
     import torch
@@ -658,6 +662,7 @@ def bench_lowbw(args):
         return e0.elapsed_time(e1), rep
 
     out = {"widths": LOWBW_WIDTHS, "streamer_alone_GBps": alone_rate, "shapes": []}
+    curve = {}   # member -> width -> (sleep_ms, stream_ms, streamer GB/s), filled at the curve's size
     for (m, n, k) in LOWBW_SHAPES:
         A, B, C = workloads.gemm_operands(m, n, k)
         Ad, Bd, Cd = (torch.from_numpy(x).to(dev) for x in (A, B, C))
@@ -681,6 +686,21 @@ def bench_lowbw(args):
                                "slowdown": round(best / t_sleep, 3),
                                "tflops_stream": round(flops / (best * 1e-3) / 1e12, 2),
                                "streamer_GBps": round(rate, 1), "covered": covered}
+            if (m, n, k) == (LOWBW_CURVE["size"],) * 3 and member in LOWBW_CURVE["members"]:
+                pts = {}
+                for g in LOWBW_CURVE["widths"]:
+                    hs = mm.BandwidthHog(g, "sleep", device=dev, stream=hog_stream)
+                    hr = mm.BandwidthHog(g, "stream", nbytes=4 << 30, device=dev, stream=hog_stream)
+                    t_sleep = min(run(member, Ad, Bd, Cd, ws, hs)[0] for _ in range(reps))
+                    t, rep = run(member, Ad, Bd, Cd, ws, hr)
+                    pts[str(g)] = {"sleep_ms": round(t_sleep, 3), "stream_ms": round(t, 3),
+                                   "slowdown": round(t / t_sleep, 3), "streamer_GBps": round(rep["GBps"], 1),
+                                   "covered": rep["covered"] and not rep["timed_out"]}
+                    del hs, hr
+                for g in LOWBW_WIDTHS:
+                    pts[str(g)] = {key: row[str(g)][key] for key in ("sleep_ms", "stream_ms", "slowdown",
+                                                                      "streamer_GBps", "covered")}
+                curve[member] = {str(g): pts[str(g)] for g in sorted(int(x) for x in pts)}
             mb = mm.model_bytes(member, m, n, k, beta=1.0)
             row["model_hbm_gb"] = round((mb["hbm_read"] + mb["hbm_write"]) / 1e9, 2)
             row["model_l2_gb"] = round((mb["l2_read"] + mb["l2_write"]) / 1e9, 2)
@@ -691,6 +711,8 @@ def bench_lowbw(args):
             order[f"sleep_{g}"] = sorted(rows, key=lambda x: rows[x][str(g)]["sleep_ms"])[:3]
             order[f"stream_{g}"] = sorted(rows, key=lambda x: rows[x][str(g)]["stream_ms"])[:3]
         out["shapes"].append({"m": m, "n": n, "k": k, "members": rows, "fastest_three": order})
+        if curve and "curve" not in out:
+            out["curve"] = {"m": m, "n": n, "k": k, "members": curve}
         del Ad, Bd, Cd
         torch.cuda.empty_cache()
     return out
