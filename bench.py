@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6
 LOWP_MFMA_PEAK_TOPS = {"bf16": 2500.0, "fp8": 5000.0, "int8": 5000.0, "crt": 5000.0}   # dense, per the MI355X specification
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_f64_8192.json")
-TILED_MEMBERS = ["C0", "C3C0", "B3C0", "A3C0", "A2C0"]
+TILED_MEMBERS = ["C0", "C3C0", "B3C0", "A3C0", "A2C0", "B3A2C0", "C3A2C0", "C4A2C0"]
 
 
 def parse():
@@ -234,12 +234,17 @@ def bench_fp64(args):
 
 
 def kernel_source_sha():
-    """Hash of the FP64 kernel sources (row-major and tiled): stored traffic is only used while it matches."""
+    """Hash of the FP64 kernel sources (row-major and tiled) without their
+    comments: stored traffic is only used while it matches."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("kernels_f64.hip", "gemm_f64.hip", "sched.h", "tiled.hip"):
-        with open(os.path.join(ROOT, "paper_1904_05717_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1904_05717_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(text.encode())
     return h.hexdigest()[:16]
 
 

@@ -12,11 +12,14 @@
 //      every 16 x 128 k-slab is contiguous (Goto's packed B panel, for the
 //      whole matrix).
 //
-// Rows and columns beyond the matrix, and k beyond k, are zero.  The C tile
-// stays in registers over all of k exactly as in the row-major kernel, with
-// the same k stagger, so for a given member the result is bitwise the one
-// the row-major path computes; only the loads differ (one pointer per thread
-// stepping through contiguous slabs, no edge predicates).
+// Rows and columns beyond the matrix, and k beyond k, are zero.  The
+// register-resident members keep the C tile in registers over all of k
+// exactly as in the row-major kernel, with the same k stagger; Goto, B3A2C0,
+// C3A2C0 and C4A2C0 run the LDS-resident A-block kernel with their row-major
+// loop nests, B read in place from the column panels.  So for a given member
+// the result is bitwise the one the row-major path computes; only the loads
+// differ (one pointer per thread stepping through contiguous slabs, no edge
+// predicates).
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -205,7 +208,26 @@ static void launch(const TArgs& a, int tile, int64_t s0, int64_t s1, double beta
                            a.kp, a.alpha, a.At, a.Bt, beta, a.C, a.ldc, s);
 }
 
-// The loop nests of the register-resident members, as in the row-major path.
+// The LDS-resident A-block kernel on tile-major operands: A from its 128 x 16
+// slabs, B k-slices straight from the tile-major column panels (the panel
+// height is the padded k).  s covers granules of 128 rows x nj column tiles.
+static void launch_a2(const TArgs& a, int64_t k0, int64_t k1, const Sched& s, int nj, int64_t slabs) {
+    const int grid = s.tiles_m * s.tiles_n;
+    if (grid <= 0) return;
+    hipLaunchKernelGGL((k_a2<CfgK, kKC, false, false, true, true>), dim3(grid), dim3(CfgK::THREADS), 0, a.st, a.M,
+                       a.N, k0, k1, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc, s, nj, (int64_t)0,
+                       (int64_t)0);
+}
+
+// Granules of 128 rows x nj column tiles over [m_off, m_lim) x [n_off, n_lim).
+static Sched granules(int64_t m_off, int64_t n_off, int64_t m_lim, int64_t n_lim, int nj, int64_t group_m,
+                      bool xcd) {
+    Sched s = sched_of(m_off, n_off, m_lim, n_lim, kT, group_m, xcd);
+    s.tiles_n = (int)cdiv(n_lim - n_off, (int64_t)nj * kT);
+    return s;
+}
+
+// The loop nests of the members, as in the row-major path.
 static int run(const momms_plan& p, const TArgs& a, int64_t K) {
     const int64_t M = a.M, N = a.N, slabs = cdiv(K, kSlab);
     const int t = p.mt;
@@ -238,15 +260,38 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
             // from the tile-major column panels.
             for (int64_t jc = 0; jc < N; jc += p.nc) {
                 const int64_t je = jc + p.nc < N ? jc + p.nc : N;
-                const Sched s = sched_of(0, jc, M, je, p.mt, 1, false);
-                Sched sg = s;
-                sg.tiles_n = (int)cdiv(je - jc, (int64_t)p.nj * p.nt);
-                const int grid = sg.tiles_m * sg.tiles_n;
+                const Sched s = granules(0, jc, M, je, p.nj, 1, false);
                 for (int64_t pc = 0; pc < K; pc += p.kc) {
                     const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
-                    hipLaunchKernelGGL((k_a2<CfgK, kKC, false, false, true, true>), dim3(grid), dim3(CfgK::THREADS),
-                                       0, a.st, M, N, pc, pe, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc,
-                                       sg, p.nj, (int64_t)0, (int64_t)0);
+                    launch_a2(a, pc, pe, s, p.nj, slabs);
+                }
+            }
+            break;
+        case MOMMS_B3A2C0: {
+            // k by kc3 -> granules of 128 rows x nc3 columns in column-major
+            // order (one XCD's run shares a kc3 x nc3 B block) -> the kernel
+            const Sched s = granules(0, 0, M, N, p.nj, p.group_m, true);
+            for (int64_t kb = 0; kb < K; kb += p.kc3) {
+                const int64_t ke = kb + p.kc3 < K ? kb + p.kc3 : K;
+                launch_a2(a, kb, ke, s, p.nj, slabs);
+            }
+            break;
+        }
+        case MOMMS_C3A2C0:
+            // XCD-grouped C tiles, each walking all of k with its A block in LDS
+            launch_a2(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true), 1, slabs);
+            break;
+        case MOMMS_C4A2C0:
+            // m, n by the MALL-resident C block -> k by kc -> the kernel
+            for (int64_t ib = 0; ib < M; ib += p.mc4) {
+                const int64_t ie = ib + p.mc4 < M ? ib + p.mc4 : M;
+                for (int64_t jb = 0; jb < N; jb += p.nc4) {
+                    const int64_t je = jb + p.nc4 < N ? jb + p.nc4 : N;
+                    const Sched s = granules(ib, jb, ie, je, p.nj, 1, false);
+                    for (int64_t pc = 0; pc < K; pc += p.kc) {
+                        const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
+                        launch_a2(a, pc, pe, s, p.nj, slabs);
+                    }
                 }
             }
             break;
@@ -335,7 +380,7 @@ int momms_gemm_tiled(int64_t m, int64_t n, int64_t k, double alpha, const double
         if (member != MOMMS_C0 && member != MOMMS_B3C0 && member != MOMMS_A3C0) member = MOMMS_C3C0;
     }
     if (member != MOMMS_C0 && member != MOMMS_C3C0 && member != MOMMS_B3C0 && member != MOMMS_A3C0 &&
-        member != MOMMS_A2C0)
+        member != MOMMS_A2C0 && member != MOMMS_B3A2C0 && member != MOMMS_C3A2C0 && member != MOMMS_C4A2C0)
         return -10;
     if (cdiv(m, 64) * cdiv(n, 64) >= (int64_t)INT_MAX / 2) return MOMMS_ERR_INFEASIBLE;
     if (m == 0 || n == 0) return 0;
