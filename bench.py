@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6
 LOWP_MFMA_PEAK_TOPS = {"bf16": 2500.0, "fp8": 5000.0, "int8": 5000.0, "crt": 5000.0}   # dense, per the MI355X specification
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_f64_8192.json")
-TILED_MEMBERS = ["C0", "C3C0", "B3C0", "A3C0", "A2C0", "B3A2C0", "C3A2C0", "C4A2C0"]
+TILED_MEMBERS = ["C0", "C3C0", "B3C0", "A3C0", "A2C0", "B3A2C0", "A3B2C0", "C3A2C0", "C4A2C0"]
 
 
 def parse():

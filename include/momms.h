@@ -320,9 +320,9 @@ int momms_from_tiled(int operand, int64_t rows, int64_t cols, const double *T, d
 /* C := alpha At Bt + beta C on tiled operands, C row-major (pitch ldc).
  * family_member: MOMMS_AUTO, MOMMS_C0, MOMMS_C3C0, MOMMS_B3C0, MOMMS_A3C0
  * (the members that keep the C tile in registers), MOMMS_A2C0 (Goto, which
- * reads the tiled B panels in place instead of packing them), MOMMS_B3A2C0,
- * MOMMS_C3A2C0 or MOMMS_C4A2C0 (the LDS-resident A block; A3B2C0 is not
- * offered on tiled operands).  Loop nests and
+ * reads the tiled B panels in place instead of packing them), or any of the
+ * LDS-resident members (MOMMS_B3A2C0, MOMMS_A3B2C0, MOMMS_C3A2C0,
+ * MOMMS_C4A2C0).  Loop nests and
  * k stagger are those of momms_gemm_ex, so the result equals that call's bit
  * for bit.  beta = 0 does not read C.  Argument numbers: 1 m, 2 n, 3 k,
  * 4 alpha, 5 At, 6 Bt, 7 beta, 8 C, 9 ldc, 10 family_member, 11 stream. */

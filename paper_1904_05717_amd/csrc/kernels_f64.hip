@@ -395,8 +395,10 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
 // ---------------------------------------------------------------------------
 // k_b2: mirror of k_a2.  Granule = (mi * MT) rows x NT columns; for each KC
 // chunk the B block (KC x NT) is resident in LDS and reused for every m-tile;
-// A slices stream through two LDS buffers.
-template <class CF, int KC, bool TA, bool TB>
+// A slices stream through two LDS buffers.  With TILED, A is tile-major
+// (128 x 16 slabs, lda = slabs per row panel) and B comes from tile-major
+// column panels (ldb = the padded k), both zero beyond the matrix.
+template <class CF, int KC, bool TA, bool TB, bool TILED = false>
 __global__ __launch_bounds__(CF::THREADS) void k_b2(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
                                                     double alpha, const double* __restrict__ A, int64_t lda,
                                                     const double* __restrict__ B, int64_t ldb, double beta,
@@ -422,13 +424,25 @@ __global__ __launch_bounds__(CF::THREADS) void k_b2(int64_t M, int64_t N, int64_
         const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
         const int total = mtiles * nsl;
         __syncthreads();
+        auto load_a = [&](int i, int sl) {
+            const int64_t r0 = mbeg + (int64_t)i * CF::MT, kk = kb + (int64_t)sl * CF::KS;
+            if (TILED) {
+                const double* P = A + ((r0 / 128) * lda + kk / 16) * 2048 + kk % 16;
+                sa.load(P, 16, 0, 0, INT64_MAX, INT64_MAX, tid);
+            } else {
+                sa.load(A, lda, r0, kk, mend, kbe, tid);
+            }
+        };
 #pragma unroll 1
         for (int c = 0; c < nsl; ++c) {
-            sb.load(B, ldb, kb + c * CF::KS, n0, kbe, N, tid);
+            if (TILED)
+                sb.load(B + (n0 / CF::NT) * ldb * CF::NT, CF::NT, kb + c * CF::KS, 0, INT64_MAX, CF::NT, tid);
+            else
+                sb.load(B, ldb, kb + c * CF::KS, n0, kbe, N, tid);
             sb.store(Bs + c * CF::KS * CF::B_LD, CF::B_LD, tid);
         }
         if (total > 0) {
-            sa.load(A, lda, mbeg, kb, mend, kbe, tid);
+            load_a(0, 0);
             sa.store(As[0], CF::A_LD, tid);
         }
         __syncthreads();
@@ -441,7 +455,7 @@ __global__ __launch_bounds__(CF::THREADS) void k_b2(int64_t M, int64_t N, int64_
             const bool more = t + 1 < total;
             if (more) {
                 const int i2 = (t + 1) / nsl, sl2 = (t + 1) - ((t + 1) / nsl) * nsl;
-                sa.load(A, lda, mbeg + (int64_t)i2 * CF::MT, kb + (int64_t)sl2 * CF::KS, mend, kbe, tid);
+                load_a(i2, sl2);
             }
             mma_lds<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs, CF::B_LD, sl * CF::KS, acc, wm, wn, lane);
             if (more) sa.store(As[cur ^ 1], CF::A_LD, tid);

@@ -15,8 +15,9 @@
 // Rows and columns beyond the matrix, and k beyond k, are zero.  The
 // register-resident members keep the C tile in registers over all of k
 // exactly as in the row-major kernel, with the same k stagger; Goto, B3A2C0,
-// C3A2C0 and C4A2C0 run the LDS-resident A-block kernel with their row-major
-// loop nests, B read in place from the column panels.  So for a given member
+// C3A2C0 and C4A2C0 run the LDS-resident A-block kernel and A3B2C0 the
+// LDS-resident B-block kernel with their row-major loop nests, B read in
+// place from the column panels.  So for a given member
 // the result is bitwise the one the row-major path computes; only the loads
 // differ (one pointer per thread stepping through contiguous slabs, no edge
 // predicates).
@@ -277,6 +278,21 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
             }
             break;
         }
+        case MOMMS_A3B2C0: {
+            // k by kc3 -> granules of mc3 rows x 128 columns, XCD-aware ->
+            // the kernel with the B block (kc x 128) in LDS, A slices streamed
+            Sched s = sched_of(0, 0, M, N, kT, 1, true);
+            s.tiles_m = (int)cdiv(M, p.mc3);
+            for (int64_t kb = 0; kb < K; kb += p.kc3) {
+                const int64_t ke = kb + p.kc3 < K ? kb + p.kc3 : K;
+                const int grid = s.tiles_m * s.tiles_n;
+                if (grid > 0)
+                    hipLaunchKernelGGL((k_b2<CfgK, kKC, false, false, true>), dim3(grid), dim3(CfgK::THREADS), 0,
+                                       a.st, M, N, kb, ke, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc, s,
+                                       p.mi);
+            }
+            break;
+        }
         case MOMMS_C3A2C0:
             // XCD-grouped C tiles, each walking all of k with its A block in LDS
             launch_a2(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true), 1, slabs);
@@ -379,9 +395,7 @@ int momms_gemm_tiled(int64_t m, int64_t n, int64_t k, double alpha, const double
         member = select_member(m, n, k);
         if (member != MOMMS_C0 && member != MOMMS_B3C0 && member != MOMMS_A3C0) member = MOMMS_C3C0;
     }
-    if (member != MOMMS_C0 && member != MOMMS_C3C0 && member != MOMMS_B3C0 && member != MOMMS_A3C0 &&
-        member != MOMMS_A2C0 && member != MOMMS_B3A2C0 && member != MOMMS_C3A2C0 && member != MOMMS_C4A2C0)
-        return -10;
+    if (member <= MOMMS_AUTO || member >= momms_num_members()) return -10;
     if (cdiv(m, 64) * cdiv(n, 64) >= (int64_t)INT_MAX / 2) return MOMMS_ERR_INFEASIBLE;
     if (m == 0 || n == 0) return 0;
     if ((alpha == 0.0 || k == 0) && beta == 1.0) return 0;

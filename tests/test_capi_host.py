@@ -155,7 +155,8 @@ def test_tiled_sizes_and_argument_errors():
     assert f(-1, 4, 4, 1.0, big, big, 0.0, big, 4, 0, None) == -1
     assert f(4, 4, 4, 1.0, None, big, 0.0, big, 4, 0, None) == -5
     assert f(4, 4, 4, 1.0, big, big, 0.0, big, 3, 0, None) == -9
-    assert f(4, 4, 4, 1.0, big, big, 0.0, big, 4, mm.MEMBERS["A3B2C0"], None) == -10
+    assert f(4, 4, 4, 1.0, big, big, 0.0, big, 4, 99, None) == -10
+    assert f(4, 4, 4, 1.0, big, big, 0.0, big, 4, -1, None) == -10
 
 
 def test_syrk_argument_errors():
