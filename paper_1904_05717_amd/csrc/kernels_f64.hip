@@ -182,7 +182,22 @@ __device__ __forceinline__ void store_c_tri(const d4 (&acc)[CF::BM][CF::BN], dou
                                         int64_t M, int64_t N, int wm, int wn, int lane) {
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int i = 0; i < CF::BM; ++i)
+    for (int i = 0; i < CF::BM; ++i) {
+        // One block row of the wave tile at a time: its C values are all
+        // loaded before any is used (an entry outside C reads C[0] and is
+        // discarded), so the reads cost one memory latency, not one each.
+        double cv[CF::BN][4];
+        if (beta != 0.0) {
+#pragma unroll
+            for (int j = 0; j < CF::BN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = m0 + wm * CF::WTM + i * 16 + lk + 4 * r;
+                    const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
+                    const bool in = row < M && col < N && (TRI == 0 || (TRI == 1 ? row >= col : row <= col));
+                    cv[j][r] = C[in ? row * ldc + col : 0];
+                }
+        }
 #pragma unroll
         for (int j = 0; j < CF::BN; ++j)
 #pragma unroll
@@ -190,12 +205,12 @@ __device__ __forceinline__ void store_c_tri(const d4 (&acc)[CF::BM][CF::BN], dou
                 const int64_t row = m0 + wm * CF::WTM + i * 16 + lk + 4 * r;
                 const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
                 if (row < M && col < N && (TRI == 0 || (TRI == 1 ? row >= col : row <= col))) {
-                    double* p = C + row * ldc + col;
                     double v = alpha * acc[i][j][r];
-                    if (beta != 0.0) v += beta * (*p);
-                    *p = v;
+                    if (beta != 0.0) v += beta * cv[j][r];
+                    C[row * ldc + col] = v;
                 }
             }
+    }
 }
 
 template <class CF>
@@ -333,8 +348,7 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
     const int wm = wave / CF::WN, wn = wave % CF::WN;
     const int ntiles = (int)((nend - nbeg + CF::NT - 1) / CF::NT);
 
-    Stage<CF::MT, CF::KS, CF::THREADS, TA> sa;
-    Stage<CF::KS, CF::NT, CF::THREADS, PACKED ? false : TB> sb;
+    Stage<CF::KS, CF::NT, CF::THREADS, PACKED ? false : TB> sb0, sb1;
     d4 acc[CF::BM][CF::BN];
 
     for (int64_t kb = k_begin; kb < k_end; kb += KC) {
@@ -342,20 +356,32 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
         const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
         const int total = ntiles * nsl;
         __syncthreads();  // previous chunk's readers of As / Bs are done
+        // the A block, four slices in flight at a time
 #pragma unroll 1
-        for (int c = 0; c < nsl; ++c) {
-            if (TILED) {
-                // tile-major A: 128 x 16 slabs, lda = slabs per row panel,
-                // zero beyond the matrix (m0 is a multiple of 128)
-                const int64_t kk = kb + (int64_t)c * CF::KS;
-                const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + kk % 16;
-                sa.load(P, 16, 0, 0, INT64_MAX, INT64_MAX, tid);
-            } else {
-                sa.load(A, lda, m0, kb + c * CF::KS, M, kbe, tid);
+        for (int c0 = 0; c0 < nsl; c0 += 4) {
+            Stage<CF::MT, CF::KS, CF::THREADS, TA> sq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u;
+                if (c >= nsl) break;
+                if (TILED) {
+                    // tile-major A: 128 x 16 slabs, lda = slabs per row panel,
+                    // zero beyond the matrix (m0 is a multiple of 128)
+                    const int64_t kk = kb + (int64_t)c * CF::KS;
+                    const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + kk % 16;
+                    sq[u].load(P, 16, 0, 0, INT64_MAX, INT64_MAX, tid);
+                } else {
+                    sq[u].load(A, lda, m0, kb + c * CF::KS, M, kbe, tid);
+                }
             }
-            sa.store(As + c * CF::KS, AB_LD, tid);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u;
+                if (c >= nsl) break;
+                sq[u].store(As + c * CF::KS, AB_LD, tid);
+            }
         }
-        auto load_b = [&](int t) {
+        auto load_b = [&](auto& st, int t) {
             const int j = t / nsl, sl = t - (t / nsl) * nsl;
             if (PACKED) {
                 // panel row (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j);
@@ -363,31 +389,39 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
                 // k for a tile-major B)
                 const int64_t jt = (nbeg - pn0) / CF::NT + j;
                 const double* P = B + jt * ldb * CF::NT;
-                sb.load(P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, INT64_MAX, CF::NT, tid);
+                st.load(P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, INT64_MAX, CF::NT, tid);
             } else {
-                sb.load(B, ldb, kb + (int64_t)sl * CF::KS, nbeg + (int64_t)j * CF::NT, kbe, nend, tid);
+                st.load(B, ldb, kb + (int64_t)sl * CF::KS, nbeg + (int64_t)j * CF::NT, kbe, nend, tid);
             }
         };
+        // B slices two ahead: slice t+1 waits in one register set while
+        // slice t+2 loads into the other (the two sets alternate, so the loop
+        // runs two steps per iteration); the prefetch index is clamped to the
+        // last slice rather than skipped, which keeps the load where it is.
         if (total > 0) {
-            load_b(0);
-            sb.store(Bs[0], CF::B_LD, tid);
+            load_b(sb0, 0);
+            sb0.store(Bs[0], CF::B_LD, tid);
+            load_b(sb1, total > 1 ? 1 : 0);
         }
         __syncthreads();
         zero_acc<CF>(acc);
         const double beta_eff = (kb == 0) ? beta : 1.0;
-#pragma unroll 1
-        for (int t = 0; t < total; ++t) {
-            const int cur = t & 1;
+        auto step = [&](int t, auto& reload, auto& ready, double* cur, double* other) {
             const int j = t / nsl, sl = t - j * nsl;
-            const bool more = t + 1 < total;
-            if (more) load_b(t + 1);
-            mma_lds<CF, CF::KS / 4>(As, AB_LD, sl * CF::KS, Bs[cur], CF::B_LD, 0, acc, wm, wn, lane);
-            if (more) sb.store(Bs[cur ^ 1], CF::B_LD, tid);
+            load_b(reload, t + 2 < total ? t + 2 : total - 1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_lds<CF, CF::KS / 4>(As, AB_LD, sl * CF::KS, cur, CF::B_LD, 0, acc, wm, wn, lane);
+            if (t + 1 < total) ready.store(other, CF::B_LD, tid);
             if (sl == nsl - 1) {
                 store_c<CF>(acc, alpha, beta_eff, C, ldc, m0, nbeg + (int64_t)j * CF::NT, M, nend, wm, wn, lane);
                 zero_acc<CF>(acc);
             }
             __syncthreads();
+        };
+#pragma unroll 1
+        for (int t = 0; t < total; t += 2) {
+            step(t, sb0, sb1, Bs[0], Bs[1]);
+            if (t + 1 < total) step(t + 1, sb1, sb0, Bs[1], Bs[0]);
         }
     }
 }
