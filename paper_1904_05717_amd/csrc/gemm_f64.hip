@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_scale_c(int64_t M, int64_t N, double be
 
 using CfgL = TileCfg<128, 128, 16, 2, 2>;  // register-resident C, large problems
 using CfgS = TileCfg<64, 64, 16, 2, 2>;    // register-resident C, small problems
-using CfgK = TileCfg<128, 128, 8, 2, 4>;   // LDS-resident A or B block: eight waves, two per SIMD
+using CfgK = TileCfg<128, 128, 8, 4, 4>;   // LDS-resident A or B block: sixteen waves, four per SIMD
 
 static hipStream_t g_stream = nullptr;
 

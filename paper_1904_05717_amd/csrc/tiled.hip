@@ -38,7 +38,7 @@ constexpr int kSlabElems = kT * kSlab;
 
 typedef TileCfg<128, 128, 16, 2, 2> Cfg128;
 typedef TileCfg<64, 64, 16, 2, 2> Cfg64;
-typedef TileCfg<128, 128, 8, 2, 4> CfgK;   // the LDS-resident block kernels (eight waves)
+typedef TileCfg<128, 128, 8, 4, 4> CfgK;   // the LDS-resident block kernels (sixteen waves)
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
