@@ -650,7 +650,7 @@ def bench_lowbw(args):
     def run(member, A, B, C, ws, hog):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         if hog is not None:
-            hog.start(max_seconds=5.0)
+            hog.start(max_seconds=2.0)
             time.sleep(0.005)
         try:
             with torch.cuda.stream(s):
@@ -664,6 +664,9 @@ def bench_lowbw(args):
                 hog.stop(s)
         rep = hog.report() if hog is not None else None
         s.synchronize()
+        if rep is not None and not (rep["covered"] and not rep["timed_out"]):
+            # the streamer did not run beside the product: stop here rather than wait out its clock every run
+            raise RuntimeError(f"streamer and product did not overlap: {rep}")
         return e0.elapsed_time(e1), rep
 
     out = {"widths": LOWBW_WIDTHS, "streamer_alone_GBps": alone_rate, "shapes": []}
