@@ -143,13 +143,21 @@ __device__ __forceinline__ void solve_block(const double (*Ts)[kBase + 1], const
 // words).  Multiply: wave w forms rows 16w .. 16w+15, sixteen independent
 // sums.  Solve: solve_block.  All 32 loads per thread (16 of op(T), 16 of
 // x) are in flight before the first is used.
+// The grid's y index picks the diagonal block: block q covers rows 64q ..
+// of the `rows`-row triangle (a solve launches one block, the multiply all of
+// them at once, since the diagonal products of a multiply are independent).
 template <int MODE, bool LOWER, bool UNIT>
-__global__ __launch_bounds__(256) void k_tri_base(int s, int64_t n, const double* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256) void k_tri_base(int64_t rows, int64_t n, const double* __restrict__ A, int64_t lda,
                                                   bool trans, bool upper_stored, double alpha, double* X,
                                                   int64_t ldx, double* Y, int64_t ldy) {
     __shared__ double Ts[kBase][kBase + 1];
     __shared__ double xs[kBase][64];
     __shared__ double rdiag[kBase];   // 1 / t_ii: the substitution multiplies
+    const int64_t r0 = (int64_t)blockIdx.y * kBase;
+    A += r0 * lda + r0;
+    X += r0 * ldx;
+    if (MODE == 1) Y += r0 * ldy;
+    const int s = (int)(rows - r0 < kBase ? rows - r0 : kBase);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const OpBlock blk = op_block_at(trans, 0, 0);
     double tv[16], xv[16];
@@ -205,24 +213,26 @@ static inline const double* op_block(const Tri& t, int64_t R0, int64_t C0, int* 
     return t.trans ? t.A + C0 * t.lda + R0 : t.A + R0 * t.lda + C0;
 }
 
+// Diagonal blocks of rows [r0, r0 + s): one block per launch row when s <= 64,
+// or every 64-row block of the range at once (blocks > 1, multiply only).
 template <int MODE>
 static int launch_base(const Tri& t, int64_t r0, int64_t s, double alpha, double* X, int64_t ldx, double* Y,
-                       int64_t ldy) {
-    const dim3 grid((unsigned)((t.n + 63) / 64));   // 64 columns per workgroup of 256 threads
+                       int64_t ldy, unsigned blocks = 1) {
+    const dim3 grid((unsigned)((t.n + 63) / 64), blocks);   // 64 columns per workgroup of 256 threads
     const double* Ab = t.A + r0 * t.lda + r0;
     if (t.lower_op) {
         if (t.unit)
-            hipLaunchKernelGGL((k_tri_base<MODE, true, true>), grid, dim3(256), 0, t.st, (int)s, t.n, Ab, t.lda,
+            hipLaunchKernelGGL((k_tri_base<MODE, true, true>), grid, dim3(256), 0, t.st, s, t.n, Ab, t.lda,
                                t.trans, t.upper_stored, alpha, X, ldx, Y, ldy);
         else
-            hipLaunchKernelGGL((k_tri_base<MODE, true, false>), grid, dim3(256), 0, t.st, (int)s, t.n, Ab, t.lda,
+            hipLaunchKernelGGL((k_tri_base<MODE, true, false>), grid, dim3(256), 0, t.st, s, t.n, Ab, t.lda,
                                t.trans, t.upper_stored, alpha, X, ldx, Y, ldy);
     } else {
         if (t.unit)
-            hipLaunchKernelGGL((k_tri_base<MODE, false, true>), grid, dim3(256), 0, t.st, (int)s, t.n, Ab, t.lda,
+            hipLaunchKernelGGL((k_tri_base<MODE, false, true>), grid, dim3(256), 0, t.st, s, t.n, Ab, t.lda,
                                t.trans, t.upper_stored, alpha, X, ldx, Y, ldy);
         else
-            hipLaunchKernelGGL((k_tri_base<MODE, false, false>), grid, dim3(256), 0, t.st, (int)s, t.n, Ab, t.lda,
+            hipLaunchKernelGGL((k_tri_base<MODE, false, false>), grid, dim3(256), 0, t.st, s, t.n, Ab, t.lda,
                                t.trans, t.upper_stored, alpha, X, ldx, Y, ldy);
     }
     const hipError_t e = hipGetLastError();
@@ -256,14 +266,17 @@ static int solve(const Tri& t, int64_t r0, int64_t s, double* B, int64_t ldb) {
 }
 
 // C[r0:r0+s] = alpha op(T)[r0:r0+s, r0:r0+s] B[r0:r0+s].
+// The off-diagonal products of the recursion, after every diagonal block has
+// been written (leaves == false: the diagonal blocks were launched together).
 static int multiply(const Tri& t, int64_t r0, int64_t s, double alpha, const double* B, int64_t ldb, double* C,
-                    int64_t ldc) {
+                    int64_t ldc, bool leaves) {
     if (s <= kBase)
-        return launch_base<1>(t, r0, s, alpha, const_cast<double*>(B) + r0 * ldb, ldb, C + r0 * ldc, ldc);
+        return leaves ? launch_base<1>(t, r0, s, alpha, const_cast<double*>(B) + r0 * ldb, ldb, C + r0 * ldc, ldc)
+                      : 0;
     const int64_t h = split_point(s);
     int ta, rc;
-    if ((rc = multiply(t, r0, h, alpha, B, ldb, C, ldc)) != 0) return rc;
-    if ((rc = multiply(t, r0 + h, s - h, alpha, B, ldb, C, ldc)) != 0) return rc;
+    if ((rc = multiply(t, r0, h, alpha, B, ldb, C, ldc, leaves)) != 0) return rc;
+    if ((rc = multiply(t, r0 + h, s - h, alpha, B, ldb, C, ldc, leaves)) != 0) return rc;
     if (t.lower_op) {   // C2 += alpha T21 B1
         const double* Ab = op_block(t, r0 + h, r0, &ta);
         return momms_gemm_ex(ta, 0, s - h, t.n, h, alpha, Ab, t.lda, B + r0 * ldb, ldb, 1.0, C + (r0 + h) * ldc,
@@ -305,7 +318,13 @@ int momms_trmm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha
     if (alpha == 0.0)   // C = 0, A and B not read
         return momms_gemm_ex(0, 0, m, n, 0, 0.0, nullptr, 1, nullptr, n, 0.0, C, ldc, MOMMS_AUTO, nullptr, 0, st);
     Tri t{trans != 0, uplo == 'U', diag == 'U', (uplo == 'L') != (trans != 0), A, lda, n, st};
-    return multiply(t, 0, m, alpha, B, ldb, C, ldc);
+    // The diagonal products are independent: all of them in one launch, then
+    // the recursion's off-diagonal products add into C.
+    const int64_t blocks = (m + kBase - 1) / kBase;
+    if (blocks > 65535) return multiply(t, 0, m, alpha, B, ldb, C, ldc, true);
+    rc = launch_base<1>(t, 0, m, alpha, const_cast<double*>(B), ldb, C, ldc, (unsigned)blocks);
+    if (rc != 0) return rc;
+    return multiply(t, 0, m, alpha, B, ldb, C, ldc, false);
 }
 
 int momms_trsm(int uplo, int trans, int diag, int64_t m, int64_t n, double alpha, const double* A, int64_t lda,
