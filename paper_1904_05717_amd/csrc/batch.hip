@@ -40,6 +40,17 @@ struct Item {
     int tile;  // row-major tile index within the problem
 };
 
+// The problem table holds device pointers, but a pointer read from memory is
+// generic to the compiler, which then emits flat loads and stores.  Flat loads
+// also count on the LDS wait counter, so every wait for an LDS read would wait
+// for the prefetch in flight too.  Rebuilding each pointer from its address
+// as a global-memory pointer lets the compiler emit global instructions (a
+// cast of the generic pointer alone is folded away).
+template <class T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+    return (T*)((__attribute__((address_space(1))) T*)(uintptr_t)p);
+}
+
 __global__ __launch_bounds__(64) void k_reset(unsigned* __restrict__ counter) {
     if (threadIdx.x == 0) *counter = 0u;
 }
@@ -63,7 +74,10 @@ void k_batch(const Prob* __restrict__ probs, const Item* __restrict__ items, int
         __syncthreads();  // all threads have read `next` before it is overwritten
         if (it >= nitems) break;
         const Item w = items[it];
-        const Prob p = probs[w.prob];
+        Prob p = probs[w.prob];
+        p.A = global_ptr(p.A);
+        p.B = global_ptr(p.B);
+        p.C = global_ptr(p.C);
         const int tm = w.tile / p.tiles_n, tn = w.tile - (w.tile / p.tiles_n) * p.tiles_n;
         if (p.tile == 128)
             regc_tile<BL, false, false, false>(p.m, p.n, 0, p.k, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C,
