@@ -85,3 +85,32 @@ def test_leading_dimension_with_nan_gap():
     assert info == 0 and np.isnan(out[:, n:]).all()
     want, _ = chol.potrf_upper(A)
     assert np.max(np.abs(np.triu(out[:, :n]) - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_benchmark_configuration_8192():
+    # the matrix the benchmark factors: S S^T + I with S uniform / sqrt(n),
+    # built by torch on the device; the residual U^T U - A on sampled rows by
+    # the oracle, and on the whole upper triangle against the same bound
+    import workloads
+    n = 8192
+    S = torch.from_numpy(workloads.uniform((n, n), 29) / np.sqrt(n)).to("cuda:0")
+    Ad = S @ S.t() + torch.eye(n, dtype=torch.float64, device="cuda:0")
+    del S
+    A = Ad.cpu().numpy()
+    Ud = Ad.clone()
+    assert mm.potrf(Ud) == 0
+    Ud = torch.triu(Ud)
+    U = Ud.cpu().numpy()
+    rows = np.array([0, 127, 128, 4096, 8191])
+    Ut = np.ascontiguousarray(U.T[rows])
+    R = oracle.gemm(Ut, U, np.ascontiguousarray(A[rows]), 1.0, -1.0)
+    bound = 4 * (n + 2) * U53 * (np.abs(Ut) @ np.abs(U) + np.abs(A[rows]))
+    keep = np.zeros((len(rows), n), dtype=bool)
+    for r, i in enumerate(rows):
+        keep[r, i:] = True   # the upper triangle: the part of A the factorization reads
+    assert np.all(np.abs(R[keep]) <= bound[keep])
+    full = mm.gemm(Ud, Ud, transA=True)
+    babs = mm.gemm(Ud.abs(), Ud.abs(), transA=True)
+    tri_mask = torch.ones(n, n, dtype=torch.bool, device="cuda:0").triu()
+    excess = ((full - Ad).abs() - 4 * (n + 2) * U53 * (babs + Ad.abs())).masked_fill(~tri_mask, -1.0)
+    assert float(excess.max().item()) <= 0.0

@@ -169,3 +169,26 @@ def test_leading_dimensions_with_nan_gaps():
     want = tri.trsm(A, B, "L", True, alpha=1.5)
     assert np.max(np.abs(gb[:, :n] - want)) <= 1e-12 * np.abs(want).max()
     assert np.isnan(gb[:, n:]).all()
+
+
+def test_benchmark_configuration_8192_sampled_columns():
+    # the shape and data the benchmark times: m = n = 8192, lower triangle,
+    # off-diagonal U[-1, 1] / sqrt(m), diagonal 1.5
+    import workloads
+    m = n = 8192
+    A = workloads.uniform((m, m), 27) / np.sqrt(m)
+    A[np.diag_indices(m)] = 1.5
+    B = workloads.uniform((m, n), 28)
+    Ad, Bd = dev(A), dev(B)
+    X = Bd.clone()
+    mm.trsm(Ad, X, uplo="L")
+    C = torch.empty_like(Bd)
+    mm.trmm(Ad, Bd, C, uplo="L")
+    torch.cuda.synchronize()
+    cols = [0, 1, 63, 64, 4095, 8191]
+    Bc = np.ascontiguousarray(B[:, cols])
+    want = tri.trsm(A, Bc, "L")
+    assert np.max(np.abs(X[:, cols].cpu().numpy() - want)) <= 1e-12 * max(1.0, np.abs(want).max())
+    T = tri.op_tri(A, "L")
+    got = C[:, cols].cpu().numpy()
+    assert np.all(np.abs(got - tri.trmm(A, Bc, "L")) <= 2 * (m + 2) * U * (np.abs(T) @ np.abs(Bc)))
