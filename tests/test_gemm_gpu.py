@@ -163,3 +163,18 @@ def test_large_register_tile_sampled(member):
 def test_bench_size_sampled():
     m = n = k = 8192
     sampled_check(m, n, k, "AUTO", npts=1024)
+
+
+@pytest.mark.parametrize("member", ["A2C0", "B3A2C0", "A3B2C0", "C3A2C0", "C4A2C0"])
+def test_lds_resident_members_bench_size_sampled(member):
+    # the LDS-resident members at the size the member table and the
+    # low-bandwidth experiments time them: every k chunk, granule and block
+    # loop runs many times over
+    sampled_check(8192, 8192, 8192, member, npts=512, seed=1)
+
+
+@pytest.mark.parametrize("member", ["AUTO", "C0", "A2C0", "A3B2C0"])
+@pytest.mark.parametrize("shape", [(16384, 16384, 256), (16384, 256, 16384)])
+def test_sweep_thin_shapes_sampled(shape, member):
+    # the rank-k and panel shapes of the sweep
+    sampled_check(*shape, member, npts=512, seed=2)
