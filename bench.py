@@ -170,7 +170,6 @@ def bench_fp64(args):
     plan = mm.member_plan(member, m, n, k)
     A, B, C = workloads.gemm_operands(m, n, k)
     Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
-    del A, B, C
     wsb = mm.workspace_size(m, n, k, member)
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda:0") if wsb else None
     stream = torch.cuda.current_stream()
@@ -193,6 +192,27 @@ def bench_fp64(args):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / steps
     flops = 2.0 * m * n * k
+    # accuracy of the same call, untimed: one product into a fresh copy of C
+    # against the oracle on sampled entries, as error / bound (<= 1 passes);
+    # skipped under --profile so the traces hold only the timed calls
+    err_over_bound = None
+    if not args.profile:
+        import numpy as np
+
+        import oracle
+        C1 = torch.from_numpy(C).to("cuda:0")
+        mm.gemm(Ad, Bd, C1, alpha=1.0, beta=1.0, member=member, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        rng = np.random.Generator(np.random.PCG64(31))
+        rows = np.concatenate([rng.integers(0, m, 256), [0, 0, m - 1, m - 1]])
+        cols = np.concatenate([rng.integers(0, n, 256), [0, n - 1, 0, n - 1]])
+        want = oracle.gemm_entries(A, B, rows, cols, C, 1.0, 1.0)
+        absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
+        bound = 2.0 * (k + 2) * 2.0 ** -53 * (absab + np.abs(C[rows, cols]))
+        got = C1.cpu().numpy()[rows, cols]
+        err_over_bound = round(float(np.max(np.abs(got - want) / bound)), 4)
+        del C1
+    del A, B, C
     # The dominant kernel is the member's main kernel; a step is
     # plan["launches"] back-to-back launches of it (plus packing launches for
     # members that pack), so one launch takes ms / compute_launches.
@@ -219,6 +239,7 @@ def bench_fp64(args):
         "wall_s_timed": round(wall, 3),
         "member": member,
         "launches_per_step": compute_launches,
+        "max_err_over_bound_260_entries": err_over_bound,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic},
         "model_bytes": {"l2_read": model["l2_read"], "l2_write": model["l2_write"], "hbm_read": model["hbm_read"],
@@ -946,6 +967,7 @@ def main():
     }
     if "measured_vs_model" in f:
         out["measured_vs_model"] = f["measured_vs_model"]
+    out["max_err_over_bound_260_entries"] = f["max_err_over_bound_260_entries"]
     if only == "all":
         out["split_precision"] = bench_split(args, fp64_ms=f["ms_per_step"])
         out["batched"] = bench_batch(args)
