@@ -241,7 +241,9 @@ def bench_fp64(args):
         "launches_per_step": compute_launches,
         "max_err_over_bound_260_entries": err_over_bound,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic},
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic,
+                     "model_bytes_per_launch": round((model["l2_read"] + model["l2_write"]) / compute_launches),
+                     "launch_ms": round(launch_ms, 4), "flops_per_launch": flops / compute_launches},
         "model_bytes": {"l2_read": model["l2_read"], "l2_write": model["l2_write"], "hbm_read": model["hbm_read"],
                         "hbm_write": model["hbm_write"], "compulsory": model["compulsory"]},
     }
@@ -533,6 +535,10 @@ def bench_tri(args):
 
 
 def bench_batch(args):
+    """512 uneven problems (config 4) in one persistent hipGraph-replayed
+    launch: the planner's per-problem choice (AUTO) against fixed choices of
+    member and register tile for the whole batch.  Median of the replays;
+    padding = flops of the padded tiles / algorithmic flops."""
     import torch
 
     import paper_1904_05717_amd as mm
@@ -544,22 +550,47 @@ def bench_batch(args):
         dev.append((torch.from_numpy(workloads.uniform((m, k), 3 * i)).to("cuda:0"),
                     torch.from_numpy(workloads.uniform((k, n), 3 * i + 1)).to("cuda:0"),
                     torch.from_numpy(workloads.uniform((m, n), 3 * i + 2)).to("cuda:0")))
-    plan = mm.BatchPlan([(A, B, C, 1.0, 1.0) for (A, B, C) in dev])
-    info = plan.info()
-    plan.run()
-    torch.cuda.synchronize()
+    probs = [(A, B, C, 1.0, 1.0) for (A, B, C) in dev]
     reps = 2 if args.profile else 20
-    e0, e1 = events()
-    e0.record()
-    for _ in range(reps):
+    choices = [("AUTO", None, None), ("C0", "C0", None), ("C3C0", "C3C0", None), ("C0/128", "C0", 128),
+               ("C0/64", "C0", 64), ("B3C0", "B3C0", None), ("A3C0", "A3C0", None)]
+    runs = {}
+    auto_info = None
+    for label, member, tile in (choices[:1] if args.profile else choices):
+        plan = mm.BatchPlan(probs, members=member, tiles=tile)
+        info = plan.info()
         plan.run()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    plan.close()
-    return {"problems": 512, "ms_per_replay": round(ms, 3), "tflops": round(info["flops"] / (ms * 1e-3) / 1e12, 3),
-            "items": info["items"], "persistent_workgroups": info["workgroups"],
-            "tiles_128": sum(1 for t in info["tiles"] if t == 128), "graph": "hipGraph replay",
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0, e1 = events()
+            e0.record()
+            plan.run()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        plan.close()
+        ms = sorted(times)[len(times) // 2]
+        runs[label] = {"ms_per_replay": round(ms, 3), "tflops": round(info["flops"] / (ms * 1e-3) / 1e12, 3),
+                       "padding_ratio": round(info["padded_flops"] / info["flops"], 3),
+                       "split_problems": sum(1 for c in info["chunks"] if c > 1)}
+        if label == "AUTO":
+            auto_info = info
+    auto = runs["AUTO"]
+    fixed = {key: v for key, v in runs.items() if key != "AUTO"}
+    best_fixed = min(fixed, key=lambda key: fixed[key]["ms_per_replay"]) if fixed else None
+    counts = {}
+    for mem, t, c in zip(auto_info["members"], auto_info["tiles"], auto_info["chunks"]):
+        key = f"{mem}/{t}" + ("/split" if c > 1 else "")
+        counts[key] = counts.get(key, 0) + 1
+    return {"problems": 512, "ms_per_replay": auto["ms_per_replay"], "tflops": auto["tflops"],
+            "frac_fp64_peak": round(auto["tflops"] / FP64_MFMA_PEAK_TFLOPS, 4),
+            "padding_ratio": auto["padding_ratio"], "members": counts,
+            "items": auto_info["items"], "persistent_workgroups": auto_info["workgroups"],
+            "best_fixed_choice": best_fixed,
+            "auto_over_best_fixed": (round(auto["ms_per_replay"] / fixed[best_fixed]["ms_per_replay"], 3)
+                                     if best_fixed else None),
+            "choices": runs, "graph": "hipGraph replay", "timing": f"median of {reps} replays",
             "shapes": "m, n, k each round(exp(U(ln 32, ln 2048)))"}
 
 
@@ -923,6 +954,58 @@ def summarize(d, m=8192, n=8192, k=8192):
     print(json.dumps({"summarized": d, "members": {k: round(v["ratio"], 3) for k, v in members.items()}}))
 
 
+def _split_summary(sp):
+    """Fastest split configuration within 1e-13 of |A||B|, and per slice type
+    the fastest such configuration (else the most accurate one)."""
+    runs = sp.get("runs", [])
+
+    def ok(r):
+        return r["max_rel_err_vs_absAB"] <= 1e-13 and r.get("max_rel_err_all_entries", 0.0) <= 1e-13
+
+    def short(r):
+        return {"slices": r["slices"], "ms": r["ms"], "speedup_vs_fp64": r["speedup_vs_fp64"],
+                "max_rel_err": float(f"{max(r['max_rel_err_vs_absAB'], r.get('max_rel_err_all_entries', 0.0)):.3g}"),
+                "lowp_frac_of_peak": r["lowp_frac_of_peak"], "within_1e-13": ok(r)}
+
+    out = {"fp64_ms": sp.get("fp64_ms")}
+    best = sp.get("fastest_within_1e-13")
+    out["fastest_within_1e-13"] = None if best is None else {
+        "slice_type": best["slice_type"], "slices": best["slices"], "ms": best["ms"],
+        "speedup_vs_fp64": best["speedup_vs_fp64"]}
+    for t in ("crt", "int8", "bf16", "fp8"):
+        rs = [r for r in runs if r["slice_type"] == t]
+        if not rs:
+            continue
+        good = [r for r in rs if ok(r)]
+        r = min(good, key=lambda x: x["ms"]) if good else min(rs, key=lambda x: x["max_rel_err_vs_absAB"])
+        out[t] = short(r)
+    return out
+
+
+def compact_line(out):
+    """The final stdout line: the headline and a short summary of every
+    section (the full sections are printed on earlier lines and written to
+    gpurun_out/bench_full.json)."""
+    keep = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "roofline", "max_err_over_bound_260_entries",
+            "measured_vs_model", "cpu_baseline"]
+    line = {k: out[k] for k in keep if k in out}
+    if "split_precision" in out:
+        line["split"] = _split_summary(out["split_precision"])
+    if "batched" in out:
+        b = out["batched"]
+        line["batched"] = {key: b[key] for key in ("ms_per_replay", "tflops", "frac_fp64_peak", "padding_ratio",
+                                                   "members", "best_fixed_choice", "auto_over_best_fixed")
+                           if key in b}
+    if "backward" in out:
+        line["backward_tflops"] = {key: v["tflops_fwd_bwd"] for key, v in out["backward"].items()
+                                   if isinstance(v, dict) and "tflops_fwd_bwd" in v}
+    if "sweep" in out:
+        line["sweep_best_tflops"] = {f"{r['m']}x{r['n']}x{r['k']}": [r["best"], r["best_tflops"], r["auto"]]
+                                     for r in out["sweep"]}
+    return line
+
+
 def main():
     args = parse()
     if args.summarize:
@@ -968,22 +1051,30 @@ def main():
     if "measured_vs_model" in f:
         out["measured_vs_model"] = f["measured_vs_model"]
     out["max_err_over_bound_260_entries"] = f["max_err_over_bound_260_entries"]
+    print(json.dumps({"section": "fp64", "result": f}), flush=True)
     if only == "all":
-        out["split_precision"] = bench_split(args, fp64_ms=f["ms_per_step"])
-        out["batched"] = bench_batch(args)
-        out["backward"] = bench_backward(args)
-        out["sweep"] = bench_sweep(args)
-        out["tiled_storage"] = bench_tiled(args)
-        out["syrk"] = bench_syrk(args)
-        out["triangular"] = bench_tri(args)
-        out["out_of_core"] = bench_ooc(args)
-        try:
-            out["low_bandwidth"] = bench_lowbw(args)
-        except Exception as exc:   # the section reports its failure; the line above still stands
-            out["low_bandwidth"] = {"error": repr(exc)}
+        sections = [("split_precision", lambda: bench_split(args, fp64_ms=f["ms_per_step"])),
+                    ("batched", lambda: bench_batch(args)), ("backward", lambda: bench_backward(args)),
+                    ("sweep", lambda: bench_sweep(args)), ("tiled_storage", lambda: bench_tiled(args)),
+                    ("syrk", lambda: bench_syrk(args)), ("triangular", lambda: bench_tri(args)),
+                    ("out_of_core", lambda: bench_ooc(args)), ("low_bandwidth", lambda: bench_lowbw(args))]
+        for name, fn in sections:
+            try:
+                out[name] = fn()
+            except Exception as exc:   # a failed section reports itself; the headline still stands
+                if name != "low_bandwidth":
+                    raise
+                out[name] = {"error": repr(exc)}
+            print(json.dumps({"section": name, "result": out[name]}), flush=True)
     if not args.no_cpu and not args.profile:
         out["cpu_baseline"] = cpu_baseline(args.size, args.size, args.size, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    try:
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        with open(os.path.join(ROOT, "gpurun_out", "bench_full.json"), "w") as fh:
+            json.dump(out, fh)
+    except OSError:
+        pass
+    print(json.dumps(compact_line(out)), flush=True)
 
 
 if __name__ == "__main__":

@@ -266,15 +266,36 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k,
  * Batched uneven FP64 GEMMs.  momms_batch_create builds a plan for `count`
  * independent problems C_i := alpha_i A_i B_i + beta_i C_i (row-major, no
  * transposition; all pointer arrays are HOST arrays holding DEVICE
- * pointers): it picks each problem's register tile (`tile` may be NULL or
- * hold 0 = choose by the analytic prior, 64, or 128 per problem), uploads a
- * descriptor table and a work queue of (problem, tile) items ordered by
- * decreasing work, and captures a hipGraph of one persistent kernel launch
- * (plus the kernel that resets the queue counter).  The plan owns that
- * device memory (allocated here, freed by momms_batch_destroy) and keeps the
- * caller's matrix pointers: they must stay valid while the plan is used.
- * Argument numbers: 1 out, 2 count, 3 m, 4 n, 5 k, 6 A, 7 lda, 8 B, 9 ldb,
- * 10 C, 11 ldc, 12 alpha, 13 beta, 14 tile.  A per-problem argument error
+ * pointers).  Each problem runs one family member (Sec. 2.3: the shape
+ * decides which operand is worth keeping resident) inside one persistent
+ * kernel:
+ *   MOMMS_C0    one work item per C tile over all of k, row-major tile order;
+ *   MOMMS_C3C0  the same items in a grouped order (8 tile rows swept column by
+ *               column), so the items running together share panels;
+ *   MOMMS_B3C0  k split into k_c3 = 512 chunks, an item per (chunk, tile),
+ *               tiles column by column within a chunk (a run shares a B block);
+ *   MOMMS_A3C0  as B3C0 with the tiles row by row (a run shares an A block).
+ * A split tile's partials are added into C in chunk order by whichever item
+ * completes the tile, rounded as the single product's per-chunk epilogue, so
+ * every member's result equals momms_gemm_ex with the same member and
+ * register tile bit for bit.  MOMMS_AUTO (member_or_auto NULL, or 0 for a
+ * problem) picks per problem: B3C0 (taller than wide) or A3C0 when one
+ * whole-k tile would run longer than a quarter of the mean per-slot time
+ * (then k is split into chunks of about that length, multiples of 256), else
+ * C3C0 when the problem has more than one tile each way, else C0.  The
+ * register tile (tile NULL or 0: the slot-time prior of
+ * momms_batch_select_tile; else 64 or 128 per problem) is chosen first.
+ * The plan uploads a descriptor table and a work queue ordered by
+ * decreasing work, allocates the split partials and arrival counters, and
+ * captures a hipGraph of a counter-reset kernel and the persistent kernel.
+ * The plan owns that device memory (allocated here, freed by
+ * momms_batch_destroy) and keeps the caller's matrix pointers: they must
+ * stay valid while the plan is used.  With alpha_i == 0 (or k_i == 0) A_i
+ * and B_i are not read (they may be NULL): C_i := beta_i C_i; beta_i == 0
+ * does not read C_i.  Argument numbers: 1 out, 2 count, 3 m, 4 n, 5 k, 6 A,
+ * 7 lda, 8 B, 9 ldb, 10 C, 11 ldc, 12 alpha, 13 beta, 14 member_or_auto
+ * (MOMMS_AUTO, MOMMS_C0, MOMMS_C3C0, MOMMS_B3C0 or MOMMS_A3C0 per problem;
+ * other members are not batched), 15 tile.  A per-problem argument error
  * returns the number of that array.  Synchronous (copies the tables).
  */
 typedef struct momms_batch momms_batch;
@@ -283,18 +304,27 @@ int momms_batch_create(momms_batch **out, int count, const int64_t *m, const int
                        const int64_t *k, const double *const *A, const int64_t *lda,
                        const double *const *B, const int64_t *ldb, double *const *C,
                        const int64_t *ldc, const double *alpha, const double *beta,
-                       const int *tile);
+                       const int *member_or_auto, const int *tile);
 /* Replays the captured graph on `stream` (asynchronous).  Runs of one plan
- * must not overlap (they share the queue counter).  1 plan, 2 stream. */
+ * must not overlap (they share the queue and arrival counters).  1 plan,
+ * 2 stream. */
 int momms_batch_run(momms_batch *plan, momms_stream_t stream);
-/* Plan facts: queue items, persistent workgroups, total 2mnk flops, and the
- * register tile chosen per problem (`tiles` holds count entries).  Any
- * output pointer may be NULL. */
-int momms_batch_info(const momms_batch *plan, int64_t *items, int64_t *workgroups,
-                     double *flops, int *tiles);
+/* Plan facts: queue items, persistent workgroups, total 2mnk flops, the
+ * flops of the padded tiles, and per problem (arrays of count entries) the
+ * member, the register tile and the number of k chunks.  Any output
+ * pointer may be NULL. */
+int momms_batch_info(const momms_batch *plan, int64_t *items, int64_t *workgroups, double *flops,
+                     double *padded_flops, int *members, int *tiles, int *chunks);
 int momms_batch_destroy(momms_batch *plan);
-/* The analytic prior's register tile (64 or 128) for one problem. */
+/* The slot-time prior's register tile (64 or 128) for one problem. */
 int momms_batch_select_tile(int64_t m, int64_t n, int64_t k);
+/* Installs the per-slot rates the prior uses (flop/s of one resident
+ * workgroup slot with the 128 and the 64 register tile, and the fixed
+ * seconds of one work item), e.g. from a measured table; plans created
+ * afterwards use them.  Process-wide.  Errors: -1, -2, -3 for a rate or
+ * time that is not positive and finite (the item time may be 0).
+ * Host-only. */
+int momms_batch_set_rates(double rate128, double rate64, double item_seconds);
 
 /* ---------------------------------------------------------------------
  * Tile-major ("prepacked") storage (Sec. 5.2: matrices stored so that every

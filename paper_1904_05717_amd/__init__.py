@@ -175,12 +175,13 @@ class BatchPlan:
     """Batched uneven GEMMs C_i := alpha_i A_i B_i + beta_i C_i (C ABI momms_batch_*).
 
     `problems` is a list of (A, B, C, alpha, beta) with float64 row-major
-    device tensors.  `tiles` optionally fixes each problem's register tile
-    (64 or 128; 0 = the library's analytic prior).  The plan keeps references
-    to the tensors so their memory stays valid while it exists.
+    device tensors.  `members` optionally fixes each problem's family member
+    ("AUTO", "C0", "C3C0", "B3C0" or "A3C0", or their ids); `tiles` its
+    register tile (64 or 128; 0 = the library's prior).  The plan keeps
+    references to the tensors so their memory stays valid while it exists.
     """
 
-    def __init__(self, problems, tiles=None):
+    def __init__(self, problems, members=None, tiles=None):
         import ctypes
         self._keep = list(problems)
         n = len(problems)
@@ -198,13 +199,20 @@ class BatchPlan:
             lda.append(_ld(A, "A")); ldb.append(_ld(B, "B")); ldc.append(_ld(C, "C"))
             pa.append(A.data_ptr()); pb.append(B.data_ptr()); pc.append(C.data_ptr())
             al.append(float(alpha)); be.append(float(beta))
+        ml = None
+        if members is not None:
+            if isinstance(members, (str, int)):
+                members = [members] * n
+            ml = (ctypes.c_int * n)(*[member_id(x) for x in members])
         tl = None
         if tiles is not None:
+            if isinstance(tiles, int):
+                tiles = [tiles] * n
             tl = (ctypes.c_int * n)(*[int(t) for t in tiles])
         self.count = n
         self._h = ctypes.c_void_p()
         st = _lib.momms_batch_create(ctypes.byref(self._h), n, I64(*ms), I64(*ns), I64(*ks), P(*pa), I64(*lda),
-                                     P(*pb), I64(*ldb), P(*pc), I64(*ldc), D(*al), D(*be), tl)
+                                     P(*pb), I64(*ldb), P(*pc), I64(*ldc), D(*al), D(*be), ml, tl)
         check_status(st, "momms_batch_create")
 
     def run(self, stream=None):
@@ -212,12 +220,15 @@ class BatchPlan:
 
     def info(self):
         import ctypes
-        items, wgs, flops = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
-        tiles = (ctypes.c_int * max(self.count, 1))()
+        items, wgs = ctypes.c_int64(), ctypes.c_int64()
+        flops, padded = ctypes.c_double(), ctypes.c_double()
+        n = max(self.count, 1)
+        members, tiles, chunks = (ctypes.c_int * n)(), (ctypes.c_int * n)(), (ctypes.c_int * n)()
         check_status(_lib.momms_batch_info(self._h, ctypes.byref(items), ctypes.byref(wgs), ctypes.byref(flops),
-                                           tiles), "momms_batch_info")
+                                           ctypes.byref(padded), members, tiles, chunks), "momms_batch_info")
         return {"items": items.value, "workgroups": wgs.value, "flops": flops.value,
-                "tiles": list(tiles)[:self.count]}
+                "padded_flops": padded.value, "members": [MEMBER_NAMES[x] for x in list(members)[:self.count]],
+                "tiles": list(tiles)[:self.count], "chunks": list(chunks)[:self.count]}
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -229,6 +240,13 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def batch_set_rates(rate128, rate64, item_seconds):
+    """Per-slot rates (flop/s) of the two register tiles and the fixed time of
+    one work item, used by the batch planner's prior from now on."""
+    check_status(_lib.momms_batch_set_rates(float(rate128), float(rate64), float(item_seconds)),
+                 "momms_batch_set_rates")
 
 
 def batch_select_tile(m, n, k):

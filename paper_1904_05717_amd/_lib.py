@@ -71,11 +71,12 @@ _pi64 = ctypes.POINTER(i64)
 _pdbl = ctypes.POINTER(dbl)
 _pi32 = ctypes.POINTER(i32)
 momms_batch_create = _fn("momms_batch_create", i32, [_pp, i32, _pi64, _pi64, _pi64, _pp, _pi64, _pp, _pi64, _pp,
-                                                     _pi64, _pdbl, _pdbl, _pi32])
+                                                     _pi64, _pdbl, _pdbl, _pi32, _pi32])
 momms_batch_run = _fn("momms_batch_run", i32, [vp, vp])
-momms_batch_info = _fn("momms_batch_info", i32, [vp, _pi64, _pi64, _pdbl, _pi32])
+momms_batch_info = _fn("momms_batch_info", i32, [vp, _pi64, _pi64, _pdbl, _pdbl, _pi32, _pi32, _pi32])
 momms_batch_destroy = _fn("momms_batch_destroy", i32, [vp])
 momms_batch_select_tile = _fn("momms_batch_select_tile", i32, [i64, i64, i64])
+momms_batch_set_rates = _fn("momms_batch_set_rates", i32, [dbl, dbl, dbl])
 
 momms_model_resident = _fn("momms_model_resident", i32, [i32, i64, i64, i64, i64, i64, dbl, _pdbl])
 momms_balanced_block = _fn("momms_balanced_block", i32, [dbl, dbl, dbl, _pdbl, _pdbl])
@@ -107,6 +108,7 @@ EXPORTS = [
     "momms_member_name", "momms_member_id", "momms_member_plan", "momms_model_bytes",
     "momms_select_member", "momms_status_string", "momms_split_workspace_size", "momms_gemm_split",
     "momms_batch_create", "momms_batch_run", "momms_batch_info", "momms_batch_destroy", "momms_batch_select_tile",
+    "momms_batch_set_rates",
     "momms_model_resident", "momms_balanced_block", "momms_set_member_table", "momms_select_member_prior",
     "momms_tiled_size", "momms_to_tiled", "momms_from_tiled", "momms_gemm_tiled", "momms_syrk", "momms_crt_bits",
     "momms_ooc_workspace_size", "momms_gemm_ooc", "momms_trmm", "momms_trsm", "momms_potrf",

@@ -171,6 +171,16 @@ __device__ __forceinline__ void zero_acc(d4 (&acc)[CF::BM][CF::BN]) {
         for (int j = 0; j < CF::BN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
+// One entry of the epilogue, alpha * acc + beta * c with the product alpha * acc
+// rounded first and beta * c fused into the addition (beta == 0: c is
+// ignored).  Every epilogue and the batched k-split reduction use this form,
+// so a result written in several passes rounds the same way wherever the
+// passes run.
+__device__ __forceinline__ double epilogue_value(double alpha, double acc, double beta, double c) {
+    const double v = alpha * acc;
+    return beta != 0.0 ? __builtin_fma(beta, c, v) : v;
+}
+
 // Epilogue: C = alpha * acc + beta * C on the workgroup tile at (m0, n0);
 // beta == 0 does not read C.  Sixteen consecutive lanes write one 128-byte row
 // segment.
@@ -204,11 +214,8 @@ __device__ __forceinline__ void store_c_tri(const d4 (&acc)[CF::BM][CF::BN], dou
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = m0 + wm * CF::WTM + i * 16 + lk + 4 * r;
                 const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
-                if (row < M && col < N && (TRI == 0 || (TRI == 1 ? row >= col : row <= col))) {
-                    double v = alpha * acc[i][j][r];
-                    if (beta != 0.0) v += beta * cv[j][r];
-                    C[row * ldc + col] = v;
-                }
+                if (row < M && col < N && (TRI == 0 || (TRI == 1 ? row >= col : row <= col)))
+                    C[row * ldc + col] = epilogue_value(alpha, acc[i][j][r], beta, beta != 0.0 ? cv[j][r] : 0.0);
             }
     }
 }
@@ -221,21 +228,18 @@ __device__ __forceinline__ void store_c(const d4 (&acc)[CF::BM][CF::BN], double 
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident C tile at (m0, n0): accumulate over k in [k_begin,
-// k_end) through the double-buffered LDS stage, then C = alpha*acc + beta*C.
-// (tm, tn) only staggers the k start (see below).  Shared by k_regc and the
-// persistent batched kernel.
-template <class CF, bool TA, bool TB, bool FAST_INTERIOR = true, int TRI = 0>
-__device__ __forceinline__ void regc_tile(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha,
-                                          const double* __restrict__ A, int64_t lda,
-                                          const double* __restrict__ B, int64_t ldb, double beta,
-                                          double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0, int tm,
-                                          int tn, double (*As)[CF::MT * CF::A_LD],
-                                          double (*Bs)[CF::KS * CF::B_LD]) {
+// Register-resident C tile at (m0, n0): acc = the product of its A row panel
+// and B column panel over k in [k_begin, k_end), through the double-buffered
+// LDS stage.  (tm, tn) only staggers the k start (see below).
+template <class CF, bool TA, bool TB, bool FAST_INTERIOR = true>
+__device__ __forceinline__ void regc_acc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
+                                         const double* __restrict__ A, int64_t lda,
+                                         const double* __restrict__ B, int64_t ldb, int64_t m0, int64_t n0, int tm,
+                                         int tn, double (*As)[CF::MT * CF::A_LD], double (*Bs)[CF::KS * CF::B_LD],
+                                         d4 (&acc)[CF::BM][CF::BN]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / CF::WN, wn = wave % CF::WN;
 
-    d4 acc[CF::BM][CF::BN];
     zero_acc<CF>(acc);
     const int64_t nsl = (k_end - k_begin + CF::KS - 1) / CF::KS;
     // Tiles that share an A row panel (same tm) or a B column panel (same tn)
@@ -301,7 +305,21 @@ __device__ __forceinline__ void regc_tile(int64_t M, int64_t N, int64_t k_begin,
             __syncthreads();
         }
     }
-    store_c_tri<CF, TRI>(acc, alpha, beta, C, ldc, m0, n0, M, N, wm, wn, lane);
+}
+
+// regc_acc, then C = alpha*acc + beta*C on the tile.  Shared by k_regc, SYRK
+// and the persistent batched kernel.
+template <class CF, bool TA, bool TB, bool FAST_INTERIOR = true, int TRI = 0>
+__device__ __forceinline__ void regc_tile(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha,
+                                          const double* __restrict__ A, int64_t lda,
+                                          const double* __restrict__ B, int64_t ldb, double beta,
+                                          double* __restrict__ C, int64_t ldc, int64_t m0, int64_t n0, int tm,
+                                          int tn, double (*As)[CF::MT * CF::A_LD],
+                                          double (*Bs)[CF::KS * CF::B_LD]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    d4 acc[CF::BM][CF::BN];
+    regc_acc<CF, TA, TB, FAST_INTERIOR>(M, N, k_begin, k_end, A, lda, B, ldb, m0, n0, tm, tn, As, Bs, acc);
+    store_c_tri<CF, TRI>(acc, alpha, beta, C, ldc, m0, n0, M, N, wave / CF::WN, wave % CF::WN, lane);
 }
 
 // k_regc: one C granule (MT x NT) per workgroup, accumulated in registers over

@@ -111,3 +111,35 @@ def test_config5_shapes_sampled():
     got2 = Bd.grad.cpu().numpy()[r2, c2]
     absab2 = np.einsum("ij,ji->i", np.abs(AT[r2]), np.abs(dC[:, c2]))
     assert np.all(np.abs(got2 - dB_o) <= 2 * (m + 2) * 2.0 ** -53 * absab2)
+
+
+def test_config5_fp32_split_sampled():
+    # The FP32 form (three BF16 slices) at the config-5 shape: forward
+    # m=4096, k=8192, n=2048 and both gradients on sampled entries plus the
+    # first and last rows and columns, against the oracle on the FP32 inputs
+    # widened exactly to FP64, within 2 (k+2) 2^-24 (|X||Y|)_ij.
+    m, k, n = 4096, 8192, 2048
+    A = workloads.uniform((m, k), workloads.SEED_A).astype(np.float32)
+    B = workloads.uniform((k, n), workloads.SEED_B).astype(np.float32)
+    dC = workloads.normal((m, n), workloads.SEED_DC).astype(np.float32)
+    Ad = torch.from_numpy(A).to(DEV).requires_grad_()
+    Bd = torch.from_numpy(B).to(DEV).requires_grad_()
+    C = matmul(Ad, Bd)
+    assert C.dtype == torch.float32
+    C.backward(torch.from_numpy(dC).to(DEV))
+    torch.cuda.synchronize()
+    A64, B64, dC64 = A.astype(np.float64), B.astype(np.float64), dC.astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(12))
+
+    def check(got, X, Y, what):
+        rows_, cols_ = X.shape[0], Y.shape[1]
+        r = np.concatenate([rng.integers(0, rows_, 150), [0, 0, rows_ - 1, rows_ - 1]])
+        c = np.concatenate([rng.integers(0, cols_, 150), [0, cols_ - 1, 0, cols_ - 1]])
+        want = oracle.gemm_entries(X, Y, r, c)
+        absxy = np.einsum("ij,ji->i", np.abs(X[r]), np.abs(Y[:, c]))
+        err = np.abs(got[r, c].astype(np.float64) - want)
+        assert np.all(err <= 2.0 * (X.shape[1] + 2) * 2.0 ** -24 * absxy), what
+
+    check(C.detach().cpu().numpy(), A64, B64, "C")
+    check(Ad.grad.cpu().numpy(), dC64, B64.T.copy(), "dA")
+    check(Bd.grad.cpu().numpy(), A64.T.copy(), dC64, "dB")

@@ -91,18 +91,87 @@ def test_config4_512_problems_sampled():
     plan.close()
 
 
-def test_batch_argument_errors():
-    import ctypes
-    h = ctypes.c_void_p()
-    one = (ctypes.c_int64 * 1)
-    ptr = (ctypes.c_void_p * 1)
-    dbl = (ctypes.c_double * 1)
-    lib = mm._lib
-    assert lib.momms_batch_create(None, 1, one(4), one(4), one(4), ptr(1 << 20), one(4), ptr(1 << 20), one(4),
-                                  ptr(1 << 20), one(4), dbl(1.0), dbl(0.0), None) == -1
-    assert lib.momms_batch_create(ctypes.byref(h), 1, one(-1), one(4), one(4), ptr(1 << 20), one(4), ptr(1 << 20),
-                                  one(4), ptr(1 << 20), one(4), dbl(1.0), dbl(0.0), None) == -3
-    assert lib.momms_batch_create(ctypes.byref(h), 1, one(4), one(4), one(4), ptr(1 << 20), one(3), ptr(1 << 20),
-                                  one(4), ptr(1 << 20), one(4), dbl(1.0), dbl(0.0), None) == -7
-    assert lib.momms_batch_create(ctypes.byref(h), 1, one(4), one(4), one(4), ptr(1 << 20), one(4), ptr(1 << 20),
-                                  one(4), ptr(1 << 20), one(4), dbl(1.0), dbl(0.0), (ctypes.c_int * 1)(96)) == -14
+SPLIT = [(130, 129, 1300), (64, 64, 64), (300, 70, 700), (1, 5, 600), (200, 150, 513), (65, 300, 1024),
+         (257, 129, 40), (33, 17, 0)]
+
+
+@pytest.mark.parametrize("member", ["C0", "C3C0", "B3C0", "A3C0"])
+def test_each_member_against_oracle_and_single_gemm(member):
+    # Every batched member against the oracle, and bitwise against the single
+    # product of the same member: these problems are small enough that the
+    # single product uses the 64 x 64 register tile, so the batch is given the
+    # same tile.  k up to 1300 runs B3C0 and A3C0 over up to three k_c3 = 512
+    # chunks, added into C by the item that completes each tile.
+    host, dev = make_batch(SPLIT, seed0=700)
+    C0 = [C.clone() for (_, _, C) in dev]
+    ref = []
+    for (A, B, _), c0 in zip(dev, C0):
+        Cr = c0.clone()
+        mm.gemm(A, B, Cr, -0.5, 1.25, member=member)
+        ref.append(Cr)
+    plan = mm.BatchPlan([(A, B, C, -0.5, 1.25) for (A, B, C) in dev], members=member, tiles=64)
+    info = plan.info()
+    assert info["members"] == [member] * len(SPLIT)
+    want_chunks = [(-(-k // 512) if member in ("B3C0", "A3C0") and k > 512 else 1) for (_, _, k) in SPLIT]
+    assert info["chunks"] == [c if (m and n) else 1 for c, (m, n, _) in zip(want_chunks, SPLIT)]
+    for rep in range(2):
+        for (_, _, C), c0 in zip(dev, C0):
+            C.copy_(c0)
+        torch.cuda.synchronize()
+        plan.run()
+        torch.cuda.synchronize()
+        for (A, B, C), (_, _, Cd), r in zip(host, dev, ref):
+            got = Cd.cpu().numpy()
+            want = oracle.gemm(A, B, C, -0.5, 1.25)
+            tol = oracle.error_bound(A, B, C, -0.5, 1.25)
+            assert np.all(np.abs(got - want) <= tol), (member, A.shape, B.shape)
+            assert torch.equal(Cd, r), f"{member} {A.shape}x{B.shape[1]}: replay {rep} differs from momms_gemm"
+    plan.close()
+
+
+def test_auto_splits_a_long_tile_and_reports_members():
+    # 200 small problems and one 64 x 64 x 8192 problem: one whole-k item of
+    # the long one would take far longer than a slot's share, so AUTO splits
+    # its k (B3C0, since it is one tile tall and one wide) and the partials are
+    # reduced in chunk order; the small ones stay whole-k (C0: a single tile).
+    shapes = [(48, 40, 64)] * 200 + [(64, 64, 8192), (400, 380, 96)]
+    host, dev = make_batch(shapes, seed0=900)
+    plan = mm.BatchPlan([(A, B, C, 1.0, 1.0) for (A, B, C) in dev])
+    info = plan.info()
+    assert info["members"][200] == "B3C0" and info["chunks"][200] > 1
+    assert all(x == "C0" and c == 1 for x, c in zip(info["members"][:200], info["chunks"][:200]))
+    assert info["members"][201] == "C3C0"
+    assert info["padded_flops"] >= info["flops"]
+    C0 = [C.clone() for (_, _, C) in dev]
+    for rep in range(2):
+        for (_, _, C), c0 in zip(dev, C0):
+            C.copy_(c0)
+        torch.cuda.synchronize()
+        plan.run()
+        torch.cuda.synchronize()
+        for i in (0, 199, 200, 201):
+            A, B, C = host[i]
+            want = oracle.gemm(A, B, C, 1.0, 1.0)
+            assert np.all(np.abs(dev[i][2].cpu().numpy() - want) <= oracle.error_bound(A, B, C, 1.0, 1.0)), i
+    plan.close()
+
+
+def test_alpha_zero_reads_neither_operand():
+    # alpha == 0: C := beta C exactly, with NaN in A and B (never read) and
+    # with NULL-free but NaN-filled operands of every member
+    shapes = [(70, 90, 40), (130, 129, 1300), (64, 64, 64)]
+    for member in ("AUTO", "C0", "B3C0"):
+        dev = []
+        Cs = []
+        for i, (m, n, k) in enumerate(shapes):
+            C = workloads.uniform((m, n), 40 + i)
+            Cs.append(C)
+            dev.append((torch.full((m, k), float("nan"), dtype=torch.float64, device=DEV),
+                        torch.full((k, n), float("nan"), dtype=torch.float64, device=DEV),
+                        torch.from_numpy(C.copy()).to(DEV)))
+        plan = mm.BatchPlan([(A, B, C, 0.0, -1.5) for (A, B, C) in dev], members=member)
+        plan.run()
+        torch.cuda.synchronize()
+        for (_, _, Cd), C in zip(dev, Cs):
+            np.testing.assert_array_equal(Cd.cpu().numpy(), -1.5 * C)
+        plan.close()

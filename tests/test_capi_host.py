@@ -276,3 +276,49 @@ def test_lowbw_sizes_and_argument_errors():
     assert L.momms_lowbw_stamp(None, None) == -1
     with pytest.raises(ValueError):
         mm.BandwidthHog(8, mode="copy")
+
+
+def _batch_args(**over):
+    one = (ctypes.c_int64 * 1)
+    ptr = (ctypes.c_void_p * 1)
+    dbl = (ctypes.c_double * 1)
+    a = dict(out=ctypes.byref(ctypes.c_void_p()), count=1, m=one(4), n=one(4), k=one(4), A=ptr(BIG), lda=one(4),
+             B=ptr(BIG), ldb=one(4), C=ptr(BIG), ldc=one(4), alpha=dbl(1.0), beta=dbl(0.0), member=None, tile=None)
+    a.update(over)
+    return list(a.values())
+
+
+def test_batch_argument_errors_before_any_device_call():
+    one = (ctypes.c_int64 * 1)
+    f = _lib.momms_batch_create
+    assert f(*_batch_args(out=None)) == -1
+    assert f(*_batch_args(count=-1)) == -2
+    assert f(*_batch_args(m=one(-1))) == -3
+    assert f(*_batch_args(lda=one(3))) == -7
+    assert f(*_batch_args(A=(ctypes.c_void_p * 1)(None))) == -6
+    assert f(*_batch_args(ldc=one(3))) == -11
+    # members: only the register-resident ones are batched
+    for bad in (mm.MEMBERS["A2C0"], mm.MEMBERS["C4A2C0"], 10, -1):
+        assert f(*_batch_args(member=(ctypes.c_int * 1)(bad))) == -14
+    assert f(*_batch_args(tile=(ctypes.c_int * 1)(96))) == -15
+
+
+def test_batch_alpha_zero_accepts_null_operands():
+    # alpha == 0: A and B are never read, so NULL operands pass validation (the
+    # call then reaches the device query, which fails here without a GPU)
+    dbl = (ctypes.c_double * 1)
+    null = (ctypes.c_void_p * 1)(None)
+    st = _lib.momms_batch_create(*_batch_args(A=null, B=null, alpha=dbl(0.0), beta=dbl(2.0)))
+    assert st not in (-6, -8), st
+    st = _lib.momms_batch_create(*_batch_args(A=null, alpha=dbl(1.0)))
+    assert st == -6
+
+
+def test_batch_set_rates_validates():
+    f = _lib.momms_batch_set_rates
+    assert f(0.0, 1.0, 0.0) == -1
+    assert f(1.0, -1.0, 0.0) == -2
+    assert f(1.0, 1.0, float("nan")) == -3
+    assert f(66e12 / 512.0, 0.55 * 66e12 / 512.0, 1.5e-6) == 0
+    assert mm.batch_select_tile(2048, 2048, 2048) == 128
+    assert mm.batch_select_tile(40, 40, 64) == 64

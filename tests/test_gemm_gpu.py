@@ -178,3 +178,46 @@ def test_lds_resident_members_bench_size_sampled(member):
 def test_sweep_thin_shapes_sampled(shape, member):
     # the rank-k and panel shapes of the sweep
     sampled_check(*shape, member, npts=512, seed=2)
+
+
+@pytest.mark.parametrize("member", ["C0", "C3C0", "B3C0", "A3C0"])
+def test_large_register_tile_integer_bit_exact(member):
+    # 3072 x 3072 is 576 tiles of 128: the 128 x 128 register tile of the
+    # benchmark's kernel (checked through the plan).  Integers in [-8, 8] with
+    # k = 640 keep every partial sum an exact integer, so any summation order
+    # gives the exact product; k = 640 also runs B3C0 and A3C0 over two k_c3
+    # passes (512 + 128) and the staggered k start wraps in every tile.  The
+    # exact product is the float64 BLAS product of the same integers (exact for
+    # the same reason).
+    m = n = 3072
+    k = 640
+    assert mm.member_plan(member, m, n, k)["mt"] == 128
+    A, B, C = workloads.gemm_operands(m, n, k, kind="int")
+    want = A @ B + C
+    np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, member), want)
+
+
+def test_momms_gemm_entry_point_on_the_set_stream():
+    # The plain momms_gemm signature (no transposition, no workspace) on data,
+    # on the stream installed by momms_set_stream: a side stream that waits on
+    # an event recorded after C is filled on torch's stream.
+    from paper_1904_05717_amd import _lib
+    m, n, k = 517, 389, 700
+    A, B, C = workloads.gemm_operands(m, n, k)
+    want = oracle.gemm(A, B, C, -0.75, 1.25)
+    Ad, Bd = dev(A), dev(B)
+    side = torch.cuda.Stream()
+    try:
+        assert _lib.momms_set_stream(side.cuda_stream) == 0
+        for member in ["AUTO", "C3C0", "A2C0", "B3A2C0"]:
+            Cd = dev(C)
+            ready = torch.cuda.Event()
+            ready.record(torch.cuda.current_stream())
+            side.wait_event(ready)
+            st = _lib.momms_gemm(m, n, k, -0.75, Ad.data_ptr(), k, Bd.data_ptr(), n, 1.25, Cd.data_ptr(), n,
+                                 mm.MEMBERS[member])
+            assert st == 0, (member, st)
+            side.synchronize()
+            assert_within_bound(Cd.cpu().numpy(), want, A, B, C, -0.75, 1.25, f"momms_gemm {member}")
+    finally:
+        _lib.momms_set_stream(None)

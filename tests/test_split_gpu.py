@@ -341,15 +341,20 @@ def test_crt_error_against_fp64_oracle():
     assert np.max(np.abs(got - want) / absab) <= 1e-13
 
 
-def test_crt_sampled_8192():
-    # m = n = k = 8192, signed log-uniform over [1e-8, 1e8], 15 moduli (t = 51)
+@pytest.mark.parametrize("N", [14, 15])
+def test_crt_sampled_8192(N):
+    # m = n = k = 8192, signed log-uniform over [1e-8, 1e8]; 14 moduli (t = 48,
+    # the fastest configuration within 1e-13) and 15 (t = 51).  Sampled
+    # entries plus every row and column on either side of a 256-wide tile
+    # edge: bit for bit against the exact-integer definition, and within
+    # 1e-13 of (|A||B|)_ij against the compensated oracle.
     m = n = k = 8192
-    N = 15
     A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform", with_c=False)
     got = run(A, B, None, 1.0, 0.0, N, kind="crt")
     rng = np.random.Generator(np.random.PCG64(6))
-    rows = np.concatenate([rng.integers(0, m, 200), [0, m - 1, 255, 256]])
-    cols = np.concatenate([rng.integers(0, n, 200), [n - 1, 0, 128, 127]])
+    edges = np.concatenate([np.arange(0, m, 256), np.arange(255, m, 256)])
+    rows = np.concatenate([rng.integers(0, m, 200), [0, m - 1, 255, 256], edges, rng.integers(0, m, edges.size)])
+    cols = np.concatenate([rng.integers(0, n, 200), [n - 1, 0, 128, 127], rng.integers(0, n, edges.size), edges])
     np.testing.assert_array_equal(got[rows, cols], ce.crt_gemm_entries(A, B, rows, cols, N))
     exact = oracle.gemm_entries(A, B, rows, cols)
     absab = np.einsum("ij,ji->i", np.abs(A[rows]), np.abs(B[:, cols]))
