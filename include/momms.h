@@ -83,6 +83,7 @@ enum momms_member {
 #define MOMMS_ERR_INFEASIBLE 1002   /* problem too large for the tile grid   */
 #define MOMMS_ERR_NO_DEVICE 1003    /* no gfx950 device / HIP init failed    */
 #define MOMMS_ERR_INTERNAL 1004
+#define MOMMS_ERR_SCRATCH 1005      /* needs more than the static scratch    */
 
 /* Blocking plan of one member for one problem (host-side description). */
 typedef struct momms_plan {
@@ -147,6 +148,28 @@ int momms_gemm_ex(int transA, int transB, int64_t m, int64_t n, int64_t k,
                   const double *B, int64_t ldb, double beta,
                   double *C, int64_t ldc, int family_member,
                   void *workspace, size_t ws_bytes, momms_stream_t stream);
+
+/* Allocation-free form of momms_gemm_ex, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same product, arguments 1-14 as in
+ * momms_gemm_ex and 15 stream, with no workspace argument.  A member that
+ * packs a panel (A2C0) packs it into a library-owned static device array of
+ * MOMMS_STATIC_SCRATCH_BYTES (4 MiB) instead, so the result is bitwise equal
+ * to momms_gemm_ex with a workspace; other members use no scratch.  If the
+ * member would need more than the array holds the call returns
+ * MOMMS_ERR_SCRATCH before any HIP call (no member does at present: Goto's
+ * panel is at most 128 x 4096 doubles).  Each GPU has its own array, kept
+ * until the process ends and shared by every call on that GPU: calls that
+ * overlap in time on one GPU (different streams, or different host threads)
+ * race on it and must be serialized by the caller.  Nothing is allocated,
+ * freed or synchronized; the first call on a device looks up the array's
+ * device address (hipGetSymbolAddress) with that device current. */
+#define MOMMS_STATIC_SCRATCH_BYTES ((size_t)4 << 20)
+int momms_gemm_static(int transA, int transB, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double *A, int64_t lda,
+                      const double *B, int64_t ldb, double beta,
+                      double *C, int64_t ldc, int family_member,
+                      momms_stream_t stream);
 
 /* Workspace bytes the member needs to pack its streamed panel for this
  * shape (0 if it packs nothing).  Host-only. */

@@ -52,6 +52,8 @@ def _fn(name, res, args):
 momms_gemm = _fn("momms_gemm", i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32])
 momms_gemm_ex = _fn("momms_gemm_ex", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32,
                                            vp, sz, vp])
+momms_gemm_static = _fn("momms_gemm_static", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64,
+                                                   i32, vp])
 momms_workspace_size = _fn("momms_workspace_size", sz, [i64, i64, i64, i32])
 momms_set_stream = _fn("momms_set_stream", i32, [vp])
 momms_num_members = _fn("momms_num_members", i32, [])

@@ -10,6 +10,7 @@
 
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 #include "../../include/momms.h"
 #include "kernels_f64.hip"
@@ -241,6 +242,58 @@ static bool grid_fits(int64_t M, int64_t N) {
     return t < (int64_t)INT_MAX / 2;
 }
 
+// Host-side argument checks shared by the FP64 entry points (argument
+// numbers of momms_gemm_ex).  No HIP call.
+static int check_args(int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                      int64_t lda, const double* B, int64_t ldb, const double* C, int64_t ldc, int member) {
+    const bool ta = transA != 0, tb = transB != 0;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const bool reads_ab = (alpha != 0.0) && k > 0 && m > 0 && n > 0;
+    if (reads_ab && A == nullptr) return -7;
+    if (lda < (ta ? (m > 1 ? m : 1) : (k > 1 ? k : 1))) return -8;
+    if (reads_ab && B == nullptr) return -9;
+    if (ldb < (tb ? (k > 1 ? k : 1) : (n > 1 ? n : 1))) return -10;
+    if (m > 0 && n > 0 && C == nullptr) return -12;
+    if (ldc < (n > 1 ? n : 1)) return -13;
+    if (member < 0 || member >= MOMMS_NUM_MEMBERS) return -14;
+    if (!grid_fits(m, n)) return MOMMS_ERR_INFEASIBLE;
+    return 0;
+}
+
+// Scratch of the allocation-free entry point: Goto's packed B panel (k_c rows
+// of at most n_c = 4096 columns, the largest workspace any member asks for)
+// in a static device array.  Each GPU holds its own copy for the life of the
+// process.  In host code `scratch` names a host-side stand-in, never the
+// device memory: its device address is taken once per device with that device
+// current, and only that address is passed to kernels.
+constexpr size_t kStaticScratchBytes = (size_t)kKC * 4096 * sizeof(double);   // 4 MiB
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+static int static_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= kMaxDevices) return MOMMS_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255u) != 0) return MOMMS_ERR_INTERNAL;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return 0;
+}
+
+static_assert(kStaticScratchBytes % 256 == 0, "scratch must keep the workspace alignment");
+static_assert(kStaticScratchBytes == MOMMS_STATIC_SCRATCH_BYTES, "header and library disagree on the scratch size");
+
 }  // namespace momms
 
 extern "C" {
@@ -254,20 +307,9 @@ int momms_gemm_ex(int transA, int transB, int64_t m, int64_t n, int64_t k, doubl
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int family_member,
                   void* workspace, size_t ws_bytes, momms_stream_t stream) {
     using namespace momms;
-    const bool ta = transA != 0, tb = transB != 0;
-    if (m < 0) return -3;
-    if (n < 0) return -4;
-    if (k < 0) return -5;
-    const bool reads_ab = (alpha != 0.0) && k > 0 && m > 0 && n > 0;
-    if (reads_ab && A == nullptr) return -7;
-    if (lda < (ta ? (m > 1 ? m : 1) : (k > 1 ? k : 1))) return -8;
-    if (reads_ab && B == nullptr) return -9;
-    if (ldb < (tb ? (k > 1 ? k : 1) : (n > 1 ? n : 1))) return -10;
-    if (m > 0 && n > 0 && C == nullptr) return -12;
-    if (ldc < (n > 1 ? n : 1)) return -13;
-    if (family_member < 0 || family_member >= MOMMS_NUM_MEMBERS) return -14;
+    const int bad = check_args(transA, transB, m, n, k, alpha, A, lda, B, ldb, C, ldc, family_member);
+    if (bad != 0) return bad;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return -15;
-    if (!grid_fits(m, n)) return MOMMS_ERR_INFEASIBLE;
 
     int member = family_member == MOMMS_AUTO ? select_member(m, n, k) : family_member;
     const size_t need = workspace_bytes(member, m, n, k);
@@ -286,8 +328,29 @@ int momms_gemm_ex(int transA, int transB, int64_t m, int64_t n, int64_t k, doubl
     }
     momms_plan p;
     if (plan_member(member, m, n, k, &p) != 0) return MOMMS_ERR_INTERNAL;
-    Args a{ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, st};
+    Args a{transA != 0, transB != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, st};
     return run_member(p, a, need > 0 ? workspace : nullptr);
+}
+
+int momms_gemm_static(int transA, int transB, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                      int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                      int family_member, momms_stream_t stream) {
+    using namespace momms;
+    const int bad = check_args(transA, transB, m, n, k, alpha, A, lda, B, ldb, C, ldc, family_member);
+    if (bad != 0) return bad;
+    const int member = family_member == MOMMS_AUTO ? select_member(m, n, k) : family_member;
+    const size_t need = workspace_bytes(member, m, n, k);
+    if (need > kStaticScratchBytes) return MOMMS_ERR_SCRATCH;
+    // Nothing to pack (or nothing to multiply): the workspace-free path.
+    const bool multiplies = m > 0 && n > 0 && k > 0 && alpha != 0.0;
+    if (need == 0 || !multiplies)
+        return momms_gemm_ex(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, member, nullptr, 0,
+                             stream);
+    void* ws = nullptr;
+    const int r = static_scratch(&ws);
+    if (r != 0) return r;
+    return momms_gemm_ex(transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, member, ws,
+                         kStaticScratchBytes, stream);
 }
 
 int momms_gemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda, const double* B,

@@ -538,6 +538,7 @@ const char* momms_status_string(int status) {
         case MOMMS_ERR_INFEASIBLE: return "problem too large for the tile grid";
         case MOMMS_ERR_NO_DEVICE: return "no usable gfx950 device";
         case MOMMS_ERR_INTERNAL: return "internal error";
+        case MOMMS_ERR_SCRATCH: return "the member needs more scratch than the static array holds";
         default: return "HIP runtime error (status is the hipError_t value)";
     }
 }

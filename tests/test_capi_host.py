@@ -76,6 +76,27 @@ def test_ex_argument_errors():
              None) == -16
 
 
+def test_static_argument_errors_and_quick_returns_before_any_device_call():
+    f = _lib.momms_gemm_static
+    goto = mm.MEMBERS["A2C0"]
+    assert f(0, 0, -1, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, goto, None) == -3
+    assert f(0, 0, 4, -1, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, goto, None) == -4
+    assert f(0, 0, 4, 4, -1, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, goto, None) == -5
+    assert f(0, 0, 4, 4, 4, 1.0, NULL, 4, BIG, 4, 0.0, BIG, 4, goto, None) == -7
+    assert f(1, 0, 8, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, goto, None) == -8
+    assert f(0, 0, 4, 4, 4, 1.0, BIG, 4, NULL, 4, 0.0, BIG, 4, goto, None) == -9
+    assert f(0, 1, 4, 4, 8, 1.0, BIG, 8, BIG, 4, 0.0, BIG, 4, goto, None) == -10
+    assert f(0, 0, 4, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, NULL, 4, goto, None) == -12
+    assert f(0, 0, 4, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 3, goto, None) == -13
+    assert f(0, 0, 4, 4, 4, 1.0, BIG, 4, BIG, 4, 0.0, BIG, 4, 99, None) == -14
+    # quick returns: nothing launched, no scratch looked up
+    assert f(0, 0, 0, 4, 4, 1.0, NULL, 4, NULL, 4, 0.0, NULL, 4, goto, None) == 0
+    assert f(0, 0, 4, 4, 4, 0.0, NULL, 4, NULL, 4, 1.0, BIG, 4, goto, None) == 0
+    # the largest panel any shape asks of Goto fits the static array exactly
+    assert _lib.momms_workspace_size(64, 1 << 20, 64, goto) == 4 << 20
+    assert _lib.momms_status_string(1005) != _lib.momms_status_string(1004)
+
+
 def test_quick_returns_do_not_touch_the_device():
     # m == 0, n == 0, or (alpha == 0 or k == 0) with beta == 1: nothing is launched
     assert _lib.momms_gemm(0, 4, 4, 1.0, NULL, 4, NULL, 4, 0.0, NULL, 4, 1) == 0
