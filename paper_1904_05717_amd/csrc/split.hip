@@ -50,8 +50,7 @@ constexpr int kB0 = 8;       // bits of the first BF16 slice
 constexpr int kB = 9;        // bits of every further slice
 constexpr int kMT = 128;     // workgroup tile of the slice-product kernel
 constexpr int kKS = 64;      // k-slice staged in LDS (bf16 elements)
-constexpr int kKPad = 64;    // k padded to a multiple of this
-constexpr int kLdsPitch = kKS + 8;  // 144-byte rows: conflict-free 16-byte fragment reads
+constexpr int kKPad = 256;   // k padded to a multiple of this (whole fold periods)
 constexpr int kExpNone = INT_MIN;   // exponent of an all-zero row/column
 // INT8 slices: 7 bits each (truncation keeps |d| <= 127); workgroup tile
 // 256 x 128, k-slice 128 bytes.  Every INT32 sum of one diagonal is exact
@@ -401,145 +400,278 @@ __global__ __launch_bounds__(256) void k_crt_combine(int64_t M, int64_t N, const
     }
 }
 
-// One diagonal d of the slice products for the 128 x 128 C tile of this
-// workgroup: Q = sum_{s=0..d} D^A_s D^B_{d-s} over the padded k range, then
-// the recombination step of s4.  SA is [S][mp][kp], SB is [S][np][kp] (B
-// stored column by column), both BF16, zero-padded.
-template <bool FIRST, bool LAST>
-__global__ __launch_bounds__(512) void k_split_diag(int64_t M, int64_t N, int64_t kp, int d,
-                                                    const uint16_t* __restrict__ SA,
-                                                    const uint16_t* __restrict__ SB, int64_t sa_stride,
-                                                    int64_t sb_stride, int shift, const int* __restrict__ ea,
-                                                    const int* __restrict__ eb, double* __restrict__ V,
-                                                    int64_t ldv, double alpha, double beta,
-                                                    double* __restrict__ C, int64_t ldc, Sched sc) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][kMT * kLdsPitch];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kMT * kLdsPitch];
+// BF16 slice products and recombination (s3 + s4) for every diagonal in one
+// launch.  The workgroup owns a 256 x 128 tile of C and walks the diagonals
+// d = S-1 .. 0 (smallest terms first); for each, the pairs s = 0 .. d, and
+// for each pair the k range in 64-deep steps:
+//   Q_d = sum_{s=0..d} D^A_s D^B_{d-s}   (v_mfma_f32_16x16x32_bf16),
+// exact: products are at most 2^16, so an FP32 accumulator stays an exact
+// integer for 256 of them (four steps) and is then added into an exact FP64
+// sum (a quarter of the accumulators on each step).  At the end of a diagonal the recombination step of s4 runs on the
+// tile: V = Q_d 2^-(16+9d) (first diagonal) or V + Q_d 2^-(16+9d), and on
+// the last diagonal C = fl(fl(alpha V 2^(e_i+f_j)) + fl(beta C)).  V lives
+// in the workspace between diagonals; only this workgroup touches its tile.
+//
+// Eight waves of 64 x 64 (4 along m, 2 along n; 16 accumulator blocks, 64
+// FP32 and 128 FP64 accumulator registers per lane).  Per 64-deep step a
+// wave reads 16 KiB of fragments from LDS for 32 MFMAs.  SA is [S][mp][kp],
+// SB is [S][np][kp] (B by column), BF16, zero-padded to the tile and to kp.
+//
+// Staging: global -> LDS directly (global_load_lds_dwordx4, no staging
+// registers), three LDS stages of one step each (48 KiB), issued two steps
+// ahead.  A stage holds each operand as two 32-deep windows of 64-byte rows;
+// the 16-byte chunk q of row r sits in slot q ^ ((r >> 1) & 3), so the
+// 16-row fragment reads (row li, chunk lk) are free of bank conflicts.  One
+// DMA instruction fills 16 rows of one window (lane L: row L / 4, slot
+// L % 4, which holds chunk (L % 4) ^ ((L / 8) & 3)); wave w fills A row
+// groups 4w .. 4w+3 and B row groups 2w, 2w+1 of every stage.
+namespace bf {
+constexpr int kMT = 256, kNT = 128;                     // workgroup tile
+constexpr int kWinA = kMT * 64, kWinB = kNT * 64;       // bytes of one 32-deep window
+constexpr int kStageA = 2 * kWinA, kStageB = 2 * kWinB; // one 64-deep step
+constexpr int kStage = kStageA + kStageB;               // 48 KiB
+constexpr int kStages = 3;
+static_assert(kStage / 1024 == 6 * 8, "1 KiB per wave instruction: four A and two B per wave");
+
+__device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^ ((r >> 1) & 3)); }
+
+typedef __attribute__((address_space(1))) const uint8_t gbyte;
+typedef __attribute__((address_space(3))) void lvoid;
+}  // namespace bf
+
+// SA and SB are not __restrict__ (see k_split_i8_diag).
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_split_bf16(int64_t M, int64_t N, int64_t kp, int S, const uint16_t* SA, const uint16_t* SB,
+                  int64_t sa_stride, int64_t sb_stride, const int* __restrict__ ea, const int* __restrict__ eb,
+                  double* __restrict__ V, int64_t ldv, double alpha, double beta, double* __restrict__ C,
+                  int64_t ldc, Sched sc) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[bf::kStages * bf::kStage];
     int tm, tn;
     decode_tile(sc, blockIdx.x, tm, tn);
-    const int64_t m0 = sc.m_off + (int64_t)tm * kMT, n0 = sc.n_off + (int64_t)tn * kMT;
-    // 8 waves as 2 (m) x 4 (n); each wave owns a 64 x 32 sub-tile: 4 x 2
-    // blocks of 16 x 16.
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 2, wn = wave & 3;
+    const int64_t m0 = sc.m_off + (int64_t)tm * bf::kMT, n0 = sc.n_off + (int64_t)tn * bf::kNT;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: keeps DMA targets scalar
+    const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
 
-    f4 acc[4][2];
-    double q[4][2][4];
+    // Fragment i of a window starts 16 rows (1 KiB) after fragment i - 1,
+    // with the same swizzle, so one offset per operand serves all four.
+    const int fa0 = bf::lds_off(wm * 64 + li, lk), fb0 = bf::kStageA + bf::lds_off(wn * 64 + li, lk);
+
+    // DMA sources (byte offsets from the tile's first row at the step's k)
+    // and LDS destinations (from the stage's start) of this thread.
+    const int dr = lane >> 2, dq = (lane & 3) ^ ((dr >> 1) & 3);
+    const int64_t rowb = 2 * kp;   // bytes per slice row
+    // 32-bit per-lane offsets that never change, added to a scalar base per
+    // step: the DMA then takes the scalar-base form, and no address register
+    // of an instruction in flight is ever rewritten
+    // Wave w's four A instructions cover row groups 4w .. 4w+3 of one window
+    // (16 rows apart: a scalar step), its two B instructions row groups 2w,
+    // 2w+1 of one window.
+    const int wa = (4 * wave) >> 4, ga0 = (4 * wave) & 15, wb = (2 * wave) >> 3, gb0 = (2 * wave) & 7;
+    uint32_t voffa = (uint32_t)((16 * ga0 + dr) * rowb + wa * 64 + dq * 16);
+    uint32_t voffb = (uint32_t)((16 * gb0 + dr) * rowb + wb * 64 + dq * 16);
+    const int ldsta = wa * bf::kWinA + ga0 * 1024, ldstb = bf::kStageA + wb * bf::kWinB + gb0 * 1024;
+    const int64_t grp = 16 * rowb;   // bytes between two row groups
+
+    const int nks = (int)(kp / kKS);
+    const int total = S * (S + 1) / 2 * nks;
+    const int last = total - 1;
+    // Tiles sharing a slice panel start their k loops apart (as in the FP64
+    // kernel): step kq of a pair reads k-step (kq + kshift) mod nks.
+    const int kshift = ((tm + tn) & 7) % nks;
+    bf::gbyte* ga = (bf::gbyte*)reinterpret_cast<const uint8_t*>(SA) + m0 * rowb;
+    bf::gbyte* gb = (bf::gbyte*)reinterpret_cast<const uint8_t*>(SB) + n0 * rowb;
+
+    // Coordinates (diagonal, pair, k-step) of the next step to fetch; steps
+    // run diagonal by diagonal from d = S-1, pairs s = 0..d, then k.  The
+    // coordinates stop at the last step: surplus fetches re-read it into a
+    // stage nobody reads again.
+    int fd = S - 1, fs = 0, fk = 0, fetched = 0;
+#define MOMMS_BF_FETCH(stage_)                                                                       \
+    do {                                                                                             \
+        int kq_ = fk + kshift;                                                                       \
+        if (kq_ >= nks) kq_ -= nks;                                                                  \
+        const int64_t kb_ = (int64_t)kq_ * (kKS * 2);                                                \
+        bf::gbyte* pa_ = ga + (int64_t)fs * sa_stride * 2 + kb_;                                     \
+        bf::gbyte* pb_ = gb + (int64_t)(fd - fs) * sb_stride * 2 + kb_;                              \
+        uint8_t* dst_ = lds + (stage_) * bf::kStage;                                                 \
+        /* opaque per use: base + offset is not hoisted into a 64-bit register */                    \
+        asm volatile("" : "+v"(voffa), "+v"(voffb));                                                 \
+        _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                              \
+            bf::gbyte* pu_ = pa_ + u * grp;                                                          \
+            asm volatile("" : "+s"(pu_));   /* the row-group step stays in the scalar base */        \
+            __builtin_amdgcn_global_load_lds(pu_ + voffa, (bf::lvoid*)(dst_ + ldsta + u * 1024), 16, 0, 0); \
+        }                                                                                            \
+        _Pragma("unroll") for (int u = 0; u < 2; ++u) {                                              \
+            bf::gbyte* pu_ = pb_ + u * grp;                                                          \
+            asm volatile("" : "+s"(pu_));                                                            \
+            __builtin_amdgcn_global_load_lds(pu_ + voffb, (bf::lvoid*)(dst_ + ldstb + u * 1024), 16, 0, 0); \
+        }                                                                                            \
+        /* advance (branch-free scalar selects; stops at the last step) */                           \
+        const int adv_ = fetched < last ? 1 : 0;                                                     \
+        fetched += adv_;                                                                             \
+        fk += adv_;                                                                                  \
+        const int wk_ = fk == nks ? 1 : 0;                                                           \
+        fk = wk_ ? 0 : fk;                                                                           \
+        fs += wk_;                                                                                   \
+        const int ws_ = fs > fd ? 1 : 0;                                                             \
+        fs = ws_ ? 0 : fs;                                                                           \
+        fd -= ws_;                                                                                   \
+    } while (0)
+
+    f4 acc[4][4];
+    double q[4][4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < 4; ++j) {
             acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) q[i][j][r] = 0.0;
         }
 
-    // Staging: each thread moves 2 x 16 bytes of A and of B per k-slice
-    // (chunk c = tid + 512 i covers row c / 8, bytes 16 (c % 8) of the row).
-    // Loads run kDepth k-slices ahead through a register FIFO: slice t lives
-    // in stage t % kDepth from its load until it is stored to LDS buffer t & 1.
-    constexpr int kDepth = 3;
-    uint4 st0_0, st0_1, st0_2, st0_3, st1_0, st1_1, st1_2, st1_3, st2_0, st2_1, st2_2, st2_3;
-    const int nks = (int)(kp / kKS);
-    const int total = (d + 1) * nks;
-    const int row0 = tid >> 3, row1 = (tid + 512) >> 3, chb = (tid & 7) * 8;
-    // Tiles sharing a slice panel start their k loops apart (as in the FP64
-    // kernel): slice t of pair s reads k-slice (t + kshift) mod nks.
-    const int kshift = ((tm + tn) & 7) % nks;
-
-#define MOMMS_SPLIT_GLOAD(t_, stage_)                                                             \
-    do {                                                                                          \
-        const int s_ = (t_) / nks;                                                                \
-        int kq_ = (t_) - s_ * nks + kshift;                                                       \
-        if (kq_ >= nks) kq_ -= nks;                                                               \
-        const int64_t kk_ = (int64_t)kq_ * kKS;                                                   \
-        const uint16_t* pa_ = SA + (int64_t)s_ * sa_stride + m0 * kp + kk_ + chb;                 \
-        const uint16_t* pb_ = SB + (int64_t)(d - s_) * sb_stride + n0 * kp + kk_ + chb;           \
-        st##stage_##_0 = *reinterpret_cast<const uint4*>(pa_ + (int64_t)row0 * kp);               \
-        st##stage_##_1 = *reinterpret_cast<const uint4*>(pa_ + (int64_t)row1 * kp);               \
-        st##stage_##_2 = *reinterpret_cast<const uint4*>(pb_ + (int64_t)row0 * kp);               \
-        st##stage_##_3 = *reinterpret_cast<const uint4*>(pb_ + (int64_t)row1 * kp);               \
+    // Row u of accumulator blocks (acc[u][*]) is added into the exact FP64
+    // sums q on step u of every group of four: four steps (256 products,
+    // sums <= 2^24) between two folds of any accumulator, and every diagonal
+    // ends on a group boundary with all rows folded.  One row per step keeps
+    // the conversions and FP64 adds spread out, next to the MFMAs of the
+    // other rows.
+#define MOMMS_BF_FOLD(u_)                                                                            \
+    do {                                                                                             \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                              \
+            _Pragma("unroll") for (int r = 0; r < 4; ++r) q[u_][j][r] += (double)acc[u_][j][r];      \
+            acc[u_][j] = f4{0.f, 0.f, 0.f, 0.f};                                                     \
+        }                                                                                            \
     } while (0)
-#define MOMMS_SPLIT_LSTORE(buf_, stage_)                                                          \
-    do {                                                                                          \
-        *reinterpret_cast<uint4*>(&As[buf_][row0 * kLdsPitch + chb]) = st##stage_##_0;            \
-        *reinterpret_cast<uint4*>(&As[buf_][row1 * kLdsPitch + chb]) = st##stage_##_1;            \
-        *reinterpret_cast<uint4*>(&Bs[buf_][row0 * kLdsPitch + chb]) = st##stage_##_2;            \
-        *reinterpret_cast<uint4*>(&Bs[buf_][row1 * kLdsPitch + chb]) = st##stage_##_3;            \
+    // One 32-deep window: four B and four A fragments, rows ia_, ia_ + 1
+    // of blocks first, then MID_ (a fold or nothing), then rows ib_, ib_ + 1.
+#define MOMMS_BF_LOADB(w_)                                                                           \
+    _Pragma("unroll") for (int j = 0; j < 4; ++j)                                                    \
+        b[j] = *reinterpret_cast<const bf16x8*>(base + (w_) * bf::kWinB + fb0 + j * 1024)
+    // A step that folds row u_: in the second window the pair holding row
+    // u_ goes first, so its fold overlaps the other pair's MFMAs.
+#define MOMMS_BF_WIN(w_, ia_, ib_, MID_)                                                             \
+    do {                                                                                             \
+        bf16x8 a[4];                                                                                 \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                                \
+            a[i] = *reinterpret_cast<const bf16x8*>(base + (w_) * bf::kWinA + fa0 + i * 1024);       \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j)                                                \
+            acc[ia_][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ia_], b[j], acc[ia_][j], 0, 0, 0); \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j)                                                \
+            acc[ia_ + 1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ia_ + 1], b[j], acc[ia_ + 1][j], 0, 0, 0); \
+        MID_;                                                                                        \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j)                                                \
+            acc[ib_][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ib_], b[j], acc[ib_][j], 0, 0, 0); \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j)                                                \
+            acc[ib_ + 1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ib_ + 1], b[j], acc[ib_ + 1][j], 0, 0, 0); \
     } while (0)
-
-    // One k-slice step: slice t is in LDS buffer t & 1 and stage (t % kDepth)
-    // is free again; refill it with slice t + kDepth, compute slice t, then
-    // move slice t + 1 from its stage into the other LDS buffer.
-#define MOMMS_SPLIT_STEP(t_, stage_, next_)                                                       \
-    do {                                                                                          \
-        const int tt_ = (t_);                                                                     \
-        if (tt_ + kDepth < total) MOMMS_SPLIT_GLOAD(tt_ + kDepth, stage_);                        \
-        const int cur_ = tt_ & 1;                                                                 \
-        _Pragma("unroll") for (int ks = 0; ks < kKS / 32; ++ks) {                                 \
-            bf16x8 a[4], b[2];                                                                    \
-            _Pragma("unroll") for (int i = 0; i < 4; ++i)                                         \
-                a[i] = *reinterpret_cast<const bf16x8*>(                                          \
-                    &As[cur_][(wm * 64 + i * 16 + li) * kLdsPitch + ks * 32 + 8 * lk]);           \
-            _Pragma("unroll") for (int j = 0; j < 2; ++j)                                         \
-                b[j] = *reinterpret_cast<const bf16x8*>(                                          \
-                    &Bs[cur_][(wn * 32 + j * 16 + li) * kLdsPitch + ks * 32 + 8 * lk]);           \
-            _Pragma("unroll") for (int i = 0; i < 4; ++i)                                         \
-                _Pragma("unroll") for (int j = 0; j < 2; ++j)                                     \
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0); \
-        }                                                                                         \
-        if (tt_ + 1 < total) MOMMS_SPLIT_LSTORE(cur_ ^ 1, next_);                                 \
-        /* 4 k-slices = 256 products per accumulator: fold the exact FP32    */                   \
-        /* integers into FP64 before they could reach 2^24.                  */                   \
-        if ((tt_ & 3) == 3 || tt_ + 1 == total) {                                                 \
-            _Pragma("unroll") for (int i = 0; i < 4; ++i)                                         \
-                _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                   \
-                    _Pragma("unroll") for (int r = 0; r < 4; ++r) q[i][j][r] += (double)acc[i][j][r]; \
-                    acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};                                           \
-                }                                                                                 \
-        }                                                                                         \
-        __syncthreads();                                                                          \
+#define MOMMS_BF_STEP(u_)                                                                            \
+    do {                                                                                             \
+        constexpr int pf_ = ((u_) / 2) * 2, po_ = 2 - pf_;                                           \
+        bf16x8 b[4];                                                                                 \
+        MOMMS_BF_LOADB(0);                                                                           \
+        MOMMS_BF_WIN(0, 0, 2, (void)0);                                                              \
+        MOMMS_BF_LOADB(1);                                                                           \
+        MOMMS_BF_WIN(1, pf_, po_, MOMMS_BF_FOLD(u_));                                                \
     } while (0)
 
-    // prologue: slice 0 into LDS buffer 0, slices 1 and 2 in flight; step t
-    // starts with stage t % kDepth free and loads slice t + kDepth into it.
-    MOMMS_SPLIT_GLOAD(0, 0);
-    MOMMS_SPLIT_LSTORE(0, 0);
-    if (1 < total) MOMMS_SPLIT_GLOAD(1, 1);
-    if (2 < total) MOMMS_SPLIT_GLOAD(2, 2);
-    __syncthreads();
-    // The loop runs in steps of kDepth so every stage index is a constant.
-    static_assert(kDepth == 3, "the step unrolling below assumes three stages");
-    for (int t = 0; t < total; t += kDepth) {
-        MOMMS_SPLIT_STEP(t, 0, 1);
-        if (t + 1 < total) MOMMS_SPLIT_STEP(t + 1, 1, 2);
-        if (t + 2 < total) MOMMS_SPLIT_STEP(t + 2, 2, 0);
-    }
-#undef MOMMS_SPLIT_STEP
-#undef MOMMS_SPLIT_GLOAD
-#undef MOMMS_SPLIT_LSTORE
-    // s4: lane (li, lk) holds rows 4 lk + r, column li of each 16 x 16 block.
+    MOMMS_BF_FETCH(0);
+    MOMMS_BF_FETCH(1);
+    // Four steps at a time (every diagonal is a multiple of four steps:
+    // kp is a multiple of 256); step u of a group folds row u.
+    int stage = 0, fstage = 2;
+#define MOMMS_BF_ONE(u_)                                                                             \
+    do {                                                                                             \
+        /* this thread's fetches of this step have landed (the next step's  */                       \
+        /* six may still be in flight); after the barrier everyone's have,  */                       \
+        /* and everyone is done with the previous step's stage, which the   */                       \
+        /* fetch below overwrites.  A bare barrier: __syncthreads() would   */                       \
+        /* add a workgroup fence, and the fetches in flight count as LDS    */                       \
+        /* writes, so it would wait for all of them.                        */                       \
+        asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");                                 \
+        MOMMS_BF_FETCH(fstage);                                                                      \
+        const uint8_t* base = lds + stage * bf::kStage;                                              \
+        MOMMS_BF_STEP(u_);                                                                           \
+        /* steps are not interleaved: that would need more registers */                              \
+        __builtin_amdgcn_sched_barrier(0);                                                           \
+        stage = stage == 2 ? 0 : stage + 1;                                                          \
+        fstage = fstage == 2 ? 0 : fstage + 1;                                                       \
+    } while (0)
+    for (int cd = S - 1; cd >= 0; --cd) {
+        const int clen = (cd + 1) * nks;
+        for (int cj = 0; cj < clen; cj += 4) {
+            MOMMS_BF_ONE(0);
+            MOMMS_BF_ONE(1);
+            MOMMS_BF_ONE(2);
+            MOMMS_BF_ONE(3);
+        }
+        // end of the diagonal: the rows folded earlier in the last group
+        // into FP64 too (row 3 was folded on the last step)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 3; ++i) MOMMS_BF_FOLD(i);
+        // s4 for diagonal cd: lane (li, lk) holds rows 4 lk + r, column li
+        // of each 16 x 16 block.  Addresses are built here from a scalar base
+        // and a 32-bit lane offset, both opaque, so that the compiler cannot
+        // hoist 64 element addresses out of the main loop (they would not
+        // fit beside the accumulators).
+        {
+            const int shift = 2 * kB0 + cd * kB;
+            const bool first = cd == S - 1, lastd = cd == 0;
+            const int64_t rb = m0 + wm * 64, cbase = n0 + wn * 64;
+            const bool full = rb + 64 <= M && cbase + 64 <= N;
+            uint32_t lo_v = (uint32_t)(((int64_t)(4 * lk) * ldv + li) * 8);
+            uint32_t lo_c = (uint32_t)(((int64_t)(4 * lk) * ldc + li) * 8);
+            bf::gbyte* vb = (bf::gbyte*)reinterpret_cast<const uint8_t*>(V + rb * ldv + cbase);
+            bf::gbyte* cb = (bf::gbyte*)reinterpret_cast<const uint8_t*>(C + rb * ldc + cbase);
+            int64_t sv = ldv * 8, sc8 = ldc * 8;   // row strides in bytes
+            // rows and columns of C left from the wave's corner (at most 64
+            // matter), and this lane's first row and column in a block
+            int mrem = (int)(M - rb < 64 ? M - rb : 64), nrem = (int)(N - cbase < 64 ? N - cbase : 64);
+            int lrow = 4 * lk, lcol = li;
+            asm volatile("" : "+v"(lo_v), "+v"(lo_c), "+s"(vb), "+s"(cb), "+s"(sv), "+s"(sc8), "+s"(mrem),
+                         "+s"(nrem), "+v"(lrow), "+v"(lcol));
+            // one 16 x 16 block at a time, so that the V and C loads in
+            // flight need no more registers than the accumulators leave free
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = m0 + wm * 64 + i * 16 + 4 * lk + r;
-                const int64_t col = n0 + wn * 32 + j * 16 + li;
-                if (row >= M || col >= N) continue;
-                const double term = ldexp(q[i][j][r], -shift);
-                const double v = FIRST ? term : __dadd_rn(V[row * ldv + col], term);
-                if (LAST) {
-                    const double T = ldexp(v, exp_or_zero(ea[row]) + exp_or_zero(eb[col]));
-                    double o = __dmul_rn(alpha, T);
-                    if (beta != 0.0) o = __dadd_rn(o, __dmul_rn(beta, C[row * ldc + col]));
-                    C[row * ldc + col] = o;
-                } else {
-                    V[row * ldv + col] = v;
+                for (int j = 0; j < 4; ++j) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int64_t col = cbase + j * 16 + li;
+                    const bool col_ok = j * 16 + lcol < nrem;
+                    const int fcol = lastd && col_ok ? exp_or_zero(eb[col]) : 0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double term = ldexp(q[i][j][r], -shift);
+                        q[i][j][r] = 0.0;
+                        const int64_t row = rb + i * 16 + 4 * lk + r;
+                        __attribute__((address_space(1))) double* pv =
+                            (__attribute__((address_space(1))) double*)(vb + (i * 16 + r) * sv + j * 128 + lo_v);
+                        __attribute__((address_space(1))) double* pc =
+                            (__attribute__((address_space(1))) double*)(cb + (i * 16 + r) * sc8 + j * 128 + lo_c);
+                        if (!full && (i * 16 + r + lrow >= mrem || !col_ok)) continue;
+                        const double v = first ? term : __dadd_rn(*pv, term);
+                        if (lastd) {
+                            const double T = ldexp(v, exp_or_zero(ea[row]) + fcol);
+                            double o = __dmul_rn(alpha, T);
+                            if (beta != 0.0) o = __dadd_rn(o, __dmul_rn(beta, *pc));
+                            *pc = o;
+                        } else {
+                            *pv = v;
+                        }
+                    }
                 }
-            }
+        }
+    }
+#undef MOMMS_BF_ONE
+    // the surplus fetches must land before the workgroup's LDS is released
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#undef MOMMS_BF_FETCH
+#undef MOMMS_BF_FOLD
+#undef MOMMS_BF_WIN
+#undef MOMMS_BF_LOADB
+#undef MOMMS_BF_STEP
 }
 
 // INT8 form of one diagonal: Q = sum_{s=0..d} D^A_s D^B_{d-s} with
@@ -891,8 +1023,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static Layout layout(int64_t m, int64_t n, int64_t k, int S, bool bytes, bool crt = false) {
     Layout L;
     const size_t esz = bytes ? sizeof(int8_t) : sizeof(uint16_t);
-    L.mp = rup(m > 0 ? m : 1, bytes ? kI8MT : kMT);
-    L.np = rup(n > 0 ? n : 1, bytes ? kI8NT : kMT);
+    L.mp = rup(m > 0 ? m : 1, bytes ? kI8MT : bf::kMT);
+    L.np = rup(n > 0 ? n : 1, bytes ? kI8NT : bf::kNT);
     L.kp = rup(k > 0 ? k : 1, bytes ? kI8KS : kKPad);
     size_t o = 0;
     L.off_ea = o; o = align256(o + sizeof(int) * (size_t)m);
@@ -964,14 +1096,6 @@ static void launch_i8_diag(dim3 grid, hipStream_t st, int64_t M, int64_t N, int6
                            double* V, int64_t ldv, double alpha, double beta, double* C, int64_t ldc, Sched s) {
     hipLaunchKernelGGL((k_split_i8_diag<F, L, F8>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs, shift, ea,
                        eb, V, ldv, alpha, beta, C, ldc, s);
-}
-
-template <bool F, bool L>
-static void launch_diag(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t kp, int d, const uint16_t* SA,
-                        const uint16_t* SB, int64_t sas, int64_t sbs, int shift, const int* ea, const int* eb,
-                        double* V, int64_t ldv, double alpha, double beta, double* C, int64_t ldc, Sched s) {
-    hipLaunchKernelGGL((k_split_diag<F, L>), grid, dim3(512), 0, st, M, N, kp, d, SA, SB, sas, sbs, shift, ea, eb, V,
-                       ldv, alpha, beta, C, ldc, s);
 }
 
 }  // namespace split
@@ -1105,7 +1229,7 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
 #undef MOMMS_SLICE_LAUNCH
     }
     // s3 + s4: one launch per diagonal, smallest first.
-    const int tile_m = bytes ? kI8MT : kMT, tile_n = bytes ? kI8NT : kMT;
+    const int tile_m = bytes ? kI8MT : bf::kMT, tile_n = bytes ? kI8NT : bf::kNT;
     Sched s;
     s.m_off = 0;
     s.n_off = 0;
@@ -1114,7 +1238,7 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
     s.tiles_m = (int)cdiv(m, tile_m);
     s.tiles_n = (int)cdiv(n, tile_n);
     const bool grouped = family_member != MOMMS_C0;
-    const int gm = bytes ? 4 : 8;  // tiles per group along m in the grouped order
+    const int gm = 4;  // tiles per group along m in the grouped order
     s.group_m = grouped ? (s.tiles_m < gm ? s.tiles_m : gm) : 1;
     s.xcd = grouped ? kXcds : 1;
     const dim3 grid((unsigned)(s.tiles_m * s.tiles_n));
@@ -1149,9 +1273,10 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
         const hipError_t e = hipGetLastError();
         return e == hipSuccess ? 0 : (int)e;
     }
-    for (int d = slices - 1; d >= 0; --d) {
-        const bool first = d == slices - 1, last = d == 0;
-        if (bytes) {
+    if (bytes) {
+        // s3 + s4, byte slices: one launch per diagonal, smallest first
+        for (int d = slices - 1; d >= 0; --d) {
+            const bool first = d == slices - 1, last = d == 0;
             const int shift = f8 ? 2 * kF8B0 + d * kF8B : 2 * kI8Bits + d * kI8Bits;
             const int8_t* a8 = static_cast<const int8_t*>(SA);
             const int8_t* b8 = static_cast<const int8_t*>(SB);
@@ -1161,23 +1286,12 @@ int momms_gemm_split(int transA, int transB, int64_t m, int64_t n, int64_t k, do
             else    launch = first ? (last ? launch_i8_diag<true, true, false> : launch_i8_diag<true, false, false>)
                                    : (last ? launch_i8_diag<false, true, false> : launch_i8_diag<false, false, false>);
             launch(grid, st, m, n, L.kp, d, a8, b8, sas, sbs, shift, ea, eb, V, n, alpha, beta, C, ldc, s);
-            continue;
         }
-        const int shift = 2 * kB0 + d * kB;
-        const uint16_t* a16 = static_cast<const uint16_t*>(SA);
-        const uint16_t* b16 = static_cast<const uint16_t*>(SB);
-        if (first && last)
-            launch_diag<true, true>(grid, st, m, n, L.kp, d, a16, b16, sas, sbs, shift, ea, eb, V, n, alpha, beta, C,
-                                    ldc, s);
-        else if (first)
-            launch_diag<true, false>(grid, st, m, n, L.kp, d, a16, b16, sas, sbs, shift, ea, eb, V, n, alpha, beta,
-                                     C, ldc, s);
-        else if (last)
-            launch_diag<false, true>(grid, st, m, n, L.kp, d, a16, b16, sas, sbs, shift, ea, eb, V, n, alpha, beta,
-                                     C, ldc, s);
-        else
-            launch_diag<false, false>(grid, st, m, n, L.kp, d, a16, b16, sas, sbs, shift, ea, eb, V, n, alpha, beta,
-                                      C, ldc, s);
+    } else {
+        // s3 + s4, BF16: every diagonal in one launch
+        hipLaunchKernelGGL(k_split_bf16, grid, dim3(512), 0, st, m, n, L.kp, slices,
+                           static_cast<const uint16_t*>(SA), static_cast<const uint16_t*>(SB), sas, sbs, ea, eb, V,
+                           n, alpha, beta, C, ldc, s);
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : (int)e;

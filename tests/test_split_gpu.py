@@ -35,7 +35,7 @@ def test_bit_exact_against_emulation(S, kind):
     np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, S), want)
 
 
-@pytest.mark.parametrize("shape", [(300, 280, 260), (1, 1, 1), (129, 7, 65), (17, 200, 3)])
+@pytest.mark.parametrize("shape", [(300, 280, 260), (1, 1, 1), (129, 7, 65), (17, 200, 3), (520, 390, 700)])
 @pytest.mark.parametrize("member", ["AUTO", "C0"])
 def test_ragged_shapes_bit_exact(shape, member):
     m, n, k = shape
@@ -104,8 +104,8 @@ def test_config3_sampled_8192():
     A, B, _ = workloads.gemm_operands(m, n, k, kind="loguniform", with_c=False)
     got = run(A, B, None, 1.0, 0.0, 7)
     rng = np.random.Generator(np.random.PCG64(3))
-    rows = np.concatenate([rng.integers(0, m, 300), [0, m - 1, 127, 128]])
-    cols = np.concatenate([rng.integers(0, n, 300), [n - 1, 0, 128, 127]])
+    rows = np.concatenate([rng.integers(0, m, 300), [0, m - 1, 127, 128, 255, 256]])
+    cols = np.concatenate([rng.integers(0, n, 300), [n - 1, 0, 128, 127, 63, 64]])
     emu = se.split_gemm_entries(A, B, rows, cols, 7, "bf16")
     np.testing.assert_array_equal(got[rows, cols], emu)
     exact = oracle.gemm_entries(A, B, rows, cols)
