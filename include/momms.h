@@ -220,6 +220,18 @@ int momms_model_resident(int resident, int64_t m, int64_t n, int64_t k, int64_t 
  * element costs beta_b and a C element beta_c (Sec. 2.4):
  * mc = sqrt(beta_b/beta_c M), kc = sqrt(beta_c/beta_b M).  Host-only. */
 int momms_balanced_block(double M, double beta_b, double beta_c, double *mc, double *kc);
+/* The planner's level-2 (LDS) block solver (Sec. 2.4 balance within the
+ * Sec. 4.1 capacity): for a fast memory of lds_bytes holding the resident
+ * block (row pitch kc + 1 doubles) plus two streamed k-slices of
+ * slice x (tile_other + 2) doubles, the block (rows a multiple of 64, kc a
+ * multiple of 64) with the most flops per unit of streamed cost, the streamed
+ * panel costing beta_stream and C beta_c per element; ties go to the block
+ * nearer the continuous optimum (momms_balanced_block), then to fewer rows.
+ * The LDS-resident kernels are built for its answer on gfx950.  Returns 0,
+ * or -i for a bad argument i (rows and kc are 0 when nothing fits).
+ * Host-only. */
+int momms_lds_block(double lds_bytes, int slice, int tile_other, double beta_stream, double beta_c, int *rows,
+                    int *kc);
 
 /* ---------------------------------------------------------------------
  * Split-precision FP64-accurate product (Ozaki-style error-free splitting;

@@ -436,6 +436,15 @@ def balanced_block(M, beta_b, beta_c):
     return mc.value, kc.value
 
 
+def lds_block(lds_bytes, slice_depth, tile_other, beta_stream, beta_c):
+    """The planner's level-2 block solver: (rows, kc) of the resident block."""
+    import ctypes
+    rows, kc = ctypes.c_int(), ctypes.c_int()
+    check_status(_lib.momms_lds_block(float(lds_bytes), int(slice_depth), int(tile_other), float(beta_stream),
+                                      float(beta_c), ctypes.byref(rows), ctypes.byref(kc)), "momms_lds_block")
+    return rows.value, kc.value
+
+
 class BandwidthHog:
     """The streaming kernel of the low-bandwidth experiments (Sec. 5), on a stream of its own.
 

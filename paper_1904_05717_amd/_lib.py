@@ -82,6 +82,7 @@ momms_batch_set_rates = _fn("momms_batch_set_rates", i32, [dbl, dbl, dbl])
 
 momms_model_resident = _fn("momms_model_resident", i32, [i32, i64, i64, i64, i64, i64, dbl, _pdbl])
 momms_balanced_block = _fn("momms_balanced_block", i32, [dbl, dbl, dbl, _pdbl, _pdbl])
+momms_lds_block = _fn("momms_lds_block", i32, [dbl, i32, i32, dbl, dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)])
 
 momms_set_member_table = _fn("momms_set_member_table", i32, [i32, _pi32, _pi32, _pi32, _pi32])
 momms_select_member_prior = _fn("momms_select_member_prior", i32, [i64, i64, i64])
@@ -115,7 +116,7 @@ EXPORTS = [
     "momms_tiled_size", "momms_to_tiled", "momms_from_tiled", "momms_gemm_tiled", "momms_syrk", "momms_crt_bits",
     "momms_ooc_workspace_size", "momms_gemm_ooc", "momms_trmm", "momms_trsm", "momms_potrf",
     "momms_lowbw_min_bytes", "momms_lowbw_record_words", "momms_lowbw_round_bytes", "momms_lowbw_clock_hz",
-    "momms_lowbw_start", "momms_lowbw_stop", "momms_lowbw_stamp",
+    "momms_lowbw_start", "momms_lowbw_stop", "momms_lowbw_stamp", "momms_lds_block", "momms_gemm_static",
 ]
 
 

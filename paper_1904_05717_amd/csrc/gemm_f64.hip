@@ -32,7 +32,12 @@ __global__ __launch_bounds__(256) void k_scale_c(int64_t M, int64_t N, double be
 
 using CfgL = TileCfg<128, 128, 16, 2, 2>;  // register-resident C, large problems
 using CfgS = TileCfg<64, 64, 16, 2, 2>;    // register-resident C, small problems
-using CfgK = TileCfg<128, 128, 8, 4, 4>;   // LDS-resident A or B block: sixteen waves, four per SIMD
+// LDS-resident blocks: eight waves of 32 x 32, two per SIMD, 32-deep streamed
+// slices.  A block kMCa x kKC (C tiles kMCa x kNTa); B block kKC x kNCb (C
+// tiles kMTb x kNCb).
+using CfgA = TileCfg<kMCa, kNTa, kKSlds, kMCa / 32, kNTa / 32>;
+using CfgB = TileCfg<kMTb, kNCb, kKSlds, kMTb / 32, kNCb / 32>;
+static_assert(CfgA::THREADS == 512 && CfgB::THREADS == 512, "eight waves per LDS-resident workgroup");
 
 static hipStream_t g_stream = nullptr;
 
@@ -88,7 +93,7 @@ static void launch_regc(const Args& a, int64_t k0, int64_t k1, double beta, cons
 template <bool TA, bool TB, bool PK>
 static void launch_a2_t(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, const double* Bsrc,
                         int64_t ldb, int64_t pk0, int64_t pn0) {
-    hipLaunchKernelGGL((k_a2<CfgK, kKC, TA, TB, PK>), dim3(grid_of(s)), dim3(CfgK::THREADS), 0, a.st, a.M, a.N, k0,
+    hipLaunchKernelGGL((k_a2<CfgA, kKC, TA, TB, PK>), dim3(grid_of(s)), dim3(CfgA::THREADS), 0, a.st, a.M, a.N, k0,
                        k1, a.alpha, a.A, a.lda, Bsrc, ldb, a.beta, a.C, a.ldc, s, nj, pk0, pn0);
 }
 
@@ -109,7 +114,7 @@ static void launch_a2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int
 
 template <bool TA, bool TB>
 static void launch_b2_t(const Args& a, int64_t k0, int64_t k1, const Sched& s, int mi) {
-    hipLaunchKernelGGL((k_b2<CfgK, kKC, TA, TB>), dim3(grid_of(s)), dim3(CfgK::THREADS), 0, a.st, a.M, a.N, k0, k1,
+    hipLaunchKernelGGL((k_b2<CfgB, kKC, TA, TB>), dim3(grid_of(s)), dim3(CfgB::THREADS), 0, a.st, a.M, a.N, k0, k1,
                        a.alpha, a.A, a.lda, a.B, a.ldb, a.beta, a.C, a.ldc, s, mi);
 }
 
@@ -122,15 +127,15 @@ static void launch_b2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int
 }
 
 static void launch_pack_b(const Args& a, int64_t pk0, int64_t pn0, int64_t ncw, double* P) {
-    const int ntiles = (int)cdiv(ncw, CfgK::NT);
-    const int64_t total = (int64_t)ntiles * kKC * CfgK::NT;
+    const int ntiles = (int)cdiv(ncw, CfgA::NT);
+    const int64_t total = (int64_t)ntiles * kKC * CfgA::NT;
     int grid = (int)cdiv(total, 256);
     if (grid > 4 * kCUs * 8) grid = 4 * kCUs * 8;
     if (a.tb)
-        hipLaunchKernelGGL((k_pack_b<CfgK::NT, true>), dim3(grid), dim3(256), 0, a.st, a.B, a.ldb, a.K, a.N, pk0, pn0,
+        hipLaunchKernelGGL((k_pack_b<CfgA::NT, true>), dim3(grid), dim3(256), 0, a.st, a.B, a.ldb, a.K, a.N, pk0, pn0,
                            (int)kKC, ntiles, P);
     else
-        hipLaunchKernelGGL((k_pack_b<CfgK::NT, false>), dim3(grid), dim3(256), 0, a.st, a.B, a.ldb, a.K, a.N, pk0,
+        hipLaunchKernelGGL((k_pack_b<CfgA::NT, false>), dim3(grid), dim3(256), 0, a.st, a.B, a.ldb, a.K, a.N, pk0,
                            pn0, (int)kKC, ntiles, P);
 }
 
@@ -263,12 +268,13 @@ static int check_args(int transA, int transB, int64_t m, int64_t n, int64_t k, d
 }
 
 // Scratch of the allocation-free entry point: Goto's packed B panel (k_c rows
-// of at most n_c = 4096 columns, the largest workspace any member asks for)
+// of at most n_c columns, the largest workspace any member asks for)
 // in a static device array.  Each GPU holds its own copy for the life of the
 // process.  In host code `scratch` names a host-side stand-in, never the
 // device memory: its device address is taken once per device with that device
 // current, and only that address is passed to kernels.
-constexpr size_t kStaticScratchBytes = (size_t)kKC * 4096 * sizeof(double);   // 4 MiB
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;   // 4 MiB
+static_assert((size_t)kKC * kGotoNc * sizeof(double) <= kStaticScratchBytes, "Goto's panel fits the scratch");
 static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
 constexpr int kMaxDevices = 64;
 static std::mutex g_scratch_mu;

@@ -62,6 +62,20 @@ struct Stage {
             L[r * lld + s] = v[i];
         }
     }
+    // X(r, s) from tile-major slabs of 16 columns (row pitch 16, consecutive
+    // slabs slab_stride apart): X(r, s) = P[(s / 16) * slab_stride + r * 16 +
+    // s % 16] for s < slim (the columns the storage holds; zero-padded up to
+    // there), zero beyond.
+    __device__ __forceinline__ void load_slabs(const double* __restrict__ P, int64_t slab_stride, int64_t slim,
+                                               int tid) {
+        static_assert(!TRANS, "slabs hold rows of 16 consecutive columns");
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            int r, s;
+            coord(tid + i * THREADS, r, s);
+            v[i] = s < slim ? P[(int64_t)(s / 16) * slab_stride + r * 16 + s % 16] : 0.0;
+        }
+    }
 };
 
 // Unchecked staging for tiles that lie wholly inside the operand.  Thread tid
@@ -163,6 +177,41 @@ __device__ __forceinline__ void mma_lds(const double* __restrict__ As, int a_ld,
     }
 }
 
+// The same micro-kernel with the fragments of step kk + 1 read from LDS
+// before the MFMAs of step kk are issued (two fragment register sets), so a
+// wave waits for LDS once per slice rather than once per 4-deep step.  For
+// small wave tiles, whose four MFMAs per step do not cover an LDS read.
+template <class CF, int KSTEPS>
+__device__ __forceinline__ void mma_lds_pipe(const double* __restrict__ As, int a_ld, int a_k0,
+                                             const double* __restrict__ Bs, int b_ld, int b_k0,
+                                             d4 (&acc)[CF::BM][CF::BN], int wm, int wn, int lane) {
+    const int li = lane & 15, lk = lane >> 4;
+    const double* ap = As + (wm * CF::WTM + li) * a_ld + a_k0 + lk;
+    const double* bp = Bs + (b_k0 + lk) * b_ld + wn * CF::WTN + li;
+    double a[2][CF::BM], b[2][CF::BN];
+#pragma unroll
+    for (int i = 0; i < CF::BM; ++i) a[0][i] = ap[i * 16 * a_ld];
+#pragma unroll
+    for (int j = 0; j < CF::BN; ++j) b[0][j] = bp[j * 16];
+#pragma unroll
+    for (int kk = 0; kk < KSTEPS; ++kk) {
+        const int cur = kk & 1;
+        if (kk + 1 < KSTEPS) {
+#pragma unroll
+            for (int i = 0; i < CF::BM; ++i) a[cur ^ 1][i] = ap[i * 16 * a_ld + (kk + 1) * 4];
+#pragma unroll
+            for (int j = 0; j < CF::BN; ++j) b[cur ^ 1][j] = bp[(kk + 1) * 4 * b_ld + j * 16];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the next step's reads ahead of these MFMAs
+#pragma unroll
+        for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::BN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][i], b[cur][j], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 template <class CF>
 __device__ __forceinline__ void zero_acc(d4 (&acc)[CF::BM][CF::BN]) {
 #pragma unroll
@@ -218,6 +267,44 @@ __device__ __forceinline__ void store_c_tri(const d4 (&acc)[CF::BM][CF::BN], dou
                     C[row * ldc + col] = epilogue_value(alpha, acc[i][j][r], beta, beta != 0.0 ? cv[j][r] : 0.0);
             }
     }
+}
+
+// The C values the epilogue of the tile at (m0, n0) reads, loaded ahead of
+// it so that their latency overlaps MFMAs (an entry outside C reads C[0] and
+// is discarded).
+template <class CF>
+__device__ __forceinline__ void load_c(double (&cv)[CF::BM][CF::BN][4], const double* __restrict__ C, int64_t ldc,
+                                       int64_t m0, int64_t n0, int64_t M, int64_t N, int wm, int wn, int lane) {
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::BN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm * CF::WTM + i * 16 + lk + 4 * r;
+                const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
+                cv[i][j][r] = C[(row < M && col < N) ? row * ldc + col : 0];
+            }
+}
+
+// Epilogue with C already loaded (load_c): C = alpha * acc + beta * cv.
+template <class CF>
+__device__ __forceinline__ void store_c_loaded(const d4 (&acc)[CF::BM][CF::BN], double alpha, double beta,
+                                               const double (&cv)[CF::BM][CF::BN][4], double* __restrict__ C,
+                                               int64_t ldc, int64_t m0, int64_t n0, int64_t M, int64_t N, int wm,
+                                               int wn, int lane) {
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::BN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + wm * CF::WTM + i * 16 + lk + 4 * r;
+                const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
+                if (row < M && col < N) C[row * ldc + col] = epilogue_value(alpha, acc[i][j][r], beta, cv[i][j][r]);
+            }
 }
 
 template <class CF>
@@ -338,6 +425,12 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha, 
     regc_tile<CF, TA, TB>(M, N, k_begin, k_end, alpha, A, lda, B, ldb, beta, C, ldc, m0, n0, tm, tn, As, Bs);
 }
 
+// Slices ahead of an LDS-resident kernel's epilogue at which its C values are
+// loaded (a 32-deep slice is about 2 us of MFMAs), and the depth of the
+// register ring that streams the other operand's slices.
+constexpr int kPrefetchC = 1;
+constexpr int kRing = 2;
+
 // ---------------------------------------------------------------------------
 // k_a2: granule = MT rows x (nj * NT) columns.  For each KC chunk of
 // [k_begin, k_end) the A block (MT x KC) is loaded into LDS once and reused for
@@ -346,7 +439,8 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha, 
 // k = 0, later chunks accumulate.  With PACKED, B comes from a packed panel
 // laid out [n-tile][k][NT] (rows of NT doubles, zero-padded, ldb rows per
 // n-tile), whose origin is (pk0, pn0) in B's coordinates; n-tiles are
-// numbered from pn0.  With TILED, A is tile-major (128 x 16 slabs).
+// numbered from pn0.  With TILED, A is tile-major (128 x 16 slabs; MT divides
+// 128).
 template <class CF, int KC, bool TA, bool TB, bool PACKED, bool TILED = false>
 __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
                                                     double alpha, const double* __restrict__ A, int64_t lda,
@@ -354,6 +448,8 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
                                                     double* __restrict__ C, int64_t ldc, Sched s, int nj,
                                                     int64_t pk0, int64_t pn0) {
     static_assert(KC % CF::KS == 0, "KC must be a multiple of the slice depth");
+    static_assert(!TILED || (CF::KS % 16 == 0 && KC % 16 == 0 && 128 % CF::MT == 0),
+                  "tile-major slices start on slab boundaries and blocks sit inside 128-row panels");
     constexpr int AB_LD = KC + 1;
     __shared__ double As[CF::MT * AB_LD];
     __shared__ double Bs[2][CF::KS * CF::B_LD];
@@ -366,7 +462,7 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
     const int wm = wave / CF::WN, wn = wave % CF::WN;
     const int ntiles = (int)((nend - nbeg + CF::NT - 1) / CF::NT);
 
-    Stage<CF::KS, CF::NT, CF::THREADS, PACKED ? false : TB> sb0, sb1;
+    Stage<CF::KS, CF::NT, CF::THREADS, PACKED ? false : TB> sb[kRing];
     d4 acc[CF::BM][CF::BN];
 
     for (int64_t kb = k_begin; kb < k_end; kb += KC) {
@@ -382,12 +478,14 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
             for (int u = 0; u < 4; ++u) {
                 const int c = c0 + u;
                 if (c >= nsl) break;
-                if (TILED) {
+                if constexpr (TILED) {
                     // tile-major A: 128 x 16 slabs, lda = slabs per row panel,
-                    // zero beyond the matrix (m0 is a multiple of 128)
+                    // zero beyond the matrix (m0 is a multiple of MT, which
+                    // divides 128: the block is rows m0 % 128 .. of its
+                    // slabs; a slice starts on a slab boundary)
                     const int64_t kk = kb + (int64_t)c * CF::KS;
-                    const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + kk % 16;
-                    sq[u].load(P, 16, 0, 0, INT64_MAX, INT64_MAX, tid);
+                    const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + (m0 % 128) * 16;
+                    sq[u].load_slabs(P, 2048, lda * 16 - kk, tid);
                 } else {
                     sq[u].load(A, lda, m0, kb + c * CF::KS, M, kbe, tid);
                 }
@@ -404,42 +502,53 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
             if (PACKED) {
                 // panel row (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j);
                 // ldb is the panel height (KC for a per-chunk pack, the padded
-                // k for a tile-major B)
+                // k for a tile-major B); rows past it read as zero
                 const int64_t jt = (nbeg - pn0) / CF::NT + j;
                 const double* P = B + jt * ldb * CF::NT;
-                st.load(P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, INT64_MAX, CF::NT, tid);
+                st.load(P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, ldb, CF::NT, tid);
             } else {
                 st.load(B, ldb, kb + (int64_t)sl * CF::KS, nbeg + (int64_t)j * CF::NT, kbe, nend, tid);
             }
         };
-        // B slices two ahead: slice t+1 waits in one register set while
-        // slice t+2 loads into the other (the two sets alternate, so the loop
-        // runs two steps per iteration); the prefetch index is clamped to the
-        // last slice rather than skipped, which keeps the load where it is.
+        // B slices kRing ahead through a ring of register sets: slice t + u
+        // waits in set (t + u) % kRing (the loop runs kRing steps per
+        // iteration, so every set index is a constant); the prefetch index
+        // is clamped to the last slice rather than skipped, which keeps the
+        // load where it is.  A 32-deep slice is about 2 us of MFMAs.
         if (total > 0) {
-            load_b(sb0, 0);
-            sb0.store(Bs[0], CF::B_LD, tid);
-            load_b(sb1, total > 1 ? 1 : 0);
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) load_b(sb[u], u < total ? u : total - 1);
+            sb[0].store(Bs[0], CF::B_LD, tid);
         }
         __syncthreads();
         zero_acc<CF>(acc);
         const double beta_eff = (kb == 0) ? beta : 1.0;
+        // each n-tile's C values are loaded kPrefetchC slices before its
+        // epilogue (at its first slice if it has fewer)
+        const int pf_sl = nsl > kPrefetchC ? nsl - kPrefetchC : 0;
+        double cv[CF::BM][CF::BN][4];
+        // step t: slice t is in Bs[t & 1] and its register set is free again
+        // (stored in step t - 1); refill it with slice t + kRing, compute,
+        // then store slice t + 1 into the other buffer.
         auto step = [&](int t, auto& reload, auto& ready, double* cur, double* other) {
             const int j = t / nsl, sl = t - j * nsl;
-            load_b(reload, t + 2 < total ? t + 2 : total - 1);
+            const int64_t n0 = nbeg + (int64_t)j * CF::NT;
+            load_b(reload, t + kRing < total ? t + kRing : total - 1);
+            if (sl == pf_sl && beta_eff != 0.0) load_c<CF>(cv, C, ldc, m0, n0, M, nend, wm, wn, lane);
             __builtin_amdgcn_sched_barrier(0);
-            mma_lds<CF, CF::KS / 4>(As, AB_LD, sl * CF::KS, cur, CF::B_LD, 0, acc, wm, wn, lane);
+            mma_lds_pipe<CF, CF::KS / 4>(As, AB_LD, sl * CF::KS, cur, CF::B_LD, 0, acc, wm, wn, lane);
             if (t + 1 < total) ready.store(other, CF::B_LD, tid);
             if (sl == nsl - 1) {
-                store_c<CF>(acc, alpha, beta_eff, C, ldc, m0, nbeg + (int64_t)j * CF::NT, M, nend, wm, wn, lane);
+                store_c_loaded<CF>(acc, alpha, beta_eff, cv, C, ldc, m0, n0, M, nend, wm, wn, lane);
                 zero_acc<CF>(acc);
             }
             __syncthreads();
         };
+        static_assert(kRing == 2, "the unrolled steps below assume a ring of two");
 #pragma unroll 1
         for (int t = 0; t < total; t += 2) {
-            step(t, sb0, sb1, Bs[0], Bs[1]);
-            if (t + 1 < total) step(t + 1, sb1, sb0, Bs[1], Bs[0]);
+            step(t, sb[0], sb[1], Bs[0], Bs[1]);
+            if (t + 1 < total) step(t + 1, sb[1], sb[0], Bs[1], Bs[0]);
         }
     }
 }
@@ -449,13 +558,16 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
 // chunk the B block (KC x NT) is resident in LDS and reused for every m-tile;
 // A slices stream through two LDS buffers.  With TILED, A is tile-major
 // (128 x 16 slabs, lda = slabs per row panel) and B comes from tile-major
-// column panels (ldb = the padded k), both zero beyond the matrix.
+// 128-column panels (ldb = the padded k; NT divides 128), both zero beyond
+// the matrix.
 template <class CF, int KC, bool TA, bool TB, bool TILED = false>
 __global__ __launch_bounds__(CF::THREADS) void k_b2(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
                                                     double alpha, const double* __restrict__ A, int64_t lda,
                                                     const double* __restrict__ B, int64_t ldb, double beta,
                                                     double* __restrict__ C, int64_t ldc, Sched s, int mi) {
     static_assert(KC % CF::KS == 0, "KC must be a multiple of the slice depth");
+    static_assert(!TILED || (CF::KS % 16 == 0 && KC % 16 == 0 && 128 % CF::MT == 0 && 128 % CF::NT == 0),
+                  "tile-major slices start on slab boundaries and tiles sit inside 128-wide panels");
     __shared__ double Bs[KC * CF::B_LD];
     __shared__ double As[2][CF::MT * CF::A_LD];
     int tm, tn;
@@ -467,7 +579,7 @@ __global__ __launch_bounds__(CF::THREADS) void k_b2(int64_t M, int64_t N, int64_
     const int wm = wave / CF::WN, wn = wave % CF::WN;
     const int mtiles = (int)((mend - mbeg + CF::MT - 1) / CF::MT);
 
-    Stage<CF::MT, CF::KS, CF::THREADS, TA> sa;
+    Stage<CF::MT, CF::KS, CF::THREADS, TA> sa[kRing];
     Stage<CF::KS, CF::NT, CF::THREADS, TB> sb;
     d4 acc[CF::BM][CF::BN];
 
@@ -476,46 +588,57 @@ __global__ __launch_bounds__(CF::THREADS) void k_b2(int64_t M, int64_t N, int64_
         const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
         const int total = mtiles * nsl;
         __syncthreads();
-        auto load_a = [&](int i, int sl) {
+        // A slice t of this chunk (m-tile t / nsl, slice t % nsl) into st
+        auto load_a = [&](auto& st, int t) {
+            const int i = t / nsl, sl = t - (t / nsl) * nsl;
             const int64_t r0 = mbeg + (int64_t)i * CF::MT, kk = kb + (int64_t)sl * CF::KS;
-            if (TILED) {
-                const double* P = A + ((r0 / 128) * lda + kk / 16) * 2048 + kk % 16;
-                sa.load(P, 16, 0, 0, INT64_MAX, INT64_MAX, tid);
+            if constexpr (TILED) {
+                const double* P = A + ((r0 / 128) * lda + kk / 16) * 2048 + (r0 % 128) * 16;
+                st.load_slabs(P, 2048, lda * 16 - kk, tid);
             } else {
-                sa.load(A, lda, r0, kk, mend, kbe, tid);
+                st.load(A, lda, r0, kk, mend, kbe, tid);
             }
         };
 #pragma unroll 1
         for (int c = 0; c < nsl; ++c) {
-            if (TILED)
-                sb.load(B + (n0 / CF::NT) * ldb * CF::NT, CF::NT, kb + c * CF::KS, 0, INT64_MAX, CF::NT, tid);
+            if (TILED)   // 128-column panels of ldb rows, k-major; the block is columns n0 % 128 ..
+                sb.load(B + (n0 / 128) * ldb * 128 + n0 % 128, 128, kb + c * CF::KS, 0, ldb, CF::NT, tid);
             else
                 sb.load(B, ldb, kb + c * CF::KS, n0, kbe, N, tid);
             sb.store(Bs + c * CF::KS * CF::B_LD, CF::B_LD, tid);
         }
+        // A slices kRing ahead through a ring of register sets (as the B
+        // slices of k_a2)
         if (total > 0) {
-            load_a(0, 0);
-            sa.store(As[0], CF::A_LD, tid);
+#pragma unroll
+            for (int u = 0; u < kRing; ++u) load_a(sa[u], u < total ? u : total - 1);
+            sa[0].store(As[0], CF::A_LD, tid);
         }
         __syncthreads();
         zero_acc<CF>(acc);
         const double beta_eff = (kb == 0) ? beta : 1.0;
-#pragma unroll 1
-        for (int t = 0; t < total; ++t) {
+        const int pf_sl = nsl > kPrefetchC ? nsl - kPrefetchC : 0;
+        double cv[CF::BM][CF::BN][4];
+        auto step = [&](int t, auto& reload, auto& ready) {
             const int cur = t & 1;
             const int i = t / nsl, sl = t - i * nsl;
-            const bool more = t + 1 < total;
-            if (more) {
-                const int i2 = (t + 1) / nsl, sl2 = (t + 1) - ((t + 1) / nsl) * nsl;
-                load_a(i2, sl2);
-            }
-            mma_lds<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs, CF::B_LD, sl * CF::KS, acc, wm, wn, lane);
-            if (more) sa.store(As[cur ^ 1], CF::A_LD, tid);
+            const int64_t r0 = mbeg + (int64_t)i * CF::MT;
+            load_a(reload, t + kRing < total ? t + kRing : total - 1);
+            if (sl == pf_sl && beta_eff != 0.0) load_c<CF>(cv, C, ldc, r0, n0, mend, N, wm, wn, lane);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_lds_pipe<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs, CF::B_LD, sl * CF::KS, acc, wm, wn, lane);
+            if (t + 1 < total) ready.store(As[cur ^ 1], CF::A_LD, tid);
             if (sl == nsl - 1) {
-                store_c<CF>(acc, alpha, beta_eff, C, ldc, mbeg + (int64_t)i * CF::MT, n0, mend, N, wm, wn, lane);
+                store_c_loaded<CF>(acc, alpha, beta_eff, cv, C, ldc, r0, n0, mend, N, wm, wn, lane);
                 zero_acc<CF>(acc);
             }
             __syncthreads();
+        };
+        static_assert(kRing == 2, "the unrolled steps below assume a ring of two");
+#pragma unroll 1
+        for (int t = 0; t < total; t += 2) {
+            step(t, sa[0], sa[1]);
+            if (t + 1 < total) step(t + 1, sa[1], sa[0]);
         }
     }
 }

@@ -7,9 +7,11 @@
 //            by 4 waves (64 doubles per lane), i.e. sqrt(M0) ~ 128 - the same
 //            order as the paper's LDS-class block, because the register file
 //            (512 KiB/CU) is larger than the LDS (160 KiB/CU).
-//   level 2: LDS.  A resident block of 128 x 128 fp64 (128 KiB) leaves room
-//            for two 8 x 128 streamed slices (Sec. 4.1: resident block plus
-//            guest panel must fit).
+//   level 2: LDS.  The resident block is sized by lds_block(): the Sec. 2.4
+//            balance between the streamed panel (from the L2) and C (from
+//            HBM, read and written), within the Sec. 4.1 capacity (block plus
+//            two 32-deep streamed slices in 160 KiB), on the MFMA wave grid:
+//            a 64 x 160 A block (or 160 x 64 B block), 80 KiB.
 //   level 3: one XCD's 4 MiB L2.  A 512 x 512 resident block (2 MiB) leaves
 //            half the L2 for the guest and streamed panels (Sec. 4.1).
 //   level 4: the 256 MiB MALL.  A 4096 x 4096 C block (128 MiB) leaves half.
@@ -32,8 +34,74 @@ static inline int regc_tile(int64_t m, int64_t n) {
     return (cdiv(m, 128) * cdiv(n, 128) >= 2 * kCUs) ? 128 : 64;
 }
 
+// Level-2 (LDS) block of the LDS-resident kernels (Sec. 2.4 balance within
+// the Sec. 4.1 capacity).  A resident A block of rows x kc, streaming B
+// slices (cost beta_stream per element) and updating C (cost beta_c per
+// element, covering its read and its write), does 2 rows kc flops per column
+// of B for beta_stream kc + beta_c rows of cost; the continuous optimum at a
+// capacity of M elements is rows = sqrt(beta_stream / beta_c M), kc =
+// sqrt(beta_c / beta_stream M) (momms_balanced_block).  The kernels need rows
+// a multiple of 64 (two rows of 32-row waves) and kc a multiple of the slice
+// depth; the block plus two streamed k-slices of slice x (tile_other + 2)
+// must fit lds_doubles with the block's row pitch kc + 1.  The slice depth
+// is the kernels' choice (32: enough MFMAs between two barriers), made before
+// the block is sized.  Among those blocks the one
+// with the most flops per unit cost wins; ties go to the one nearer the
+// continuous optimum (in kc / rows), then to fewer rows.  The B-resident
+// kernel is the mirror (rows = block columns).
+void lds_block(double lds_doubles, int slice, int tile_other, double beta_stream, double beta_c, int* rows,
+               int* kc) {
+    const double stream = 2.0 * slice * (tile_other + 2);
+    const double M = lds_doubles - stream;
+    const double ratio_opt = beta_c / beta_stream;   // kc / rows at the optimum
+    int best_r = 0, best_k = 0;
+    double best_e = -1.0, best_d = 0.0;
+    for (int r = 64; r <= 512; r += 64) {
+        const int kmax = (int)std::floor(M / r) - 1;   // r (kc + 1) <= M
+        const int kcand = (kmax / slice) * slice;
+        if (kcand < slice) continue;
+        const double e = 2.0 * r * kcand / (beta_stream * kcand + beta_c * r);
+        const double d = std::fabs(std::log((double)kcand / r / ratio_opt));
+        if (e > best_e * (1.0 + 1e-12) || (e > best_e * (1.0 - 1e-12) && d < best_d - 1e-12)) {
+            best_e = e;
+            best_d = d;
+            best_r = r;
+            best_k = kcand;
+        }
+    }
+    *rows = best_r;
+    *kc = best_k;
+}
+
+// gfx950 costs for lds_block: an element of the streamed panel comes from the
+// L2 (64 B/clk per CU, 2.4 GHz: 39 TB/s over 256 CUs); an element of C is
+// read from and written to HBM (8 TB/s), so it costs 2 x 39 / 8 times more.
+constexpr double kLdsDoubles = 160.0 * 1024 / 8;
+constexpr double kBetaStream = 1.0, kBetaC = 2.0 * 39.3 / 8.0;
+
+// The LDS-resident kernels are compiled for the solver's answer on gfx950;
+// the plan refuses to run if the two ever disagree.
+static bool lds_blocks_match() {
+    static const bool ok = [] {
+        int ra = 0, ka = 0, rb = 0, kb = 0;
+        lds_block(kLdsDoubles, kKSlds, kNTa, kBetaStream, kBetaC, &ra, &ka);   // A block, B slices of kNTa
+        lds_block(kLdsDoubles, kKSlds, kMTb, kBetaStream, kBetaC, &rb, &kb);   // B block, A slices of kMTb
+        return ra == kMCa && ka == kKC && rb == kNCb && kb == kKC;
+    }();
+    return ok;
+}
+
+// Column tiles per workgroup (the inner loop over the resident block): the
+// largest of 4, 2, 1 that still gives two rounds of workgroups on the chip.
+static int tiles_per_wg(int64_t blocks, int64_t tiles_other) {
+    for (int j = 4; j > 1; j /= 2)
+        if (blocks * cdiv(tiles_other, j) >= 2 * kCUs) return j;
+    return 1;
+}
+
 int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
     std::memset(p, 0, sizeof(*p));
+    if (!lds_blocks_match()) return -1;
     p->member = member;
     p->ks = 16;
     p->xcd_aware = 0;
@@ -92,14 +160,15 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             break;
         }
         case MOMMS_A2C0: {
-            // Goto: n by nc -> k by kc (pack B panel) -> m by 128 (A block
+            // Goto: n by nc -> k by kc (pack B panel) -> m by 64 (A block
             // in LDS) -> n by 128 across workgroups (the parallel 2nd loop).
             p->kernel = 1;
-            p->mt = p->nt = 128;
-            p->ks = 8;
+            p->mt = kMCa;
+            p->nt = kNTa;
+            p->ks = kKSlds;
             p->kc = kKC;
-            p->nc = 4096;
-            p->nj = 4;
+            p->nc = kGotoNc;
+            p->nj = tiles_per_wg(cdiv(m, p->mt), cdiv(n < p->nc ? n : p->nc, p->nt));
             p->k_range = p->kc < k ? p->kc : k;
             p->pack = 1;
             const int64_t jcs = cdiv(n, p->nc), pcs = k > 0 ? cdiv(k, p->kc) : 1;
@@ -109,15 +178,17 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             break;
         }
         case MOMMS_B3A2C0: {
-            // n by nc3 -> k by kc3 (B block in one XCD's L2) -> m by 128 (A
-            // block in LDS) -> k by kc -> n by 128.
+            // n by nc3 -> k by kc3 (B block in one XCD's L2) -> m by 64 (A
+            // block in LDS) -> k by kc -> n by 128.  nc3 = nj tiles (at most
+            // 512: a 512 x 512 B block is half the L2).
             p->kernel = 1;
-            p->mt = p->nt = 128;
-            p->ks = 8;
+            p->mt = kMCa;
+            p->nt = kNTa;
+            p->ks = kKSlds;
             p->kc = kKC;
             p->kc3 = 512;
-            p->nc3 = 512;
-            p->nj = (int)(p->nc3 / p->nt);
+            p->nj = tiles_per_wg(cdiv(m, p->mt), cdiv(n, p->nt));
+            p->nc3 = (int64_t)p->nj * p->nt;
             p->xcd_aware = 1;
             p->group_m = (int)cdiv(m, p->mt);
             p->k_range = p->kc < k ? p->kc : k;
@@ -126,15 +197,17 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             break;
         }
         case MOMMS_A3B2C0: {
-            // m by mc3 -> k by kc3 (A block in one XCD's L2) -> n by 128 (B
-            // block in LDS) -> k by kc -> m by 128.
+            // m by mc3 -> k by kc3 (A block in one XCD's L2) -> n by 64 (B
+            // block in LDS) -> k by kc -> m by 128.  mc3 = mi tiles (at most
+            // 512).
             p->kernel = 2;
-            p->mt = p->nt = 128;
-            p->ks = 8;
+            p->mt = kMTb;
+            p->nt = kNCb;
+            p->ks = kKSlds;
             p->kc = kKC;
             p->kc3 = 512;
-            p->mc3 = 512;
-            p->mi = (int)(p->mc3 / p->mt);
+            p->mi = tiles_per_wg(cdiv(n, p->nt), cdiv(m, p->mt));
+            p->mc3 = (int64_t)p->mi * p->mt;
             p->xcd_aware = 1;
             p->group_m = 1;
             p->k_range = p->kc < k ? p->kc : k;
@@ -143,30 +216,36 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             break;
         }
         case MOMMS_C3A2C0: {
-            // n, m by a C block per XCD -> k by kc -> m by 128 (A block in
+            // n, m by a C block per XCD -> k by kc -> m by 64 (A block in
             // LDS) -> n by 128; one launch, every workgroup walks all of k.
+            // The C block is the tiles one XCD runs at once (32 workgroups,
+            // one per CU): 4 x 8 tiles of 64 x 128 = 256 x 1024 = 2 MiB,
+            // half the L2 (Sec. 4.1: the other half holds the A blocks and
+            // B slices streaming through it).
             p->kernel = 1;
-            p->mt = p->nt = 128;
-            p->ks = 8;
+            p->mt = kMCa;
+            p->nt = kNTa;
+            p->ks = kKSlds;
             p->kc = kKC;
             p->nj = 1;
             p->xcd_aware = 1;
-            p->group_m = (int)(cdiv(m, 128) < 4 ? cdiv(m, 128) : 4);
-            p->mc3 = (int64_t)p->group_m * 128;
-            p->nc3 = 8 * 128;
+            p->group_m = (int)(cdiv(m, p->mt) < 4 ? cdiv(m, p->mt) : 4);
+            p->mc3 = (int64_t)p->group_m * p->mt;
+            p->nc3 = (int64_t)(kWGsPerXcdLds / 4) * p->nt;
             p->k_range = p->kc < k ? p->kc : k;
             p->workgroups = cdiv(m, p->mt) * cdiv(n, p->nt);
             break;
         }
         case MOMMS_C4A2C0: {
-            // m, n by a 4096 x 4096 C block (MALL) -> k by kc -> m by 128 (A
+            // m, n by a 4096 x 4096 C block (MALL) -> k by kc -> m by 64 (A
             // block in LDS) -> n by 128 across workgroups.
             p->kernel = 1;
-            p->mt = p->nt = 128;
-            p->ks = 8;
+            p->mt = kMCa;
+            p->nt = kNTa;
+            p->ks = kKSlds;
             p->kc = kKC;
             p->mc4 = p->nc4 = 4096;
-            p->nj = 4;
+            p->nj = tiles_per_wg(cdiv(m < p->mc4 ? m : p->mc4, p->mt), cdiv(n < p->nc4 ? n : p->nc4, p->nt));
             p->k_range = p->kc < k ? p->kc : k;
             const int64_t blocks = cdiv(m, p->mc4) * cdiv(n, p->nc4);
             const int64_t pcs = k > 0 ? cdiv(k, p->kc) : 1;
@@ -185,8 +264,8 @@ size_t workspace_bytes(int member, int64_t m, int64_t n, int64_t k) {
     (void)m;
     (void)k;
     if (member != MOMMS_A2C0) return 0;
-    const int64_t nc = n < 4096 ? n : 4096;
-    return (size_t)(kKC * cdiv(nc, 128) * 128) * sizeof(double);
+    const int64_t nc = n < kGotoNc ? n : kGotoNc;
+    return (size_t)(kKC * cdiv(nc, kNTa) * kNTa) * sizeof(double);
 }
 
 // Element transfers of the resident algorithms of Sec. 2.2 between a slow
@@ -323,7 +402,7 @@ int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int pa
             const double gn = std::ceil((double)kWGsPerXcdLds / gm);
             const double rounds = (tm * tn) / (gm * gn);
             a = rounds * gm * t * K;
-            b = rounds * gn * t * K;
+            b = rounds * gn * (double)p.nt * K;
             // C is updated per kc but stays in L2: fabric sees it once.
             c_traffic(m, n, k, k, beta, &cr, &cw);
             break;
@@ -513,6 +592,19 @@ int momms_model_resident(int resident, int64_t m, int64_t n, int64_t k, int64_t 
     if (b2 < 1) return -6;
     if (!counts) return -8;
     momms::resident_counts(resident, m, n, k, b1, b2, beta, counts);
+    return 0;
+}
+
+int momms_lds_block(double lds_bytes, int slice, int tile_other, double beta_stream, double beta_c, int* rows,
+                    int* kc) {
+    if (!(lds_bytes > 0) || !std::isfinite(lds_bytes)) return -1;
+    if (slice < 1) return -2;
+    if (tile_other < 1) return -3;
+    if (!(beta_stream > 0) || !std::isfinite(beta_stream)) return -4;
+    if (!(beta_c > 0) || !std::isfinite(beta_c)) return -5;
+    if (!rows) return -6;
+    if (!kc) return -7;
+    momms::lds_block(lds_bytes / 8.0, slice, tile_other, beta_stream, beta_c, rows, kc);
     return 0;
 }
 

@@ -9,12 +9,22 @@ namespace momms {
 
 constexpr int kCUs = 256;              // MI355X: 8 XCDs x 32 CUs
 constexpr double kXcdsH = 8.0;         // XCD count as a double for the model
-constexpr int64_t kKC = 128;           // k depth of an LDS-resident block
+// LDS-resident blocks (level 2): A block kMCa x kKC for the A-resident
+// kernel, B block kKC x kNCb for the B-resident kernel; the C tiles they
+// update are kMCa x kNTa and kMTb x kNCb.  lds_block() derives these from the
+// Sec. 2.4 balance and the Sec. 4.1 capacity.
+constexpr int kKSlds = 32;             // k depth of a streamed slice of the LDS-resident kernels
+constexpr int64_t kKC = 160;           // k depth of an LDS-resident block
+constexpr int kMCa = 64, kNTa = 128;   // A-resident kernel: block rows, C tile columns
+constexpr int kMTb = 128, kNCb = 64;   // B-resident kernel: C tile rows, block columns
+constexpr int64_t kGotoNc = 2048;      // Goto's n_c: its packed k_c x n_c panel is 2.5 MiB
 constexpr int kWGsPerXcd128 = 64;      // 128x128 register tile: 2 workgroups per CU
 constexpr int kWGsPerXcd64 = 128;      // 64x64 register tile: 4 workgroups per CU (LDS-bound)
 constexpr int kWGsPerXcdLds = 32;      // LDS-resident kernels: 1 workgroup per CU
 
 int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p);
+void lds_block(double lds_doubles, int slice, int tile_other, double beta_stream, double beta_c, int* rows,
+               int* kc);
 size_t workspace_bytes(int member, int64_t m, int64_t n, int64_t k);
 int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int packed, momms_bytes* o);
 int select_member(int64_t m, int64_t n, int64_t k);

@@ -38,7 +38,8 @@ constexpr int kSlabElems = kT * kSlab;
 
 typedef TileCfg<128, 128, 16, 2, 2> Cfg128;
 typedef TileCfg<64, 64, 16, 2, 2> Cfg64;
-typedef TileCfg<128, 128, 8, 4, 4> CfgK;   // the LDS-resident block kernels (sixteen waves)
+typedef TileCfg<kMCa, kNTa, kKSlds, kMCa / 32, kNTa / 32> CfgA;   // the LDS-resident A-block kernel
+typedef TileCfg<kMTb, kNCb, kKSlds, kMTb / 32, kNCb / 32> CfgB;   // the LDS-resident B-block kernel
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
@@ -211,20 +212,21 @@ static void launch(const TArgs& a, int tile, int64_t s0, int64_t s1, double beta
 
 // The LDS-resident A-block kernel on tile-major operands: A from its 128 x 16
 // slabs, B k-slices straight from the tile-major column panels (the panel
-// height is the padded k).  s covers granules of 128 rows x nj column tiles.
+// height is the padded k).  s covers granules of kMCa rows x nj column tiles.
 static void launch_a2(const TArgs& a, int64_t k0, int64_t k1, const Sched& s, int nj, int64_t slabs) {
     const int grid = s.tiles_m * s.tiles_n;
     if (grid <= 0) return;
-    hipLaunchKernelGGL((k_a2<CfgK, kKC, false, false, true, true>), dim3(grid), dim3(CfgK::THREADS), 0, a.st, a.M,
+    hipLaunchKernelGGL((k_a2<CfgA, kKC, false, false, true, true>), dim3(grid), dim3(CfgA::THREADS), 0, a.st, a.M,
                        a.N, k0, k1, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc, s, nj, (int64_t)0,
                        (int64_t)0);
 }
 
-// Granules of 128 rows x nj column tiles over [m_off, m_lim) x [n_off, n_lim).
+// Granules of kMCa rows x nj column tiles (kNTa wide) over [m_off, m_lim) x
+// [n_off, n_lim).
 static Sched granules(int64_t m_off, int64_t n_off, int64_t m_lim, int64_t n_lim, int nj, int64_t group_m,
                       bool xcd) {
-    Sched s = sched_of(m_off, n_off, m_lim, n_lim, kT, group_m, xcd);
-    s.tiles_n = (int)cdiv(n_lim - n_off, (int64_t)nj * kT);
+    Sched s = sched_of(m_off, n_off, m_lim, n_lim, kMCa, group_m, xcd);
+    s.tiles_n = (int)cdiv(n_lim - n_off, (int64_t)nj * kNTa);
     return s;
 }
 
@@ -269,7 +271,7 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
             }
             break;
         case MOMMS_B3A2C0: {
-            // k by kc3 -> granules of 128 rows x nc3 columns in column-major
+            // k by kc3 -> granules of kMCa rows x nc3 columns in column-major
             // order (one XCD's run shares a kc3 x nc3 B block) -> the kernel
             const Sched s = granules(0, 0, M, N, p.nj, p.group_m, true);
             for (int64_t kb = 0; kb < K; kb += p.kc3) {
@@ -279,15 +281,15 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
             break;
         }
         case MOMMS_A3B2C0: {
-            // k by kc3 -> granules of mc3 rows x 128 columns, XCD-aware ->
-            // the kernel with the B block (kc x 128) in LDS, A slices streamed
-            Sched s = sched_of(0, 0, M, N, kT, 1, true);
+            // k by kc3 -> granules of mc3 rows x kNCb columns, XCD-aware ->
+            // the kernel with the B block (kc x kNCb) in LDS, A slices streamed
+            Sched s = sched_of(0, 0, M, N, kNCb, 1, true);
             s.tiles_m = (int)cdiv(M, p.mc3);
             for (int64_t kb = 0; kb < K; kb += p.kc3) {
                 const int64_t ke = kb + p.kc3 < K ? kb + p.kc3 : K;
                 const int grid = s.tiles_m * s.tiles_n;
                 if (grid > 0)
-                    hipLaunchKernelGGL((k_b2<CfgK, kKC, false, false, true>), dim3(grid), dim3(CfgK::THREADS), 0,
+                    hipLaunchKernelGGL((k_b2<CfgB, kKC, false, false, true>), dim3(grid), dim3(CfgB::THREADS), 0,
                                        a.st, M, N, kb, ke, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc, s,
                                        p.mi);
             }

@@ -124,7 +124,8 @@ def test_alpha_zero_k_zero_beta_zero():
 
 
 def test_packed_goto_with_workspace():
-    # n spans two n_c = 4096 panels; k spans three kc = 128 passes.
+    # n spans three n_c = 2048 panels (the last one ragged); k spans two
+    # kc = 256 passes.
     m, n, k = 160, 4200, 300
     A, B, C = workloads.gemm_operands(m, n, k)
     ws = torch.empty(mm.workspace_size(m, n, k, "A2C0"), dtype=torch.uint8, device=DEV)

@@ -108,10 +108,42 @@ def test_member_models_follow_resident_counts():
     # The level-3 models of the gfx950 members are resident counts with the
     # member's block sizes at the L2 boundary.
     m = n = k = 8192
+    g = mm.member_plan("A2C0", m, n, k)
     for name, res, b in [("B3C0", "B", (512, 128)), ("A3C0", "A", (128, 512)), ("C3C0", "C", (1024, 1024)),
-                         ("A2C0", "B", (128, 512))]:
+                         ("A2C0", "B", (g["kc"], g["nj"] * g["nt"]))]:
         got = mm.model_bytes(name, m, n, k, beta=1.0)
         want = mm.model_resident(res, m, n, k, *b, 1.0)
         assert got["a_reads"] == 8 * want["a_reads"], name
         assert got["b_reads"] == 8 * want["b_reads"], name
         assert got["c_reads"] == 8 * want["c_reads"] and got["c_writes"] == 8 * want["c_writes"], name
+
+
+def test_lds_block_solver():
+    # gfx950: 160 KiB of LDS, 8-deep slices of a 128-wide streamed panel; the
+    # panel comes from the L2 (39 TB/s) and C is read and written in HBM
+    # (8 TB/s), so a C element costs 2 * 39.3 / 8 streamed elements.
+    lds, bc = 160 * 1024, 2 * 39.3 / 8
+    assert mm.lds_block(lds, 32, 128, 1.0, bc) == (64, 160)
+    # the plans of the LDS-resident members use exactly that block, with
+    # 32-deep streamed slices
+    for name in ("A2C0", "B3A2C0", "C3A2C0", "C4A2C0"):
+        p = mm.member_plan(name, 8192, 8192, 8192)
+        assert (p["mt"], p["kc"], p["ks"]) == (64, 160, 32), name
+    p = mm.member_plan("A3B2C0", 8192, 8192, 8192)
+    assert (p["nt"], p["kc"], p["ks"]) == (64, 160, 32)
+    # equal costs and thin slices: the block comes out nearly square
+    # (Sec. 2.4), 128 x 136 within capacity
+    assert mm.lds_block(lds, 8, 128, 1.0, 1.0) == (128, 136)
+    # every answer fits: block (pitch kc + 1) plus two streamed slices
+    for b in (8 * 1024, 64 * 1024, 160 * 1024, 1 << 20):
+        for ratio in (0.25, 1.0, 2.0, 10.0):
+            r, k = mm.lds_block(b, 8, 128, 1.0, ratio)
+            if r:
+                assert r % 64 == 0 and k % 8 == 0
+                assert 8 * (r * (k + 1) + 2 * 8 * 130) <= b
+    # C dearer -> the block deepens (kc / rows grows), never the reverse
+    ratios = [mm.lds_block(1 << 20, 8, 128, 1.0, c) for c in (0.5, 1.0, 4.0, 16.0)]
+    depth = [k / r for r, k in ratios]
+    assert depth == sorted(depth)
+    with pytest.raises(Exception):
+        mm.lds_block(-1, 8, 128, 1.0, 1.0)
