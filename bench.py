@@ -257,12 +257,12 @@ def bench_fp64(args):
 
 
 def kernel_source_sha():
-    """Hash of the FP64 kernel sources (row-major and tiled) without their
-    comments: stored traffic is only used while it matches."""
+    """Hash of the FP64 kernel and planner sources (row-major and tiled)
+    without their comments: stored traffic is only used while it matches."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("kernels_f64.hip", "gemm_f64.hip", "sched.h", "tiled.hip"):
+    for f in ("kernels_f64.hip", "gemm_f64.hip", "sched.h", "tiled.hip", "plan.cpp", "plan_internal.h"):
         with open(os.path.join(ROOT, "paper_1904_05717_amd", "csrc", f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmomms.so")
 SOURCES = ["gemm_f64.hip", "split.hip", "batch.hip", "tiled.hip", "syrk.hip", "tri.hip", "chol.hip", "ooc.hip",
-           "lowbw.hip", "plan.cpp"]
+           "lowbw.hip", "plan.cpp", "model.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

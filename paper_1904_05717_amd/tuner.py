@@ -2,10 +2,12 @@
 
 `sweep` times every family member on the device for a list of shapes and
 returns, per shape bucket (rounded log2 of m, n, k), the fastest member.
-`save` writes that table as JSON; `install` loads a table into the library
+`save` writes that table as JSON, with a hash of the FP64 kernel and planner
+sources it was measured on; `install` loads a table into the library
 (momms_set_member_table), after which MOMMS_AUTO uses it before the analytic
-prior.  The package installs tuned_members.json (next to this file) at
-import when it exists.
+prior, but only while that hash matches the sources next to the built
+library (otherwise the prior decides).  The package installs
+tuned_members.json (next to this file) at import when it exists.
 
     python -c "from paper_1904_05717_amd import tuner; tuner.main()"   # on the GPU
 """
@@ -14,7 +16,25 @@ import json
 import math
 import os
 
-TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_members.json")
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tuned_members.json")
+# The sources whose code decides a member's speed: its kernels, its launch
+# sequence and its plan.
+SOURCES = ("kernels_f64.hip", "gemm_f64.hip", "sched.h", "plan.cpp", "plan_internal.h")
+
+
+def source_sha(files=SOURCES):
+    """Hash of the given csrc files with their comments stripped."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(text.encode())
+    return h.hexdigest()[:16]
 
 SWEEP_SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
                 (16384, 16384, 256), (16384, 256, 16384), (4096, 8192, 2048), (4096, 2048, 4096),
@@ -64,14 +84,16 @@ def pick(mm, m, n, k, times):
 
 
 def repick(path=TABLE):
-    """Recompute `best` of a saved table from its stored timings."""
+    """Recompute `best` of a saved table from its stored timings (keeps the
+    table's source hash: the timings still belong to those sources)."""
     import paper_1904_05717_amd as mm
     with open(path) as fh:
-        entries = json.load(fh)["entries"]
-    for e in entries:
+        table = json.load(fh)
+    for e in table["entries"]:
         e["best"] = pick(mm, *e["shape"], e["ms"])
-    save(entries, path)
-    return entries
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1)
+    return table["entries"]
 
 
 def sweep(shapes=SWEEP_SHAPES, members=None):
@@ -99,16 +121,22 @@ def sweep(shapes=SWEEP_SHAPES, members=None):
 
 def save(entries, path=TABLE):
     with open(path, "w") as fh:
-        json.dump({"entries": entries}, fh, indent=1)
+        json.dump({"source_sha": source_sha(), "entries": entries}, fh, indent=1)
 
 
 def install(path=TABLE):
-    """Load a saved table into the library; returns the number of entries."""
+    """Load a saved table into the library; returns the number of entries
+    (0, leaving the analytic prior in charge, when there is no table or it
+    was measured on other kernel or planner sources)."""
     from . import MEMBERS, _lib
     if not os.path.exists(path):
         return 0
     with open(path) as fh:
-        entries = json.load(fh)["entries"]
+        table = json.load(fh)
+    if table.get("source_sha") != source_sha():
+        _lib.momms_set_member_table(0, None, None, None, None)
+        return 0
+    entries = table["entries"]
     rows = [(e["bucket"], MEMBERS[e["best"]]) for e in entries]
     n = len(rows)
     arr = ctypes.c_int * max(n, 1)

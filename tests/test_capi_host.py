@@ -136,6 +136,24 @@ def test_member_table_overrides_prior_and_validates():
     assert mm.select_member(8192, 8192, 8192) in mm.FAMILY
 
 
+def test_member_table_is_ignored_when_measured_on_other_sources(tmp_path):
+    import json
+    from paper_1904_05717_amd import tuner
+    entry = {"shape": [32, 32, 32], "bucket": [5, 5, 5], "best": "B3C0", "ms": {}, "prior": "C0"}
+    stale = tmp_path / "stale.json"
+    stale.write_text(json.dumps({"source_sha": "0000000000000000", "entries": [entry]}))
+    fresh = tmp_path / "fresh.json"
+    fresh.write_text(json.dumps({"source_sha": tuner.source_sha(), "entries": [entry]}))
+    try:
+        assert tuner.install(str(stale)) == 0
+        assert mm.select_member(32, 32, 32) == mm.MEMBER_NAMES[_lib.momms_select_member_prior(32, 32, 32)]
+        assert tuner.install(str(fresh)) == 1
+        assert mm.select_member(32, 32, 32) == "B3C0"
+    finally:
+        _lib.momms_set_member_table(0, None, None, None, None)
+        tuner.install()
+
+
 def test_int8_and_fp8_exactness_limits():
     # slices * k (k rounded up to 128) must stay <= 2^17 so every INT32 sum
     # is exact; beyond it the call is refused before any launch.

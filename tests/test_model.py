@@ -147,3 +147,80 @@ def test_lds_block_solver():
     assert depth == sorted(depth)
     with pytest.raises(Exception):
         mm.lds_block(-1, 8, 128, 1.0, 1.0)
+
+
+L2_HALF = 0.5 * 4 * 1024 * 1024   # bytes: the Sec. 4.1 share of one XCD's L2 a block may take
+
+
+def resident(res, shape, b1, b2, beta=1.0):
+    return mm.model_resident(res, *shape, b1, b2, beta)
+
+
+def member_counts(name, shape):
+    """Element transfers each member's model must equal, written as the Sec.
+    2.2 resident counts (pinned above against the LRU simulation) of the
+    member's own planned blocks at the L2 boundary, plus the member's rule
+    for C: C is read and written once per pass over its k range."""
+    m, n, k = shape
+    p = mm.member_plan(name, m, n, k)
+    cdiv = lambda a, b: -(-a // b)  # noqa: E731
+    passes = cdiv(k, p["k_range"]) if k else 1
+    c = {"c_reads": m * n * passes, "c_writes": m * n * passes}
+    t, tm, tn = p["mt"], cdiv(m, p["mt"]), cdiv(n, p["nt"])
+    if name == "C0":
+        # the tiles one XCD runs at once: every 8th tile of a run of
+        # 8 * per_xcd consecutive row-major tiles, i.e. (with at least 8 tile
+        # columns, so every XCD gets whole column sets) a C block of `rows`
+        # tile rows by tn / 8 (strided) tile columns: Resident C on it
+        per_xcd = 64 if t == 128 else 128
+        if tn < 8 or tn % 8:
+            pytest.skip("C0's every-8th-tile pattern on a grid not 8 tiles wide has no Resident C block form")
+        rows = min(cdiv(8 * per_xcd, tn), tm)
+        ab = resident("C", shape, rows * t, (tn // 8) * t)
+    elif name == "C3C0":
+        ab = resident("C", shape, p["mc3"], p["nc3"])
+    elif name == "B3C0":
+        r = resident("B", shape, p["kc3"], t)
+        ab = {"a_reads": r["a_reads"] if 8 * m * p["kc3"] > L2_HALF else m * k * min(tn, 8), "b_reads": r["b_reads"]}
+    elif name == "A3C0":
+        r = resident("A", shape, t, p["kc3"])
+        ab = {"a_reads": r["a_reads"], "b_reads": r["b_reads"] if 8 * p["kc3"] * n > L2_HALF else k * n * min(tm, 8)}
+    elif name == "A2C0":
+        # Resident B (kc x nj tiles) inside every n_c panel
+        panels = [min(p["nc"], n - j) for j in range(0, n, p["nc"])]
+        ab = {"a_reads": m * k * sum(cdiv(w, p["nj"] * p["nt"]) for w in panels),
+              "b_reads": resident("B", shape, p["kc"], p["nj"] * p["nt"])["b_reads"]}
+    elif name == "B3A2C0":
+        r = resident("B", shape, p["kc3"], p["nc3"])
+        jc3 = cdiv(n, p["nc3"])
+        ab = {"a_reads": r["a_reads"] if 8 * m * p["kc3"] > L2_HALF else m * k * min(jc3, 8), "b_reads": r["b_reads"]}
+    elif name == "A3B2C0":
+        r = resident("A", shape, p["mc3"], p["kc3"])
+        ic3 = cdiv(m, p["mc3"])
+        ab = {"a_reads": r["a_reads"], "b_reads": r["b_reads"] if 8 * p["kc3"] * n > L2_HALF else k * n * min(ic3, 8)}
+    elif name == "C3A2C0":
+        # the C block of one XCD round (group_m x 32 / group_m tiles) is
+        # Resident C; its lines stay for reads (C read once) but are written
+        # back after every pass
+        cols = min(tn, cdiv(32, p["group_m"]))
+        rows = min(tm, cdiv(32, cols))
+        ab = resident("C", shape, rows * p["mt"], cols * p["nt"])
+        c = {"c_reads": m * n, "c_writes": m * n * passes}
+    elif name == "C4A2C0":
+        # Resident C at level 4 (mc4 x nc4) for B; inside a C block A is
+        # streamed once per n-granule of nj tiles (Goto's loop)
+        panels = [min(p["nc4"], n - j) for j in range(0, n, p["nc4"])]
+        ab = {"a_reads": m * k * sum(cdiv(w, p["nj"] * p["nt"]) for w in panels),
+              "b_reads": resident("C", shape, p["mc4"], p["nc4"])["b_reads"]}
+    else:
+        raise ValueError(name)
+    return {**{x: float(v) for x, v in ab.items() if x in ("a_reads", "b_reads")}, **c}
+
+
+@pytest.mark.parametrize("name", ["C0", "C3C0", "B3C0", "A3C0", "A2C0", "B3A2C0", "A3B2C0", "C3A2C0", "C4A2C0"])
+@pytest.mark.parametrize("shape", [(8192, 8192, 8192), (16384, 16384, 256), (16384, 256, 16384), (1000, 3000, 700)])
+def test_every_member_model_is_its_resident_counts(name, shape):
+    got = mm.model_bytes(name, *shape, beta=1.0)
+    want = member_counts(name, shape)
+    for x in ("a_reads", "b_reads", "c_reads", "c_writes"):
+        assert got[x] == pytest.approx(8 * want[x], rel=1e-12), (name, x, got[x], 8 * want[x])
