@@ -24,11 +24,39 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sched.h"
 
 namespace momms {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
+// A zero in device memory for staged entries outside an operand (see
+// Stage::load).  Not const, so that the compiler does not fold its loads.
+static __device__ double kZeroEntry = 0.0;
+
+// *(base + off bytes) for a wave-uniform base and a 32-bit lane offset, as a
+// global load with a scalar base address and a vector offset: no per-lane
+// 64-bit address arithmetic.  The base is opaque to the compiler, which
+// otherwise folds the offset in once and steps a 64-bit vector address per
+// load.  The offset is opaque at each use too, or its zero extension is
+// hoisted into a 64-bit register and the scalar-base form is lost.
+typedef __attribute__((address_space(1))) const char gchar;
+__device__ __forceinline__ double load_sbase(const double* base, uint32_t off) {
+    gchar* b = (gchar*)reinterpret_cast<const char*>(base);
+    asm volatile("" : "+s"(b), "+v"(off));
+    return *reinterpret_cast<__attribute__((address_space(1))) const double*>(b + off);
+}
+// The store of the same form.
+typedef __attribute__((address_space(1))) char gchar_w;
+__device__ __forceinline__ void store_sbase(double* base, uint32_t off, double v) {
+    gchar_w* b = (gchar_w*)reinterpret_cast<char*>(base);
+    asm volatile("" : "+s"(b), "+v"(off));
+    *reinterpret_cast<__attribute__((address_space(1))) double*>(b + off) = v;
+}
+// A lane offset of that form fits 32 bits for a leading dimension below 2^24.
+__device__ __forceinline__ bool sbase_ld(int64_t ld) { return ld < ((int64_t)1 << 24); }
 
 // Register staging of an R x S tile of a logical operand X, where
 // X(r, s) = P[(r0 + r) * ld + s0 + s] if !TRANS, P[(s0 + s) * ld + r0 + r] if TRANS.
@@ -44,37 +72,63 @@ struct Stage {
         if (TRANS) { s = e / R; r = e - s * R; }
         else       { r = e / S; s = e - r * S; }
     }
+    // Element i of the stage (a stage's loads and stores can then be spread
+    // over a step).  Every lane loads, an entry outside from kZeroEntry: a
+    // load inside a branch may not have been issued, and the compiler then
+    // waits for every load in flight before it uses any older one; a value
+    // masked after its load would be waited for where the mask is applied.
+    __device__ __forceinline__ void load_elem(int i, const double* __restrict__ P, int64_t ld, int64_t r0,
+                                              int64_t s0, int64_t rlim, int64_t slim, int tid) {
+        int r, s;
+        coord(tid + i * THREADS, r, s);
+        const int64_t gr = r0 + r, gs = s0 + s;
+        const bool ok = gr < rlim && gs < slim;
+        v[i] = *(ok ? P + (TRANS ? gs * ld + gr : gr * ld + gs) : &kZeroEntry);
+    }
     __device__ __forceinline__ void load(const double* __restrict__ P, int64_t ld, int64_t r0, int64_t s0,
                                          int64_t rlim, int64_t slim, int tid) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            int r, s;
-            coord(tid + i * THREADS, r, s);
-            const int64_t gr = r0 + r, gs = s0 + s;
-            v[i] = (gr < rlim && gs < slim) ? (TRANS ? P[gs * ld + gr] : P[gr * ld + gs]) : 0.0;
-        }
+        for (int i = 0; i < N; ++i) load_elem(i, P, ld, r0, s0, rlim, slim, tid);
+    }
+    // Interior staging: when every entry of the stage lies inside the
+    // operand, lane tid's entry i is at a wave-uniform address plus one
+    // per-lane 32-bit byte offset (lane_offset), so each load is a scalar
+    // base plus that offset with no per-entry address arithmetic.  origin
+    // points at X(0, 0).
+    static constexpr int CONT = TRANS ? R : S;       // contiguous extent
+    static_assert(THREADS % CONT == 0, "threads must cover whole contiguous rows");
+    static constexpr int RPP = THREADS / CONT;       // strided positions per pass
+    __device__ __forceinline__ static uint32_t lane_offset(int64_t ld, int tid) {
+        return (uint32_t)(((int64_t)(tid / CONT) * ld + tid % CONT) * (int64_t)sizeof(double));
+    }
+    __device__ __forceinline__ static bool fast_ld(int64_t ld) { return sbase_ld(ld); }
+    __device__ __forceinline__ void load_elem_fast(int i, const double* origin, int64_t ld, uint32_t off) {
+        v[i] = load_sbase(origin + (int64_t)i * RPP * ld, off);
+    }
+    __device__ __forceinline__ void store_elem(int i, double* __restrict__ L, int lld, int tid) const {
+        int r, s;
+        coord(tid + i * THREADS, r, s);
+        L[r * lld + s] = v[i];
     }
     __device__ __forceinline__ void store(double* __restrict__ L, int lld, int tid) const {
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            int r, s;
-            coord(tid + i * THREADS, r, s);
-            L[r * lld + s] = v[i];
-        }
+        for (int i = 0; i < N; ++i) store_elem(i, L, lld, tid);
     }
     // X(r, s) from tile-major slabs of 16 columns (row pitch 16, consecutive
     // slabs slab_stride apart): X(r, s) = P[(s / 16) * slab_stride + r * 16 +
     // s % 16] for s < slim (the columns the storage holds; zero-padded up to
     // there), zero beyond.
+    __device__ __forceinline__ void load_slabs_elem(int i, const double* __restrict__ P, int64_t slab_stride,
+                                                    int64_t slim, int tid) {
+        static_assert(!TRANS, "slabs hold rows of 16 consecutive columns");
+        int r, s;
+        coord(tid + i * THREADS, r, s);
+        v[i] = *(s < slim ? P + (int64_t)(s / 16) * slab_stride + r * 16 + s % 16 : &kZeroEntry);   // as in load
+    }
     __device__ __forceinline__ void load_slabs(const double* __restrict__ P, int64_t slab_stride, int64_t slim,
                                                int tid) {
-        static_assert(!TRANS, "slabs hold rows of 16 consecutive columns");
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            int r, s;
-            coord(tid + i * THREADS, r, s);
-            v[i] = s < slim ? P[(int64_t)(s / 16) * slab_stride + r * 16 + s % 16] : 0.0;
-        }
+        for (int i = 0; i < N; ++i) load_slabs_elem(i, P, slab_stride, slim, tid);
     }
 };
 
@@ -181,10 +235,14 @@ __device__ __forceinline__ void mma_lds(const double* __restrict__ As, int a_ld,
 // before the MFMAs of step kk are issued (two fragment register sets), so a
 // wave waits for LDS once per slice rather than once per 4-deep step.  For
 // small wave tiles, whose four MFMAs per step do not cover an LDS read.
-template <class CF, int KSTEPS>
+// between(kk) runs in step kk, after those reads and before its MFMAs: work
+// placed there (staging loads and stores) is spread over the MFMA stream
+// instead of stalling it all at once.
+template <class CF, int KSTEPS, class Between>
 __device__ __forceinline__ void mma_lds_pipe(const double* __restrict__ As, int a_ld, int a_k0,
                                              const double* __restrict__ Bs, int b_ld, int b_k0,
-                                             d4 (&acc)[CF::BM][CF::BN], int wm, int wn, int lane) {
+                                             d4 (&acc)[CF::BM][CF::BN], int wm, int wn, int lane,
+                                             Between&& between) {
     const int li = lane & 15, lk = lane >> 4;
     const double* ap = As + (wm * CF::WTM + li) * a_ld + a_k0 + lk;
     const double* bp = Bs + (b_k0 + lk) * b_ld + wn * CF::WTN + li;
@@ -202,6 +260,7 @@ __device__ __forceinline__ void mma_lds_pipe(const double* __restrict__ As, int 
 #pragma unroll
             for (int j = 0; j < CF::BN; ++j) b[cur ^ 1][j] = bp[(kk + 1) * 4 * b_ld + j * 16];
         }
+        between(kk);
         __builtin_amdgcn_sched_barrier(0);   // keep the next step's reads ahead of these MFMAs
 #pragma unroll
         for (int i = 0; i < CF::BM; ++i)
@@ -270,11 +329,13 @@ __device__ __forceinline__ void store_c_tri(const d4 (&acc)[CF::BM][CF::BN], dou
 }
 
 // The C values the epilogue of the tile at (m0, n0) reads, loaded ahead of
-// it so that their latency overlaps MFMAs (an entry outside C reads C[0] and
-// is discarded).
+// it so that their latency overlaps MFMAs.  Every lane loads: an entry
+// outside C, or every entry when !read (beta = 0, C is not read), comes from
+// kZeroEntry.
 template <class CF>
 __device__ __forceinline__ void load_c(double (&cv)[CF::BM][CF::BN][4], const double* __restrict__ C, int64_t ldc,
-                                       int64_t m0, int64_t n0, int64_t M, int64_t N, int wm, int wn, int lane) {
+                                       int64_t m0, int64_t n0, int64_t M, int64_t N, int wm, int wn, int lane,
+                                       bool read) {
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int i = 0; i < CF::BM; ++i)
@@ -284,7 +345,7 @@ __device__ __forceinline__ void load_c(double (&cv)[CF::BM][CF::BN][4], const do
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = m0 + wm * CF::WTM + i * 16 + lk + 4 * r;
                 const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
-                cv[i][j][r] = C[(row < M && col < N) ? row * ldc + col : 0];
+                cv[i][j][r] = *(read && row < M && col < N ? C + row * ldc + col : &kZeroEntry);
             }
 }
 
@@ -305,6 +366,37 @@ __device__ __forceinline__ void store_c_loaded(const d4 (&acc)[CF::BM][CF::BN], 
                 const int64_t col = n0 + wn * CF::WTN + j * 16 + li;
                 if (row < M && col < N) C[row * ldc + col] = epilogue_value(alpha, acc[i][j][r], beta, cv[i][j][r]);
             }
+}
+
+// load_c and store_c_loaded for a tile that lies inside C (ldc below 2^24):
+// each of a lane's entries is at a wave-uniform address (Cw, the wave's C
+// origin, plus a multiple of 16 rows or columns) plus the lane offset coff =
+// ((lane / 16) * ldc + lane % 16) * 8 bytes, so no entry needs address
+// arithmetic or a bounds test.  With !read every entry loads kZeroEntry.
+template <class CF>
+__device__ __forceinline__ void load_c_fast(double (&cv)[CF::BM][CF::BN][4], const double* Cw, int64_t ldc,
+                                            uint32_t coff, bool read) {
+    const uint32_t co = read ? coff : 0u;
+#pragma unroll
+    for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::BN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                cv[i][j][r] = load_sbase(read ? Cw + (int64_t)(i * 16 + 4 * r) * ldc + j * 16 : &kZeroEntry, co);
+}
+template <class CF>
+__device__ __forceinline__ void store_c_fast(const d4 (&acc)[CF::BM][CF::BN], double alpha, double beta,
+                                             const double (&cv)[CF::BM][CF::BN][4], double* Cw, int64_t ldc,
+                                             uint32_t coff) {
+#pragma unroll
+    for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::BN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                store_sbase(Cw + (int64_t)(i * 16 + 4 * r) * ldc + j * 16, coff,
+                            epilogue_value(alpha, acc[i][j][r], beta, cv[i][j][r]));
 }
 
 template <class CF>
@@ -425,10 +517,8 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha, 
     regc_tile<CF, TA, TB>(M, N, k_begin, k_end, alpha, A, lda, B, ldb, beta, C, ldc, m0, n0, tm, tn, As, Bs);
 }
 
-// Slices ahead of an LDS-resident kernel's epilogue at which its C values are
-// loaded (a 32-deep slice is about 2 us of MFMAs), and the depth of the
-// register ring that streams the other operand's slices.
-constexpr int kPrefetchC = 1;
+// Depth of the register ring that streams the other operand's slices
+// through an LDS-resident kernel (a 32-deep slice is about 2 us of MFMAs).
 constexpr int kRing = 2;
 
 // ---------------------------------------------------------------------------
@@ -458,46 +548,28 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
     const int64_t m0 = s.m_off + (int64_t)tm * CF::MT;
     const int64_t nbeg = s.n_off + (int64_t)tn * nj * CF::NT;
     const int64_t nend = (nbeg + (int64_t)nj * CF::NT) < s.n_lim ? (nbeg + (int64_t)nj * CF::NT) : s.n_lim;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: wave-level addresses stay scalar
     const int wm = wave / CF::WN, wn = wave % CF::WN;
     const int ntiles = (int)((nend - nbeg + CF::NT - 1) / CF::NT);
+    const uint32_t coff = (uint32_t)(((int64_t)(lane >> 4) * ldc + (lane & 15)) * 8);
+    // Below, every chunk has at least one step (total >= 1), so that no ring
+    // load or store is conditional (see the steps).
+    if (ntiles <= 0) return;
 
-    Stage<CF::KS, CF::NT, CF::THREADS, PACKED ? false : TB> sb[kRing];
+    using SB = Stage<CF::KS, CF::NT, CF::THREADS, PACKED ? false : TB>;
+    using SA = Stage<CF::MT, CF::KS, CF::THREADS, TA>;
+    SB sb[kRing];
     d4 acc[CF::BM][CF::BN];
+    const int64_t ldbs = PACKED ? CF::NT : ldb;   // the B slices' leading dimension
+    const uint32_t boff = SB::lane_offset(ldbs, tid), aoff = SA::lane_offset(lda, tid);
 
     for (int64_t kb = k_begin; kb < k_end; kb += KC) {
         const int64_t kbe = (kb + KC) < k_end ? (kb + KC) : k_end;
         const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
         const int total = ntiles * nsl;
-        __syncthreads();  // previous chunk's readers of As / Bs are done
-        // the A block, four slices in flight at a time
-#pragma unroll 1
-        for (int c0 = 0; c0 < nsl; c0 += 4) {
-            Stage<CF::MT, CF::KS, CF::THREADS, TA> sq[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + u;
-                if (c >= nsl) break;
-                if constexpr (TILED) {
-                    // tile-major A: 128 x 16 slabs, lda = slabs per row panel,
-                    // zero beyond the matrix (m0 is a multiple of MT, which
-                    // divides 128: the block is rows m0 % 128 .. of its
-                    // slabs; a slice starts on a slab boundary)
-                    const int64_t kk = kb + (int64_t)c * CF::KS;
-                    const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + (m0 % 128) * 16;
-                    sq[u].load_slabs(P, 2048, lda * 16 - kk, tid);
-                } else {
-                    sq[u].load(A, lda, m0, kb + c * CF::KS, M, kbe, tid);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + u;
-                if (c >= nsl) break;
-                sq[u].store(As + c * CF::KS, AB_LD, tid);
-            }
-        }
-        auto load_b = [&](auto& st, int t) {
+        // element e of B slice t of this chunk (n-tile t / nsl, slice t % nsl)
+        auto load_b = [&](auto& st, int t, int e) {
             const int j = t / nsl, sl = t - (t / nsl) * nsl;
             if (PACKED) {
                 // panel row (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j);
@@ -505,51 +577,126 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
                 // k for a tile-major B); rows past it read as zero
                 const int64_t jt = (nbeg - pn0) / CF::NT + j;
                 const double* P = B + jt * ldb * CF::NT;
-                st.load(P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, ldb, CF::NT, tid);
+                st.load_elem(e, P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, ldb, CF::NT, tid);
             } else {
-                st.load(B, ldb, kb + (int64_t)sl * CF::KS, nbeg + (int64_t)j * CF::NT, kbe, nend, tid);
+                st.load_elem(e, B, ldb, kb + (int64_t)sl * CF::KS, nbeg + (int64_t)j * CF::NT, kbe, nend, tid);
             }
         };
+        // all of B slice t: the interior form when the slice lies inside B
+        // (both forms issue the same loads, so the branch does not disturb
+        // the compiler's count of loads in flight)
+        auto b_plan = [&](int t, bool& interior, const double*& origin) {
+            const int j = t / nsl, sl = t - (t / nsl) * nsl;
+            if (PACKED) {
+                const int64_t row0 = (kb - pk0) + (int64_t)sl * CF::KS;
+                interior = row0 + CF::KS <= ldb;
+                origin = B + ((nbeg - pn0) / CF::NT + j) * ldb * CF::NT + row0 * CF::NT;
+            } else {
+                const int64_t row0 = kb + (int64_t)sl * CF::KS, col0 = nbeg + (int64_t)j * CF::NT;
+                interior = row0 + CF::KS <= kbe && col0 + CF::NT <= nend && SB::fast_ld(ldb);
+                origin = TB ? B + col0 * ldb + row0 : B + row0 * ldb + col0;
+            }
+        };
+        auto load_b_elem = [&](auto& st, int t, int e, bool interior, const double* origin) {
+            if (interior) st.load_elem_fast(e, origin, ldbs, boff);
+            else          load_b(st, t, e);
+        };
+        auto load_b_all = [&](auto& st, int t) {
+            bool interior;
+            const double* origin;
+            b_plan(t, interior, origin);
+#pragma unroll
+            for (int e = 0; e < SB::N; ++e) load_b_elem(st, t, e, interior, origin);
+        };
+        // The chunk's A block and its first kRing B slices are all loaded
+        // into registers at once (one memory latency per chunk), then
+        // stored to LDS once the previous chunk's readers are done.
+        SA sq[KC / CF::KS];
+#pragma unroll
+        for (int c = 0; c < KC / CF::KS; ++c) {
+            if (c >= nsl) break;
+            const int64_t kk = kb + (int64_t)c * CF::KS;
+            if constexpr (TILED) {
+                // tile-major A: 128 x 16 slabs, lda = slabs per row panel,
+                // zero beyond the matrix (m0 is a multiple of MT, which
+                // divides 128: the block is rows m0 % 128 .. of its
+                // slabs; a slice starts on a slab boundary)
+                const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + (m0 % 128) * 16;
+                sq[c].load_slabs(P, 2048, lda * 16 - kk, tid);
+            } else if (m0 + CF::MT <= M && kk + CF::KS <= kbe && SA::fast_ld(lda)) {
+#pragma unroll
+                for (int e = 0; e < SA::N; ++e)
+                    sq[c].load_elem_fast(e, TA ? A + kk * lda + m0 : A + m0 * lda + kk, lda, aoff);
+            } else {
+                sq[c].load(A, lda, m0, kk, M, kbe, tid);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) load_b_all(sb[u], u < total ? u : total - 1);
+        __syncthreads();  // previous chunk's readers of As / Bs are done
+#pragma unroll
+        for (int c = 0; c < KC / CF::KS; ++c) {
+            if (c >= nsl) break;
+            sq[c].store(As + c * CF::KS, AB_LD, tid);
+        }
         // B slices kRing ahead through a ring of register sets: slice t + u
         // waits in set (t + u) % kRing (the loop runs kRing steps per
         // iteration, so every set index is a constant); the prefetch index
         // is clamped to the last slice rather than skipped, which keeps the
         // load where it is.  A 32-deep slice is about 2 us of MFMAs.
-        if (total > 0) {
-#pragma unroll
-            for (int u = 0; u < kRing; ++u) load_b(sb[u], u < total ? u : total - 1);
-            sb[0].store(Bs[0], CF::B_LD, tid);
-        }
+        sb[0].store(Bs[0], CF::B_LD, tid);
         __syncthreads();
         zero_acc<CF>(acc);
         const double beta_eff = (kb == 0) ? beta : 1.0;
-        // each n-tile's C values are loaded kPrefetchC slices before its
-        // epilogue (at its first slice if it has fewer)
-        const int pf_sl = nsl > kPrefetchC ? nsl - kPrefetchC : 0;
         double cv[CF::BM][CF::BN][4];
         // step t: slice t is in Bs[t & 1] and its register set is free again
-        // (stored in step t - 1); refill it with slice t + kRing, compute,
-        // then store slice t + 1 into the other buffer.
+        // (stored in step t - 1).  A tile's last step first loads the tile's
+        // C values (the epilogue's wait for them then leaves the refill in
+        // flight).  Every step refills the free set with slice t + kRing
+        // (clamped to the last slice), computes, and stores slice t + 1 into
+        // the other buffer; on the chunk's last step that is a clamped slice
+        // nobody reads, in a buffer the barrier of step t - 1 released.  No
+        // ring load or store is conditional: the compiler counts the loads in
+        // flight across steps only when every path issues the same ones.
         auto step = [&](int t, auto& reload, auto& ready, double* cur, double* other) {
             const int j = t / nsl, sl = t - j * nsl;
             const int64_t n0 = nbeg + (int64_t)j * CF::NT;
-            load_b(reload, t + kRing < total ? t + kRing : total - 1);
-            if (sl == pf_sl && beta_eff != 0.0) load_c<CF>(cv, C, ldc, m0, n0, M, nend, wm, wn, lane);
-            __builtin_amdgcn_sched_barrier(0);
-            mma_lds_pipe<CF, CF::KS / 4>(As, AB_LD, sl * CF::KS, cur, CF::B_LD, 0, acc, wm, wn, lane);
-            if (t + 1 < total) ready.store(other, CF::B_LD, tid);
-            if (sl == nsl - 1) {
-                store_c_loaded<CF>(acc, alpha, beta_eff, cv, C, ldc, m0, n0, M, nend, wm, wn, lane);
+            const bool last = sl == nsl - 1;
+            const int tr = t + kRing < total ? t + kRing : total - 1;
+            const bool cin = m0 + CF::MT <= M && n0 + CF::NT <= nend && sbase_ld(ldc);   // tile inside C
+            double* Cw = C + (m0 + wm * CF::WTM) * ldc + n0 + wn * CF::WTN;
+            if (last) {
+                if (cin) load_c_fast<CF>(cv, Cw, ldc, coff, beta_eff != 0.0);
+                else     load_c<CF>(cv, C, ldc, m0, n0, M, nend, wm, wn, lane, beta_eff != 0.0);
+            }
+            bool rin;
+            const double* rorg;
+            b_plan(tr, rin, rorg);
+            // the slice store and the refill, one entry per MFMA step, so
+            // that the compute unit's memory pipeline works beside the MFMAs
+            mma_lds_pipe<CF, CF::KS / 4>(As, AB_LD, sl * CF::KS, cur, CF::B_LD, 0, acc, wm, wn, lane, [&](int kk) {
+#pragma unroll
+                for (int e = kk; e < SB::N; e += CF::KS / 4) {
+                    ready.store_elem(e, other, CF::B_LD, tid);
+                    load_b_elem(reload, tr, e, rin, rorg);
+                }
+            });
+            if (last) {
+                if (cin) store_c_fast<CF>(acc, alpha, beta_eff, cv, Cw, ldc, coff);
+                else     store_c_loaded<CF>(acc, alpha, beta_eff, cv, C, ldc, m0, n0, M, nend, wm, wn, lane);
                 zero_acc<CF>(acc);
             }
             __syncthreads();
         };
         static_assert(kRing == 2, "the unrolled steps below assume a ring of two");
+        // both steps of an iteration always run; an odd last step is peeled
+        int t = 0;
 #pragma unroll 1
-        for (int t = 0; t < total; t += 2) {
+        for (; t + 1 < total; t += 2) {
             step(t, sb[0], sb[1], Bs[0], Bs[1]);
-            if (t + 1 < total) step(t + 1, sb[1], sb[0], Bs[1], Bs[0]);
+            step(t + 1, sb[1], sb[0], Bs[1], Bs[0]);
         }
+        if (t < total) step(t, sb[0], sb[1], Bs[0], Bs[1]);
     }
 }
 
@@ -575,71 +722,144 @@ __global__ __launch_bounds__(CF::THREADS) void k_b2(int64_t M, int64_t N, int64_
     const int64_t mbeg = s.m_off + (int64_t)tm * mi * CF::MT;
     const int64_t mend = (mbeg + (int64_t)mi * CF::MT) < s.m_lim ? (mbeg + (int64_t)mi * CF::MT) : s.m_lim;
     const int64_t n0 = s.n_off + (int64_t)tn * CF::NT;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform, as in k_a2
     const int wm = wave / CF::WN, wn = wave % CF::WN;
     const int mtiles = (int)((mend - mbeg + CF::MT - 1) / CF::MT);
+    const uint32_t coff = (uint32_t)(((int64_t)(lane >> 4) * ldc + (lane & 15)) * 8);
+    if (mtiles <= 0) return;   // as in k_a2: every chunk has a step
 
-    Stage<CF::MT, CF::KS, CF::THREADS, TA> sa[kRing];
-    Stage<CF::KS, CF::NT, CF::THREADS, TB> sb;
+    using SA = Stage<CF::MT, CF::KS, CF::THREADS, TA>;
+    using SB = Stage<CF::KS, CF::NT, CF::THREADS, TB>;
+    SA sa[kRing];
     d4 acc[CF::BM][CF::BN];
+    const uint32_t aoff = SA::lane_offset(lda, tid), boff = SB::lane_offset(TILED ? 128 : ldb, tid);
+    // tile-major A: lane offset within a slice of 128 x 16 slabs (entry i
+    // of a lane is RPP rows further down the same slab)
+    const uint32_t aoff_slab = (uint32_t)((((tid % CF::KS) / 16) * 2048 + (tid / CF::KS) * 16 + tid % 16) * 8);
 
     for (int64_t kb = k_begin; kb < k_end; kb += KC) {
         const int64_t kbe = (kb + KC) < k_end ? (kb + KC) : k_end;
         const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
         const int total = mtiles * nsl;
-        __syncthreads();
-        // A slice t of this chunk (m-tile t / nsl, slice t % nsl) into st
-        auto load_a = [&](auto& st, int t) {
+        // element e of A slice t of this chunk (m-tile t / nsl, slice t % nsl)
+        auto load_a = [&](auto& st, int t, int e) {
             const int i = t / nsl, sl = t - (t / nsl) * nsl;
             const int64_t r0 = mbeg + (int64_t)i * CF::MT, kk = kb + (int64_t)sl * CF::KS;
             if constexpr (TILED) {
                 const double* P = A + ((r0 / 128) * lda + kk / 16) * 2048 + (r0 % 128) * 16;
-                st.load_slabs(P, 2048, lda * 16 - kk, tid);
+                st.load_slabs_elem(e, P, 2048, lda * 16 - kk, tid);
             } else {
-                st.load(A, lda, r0, kk, mend, kbe, tid);
+                st.load_elem(e, A, lda, r0, kk, mend, kbe, tid);
             }
         };
-#pragma unroll 1
-        for (int c = 0; c < nsl; ++c) {
-            if (TILED)   // 128-column panels of ldb rows, k-major; the block is columns n0 % 128 ..
-                sb.load(B + (n0 / 128) * ldb * 128 + n0 % 128, 128, kb + c * CF::KS, 0, ldb, CF::NT, tid);
-            else
-                sb.load(B, ldb, kb + c * CF::KS, n0, kbe, N, tid);
-            sb.store(Bs + c * CF::KS * CF::B_LD, CF::B_LD, tid);
+        // all of A slice t: the interior form when the slice lies inside A
+        // (as load_b_all in k_a2)
+        auto a_plan = [&](int t, bool& interior, const double*& origin) {
+            const int i = t / nsl, sl = t - (t / nsl) * nsl;
+            const int64_t r0 = mbeg + (int64_t)i * CF::MT, kk = kb + (int64_t)sl * CF::KS;
+            if constexpr (TILED) {
+                origin = A + ((r0 / 128) * lda + kk / 16) * 2048 + (r0 % 128) * 16;
+                interior = kk + CF::KS <= lda * 16;
+            } else {
+                origin = TA ? A + kk * lda + r0 : A + r0 * lda + kk;
+                interior = r0 + CF::MT <= mend && kk + CF::KS <= kbe && SA::fast_ld(lda);
+            }
+        };
+        auto load_a_elem = [&](auto& st, int t, int e, bool interior, const double* origin) {
+            if (interior) {
+                if constexpr (TILED) st.v[e] = load_sbase(origin + (int64_t)e * SA::RPP * 16, aoff_slab);   // RPP rows of 16 further
+                else                 st.load_elem_fast(e, origin, lda, aoff);
+            } else {
+                load_a(st, t, e);
+            }
+        };
+        auto load_a_all = [&](auto& st, int t) {
+            bool interior;
+            const double* origin;
+            a_plan(t, interior, origin);
+#pragma unroll
+            for (int e = 0; e < SA::N; ++e) load_a_elem(st, t, e, interior, origin);
+        };
+        // The chunk's B block and its first kRing A slices are all loaded
+        // into registers at once, then stored to LDS once the previous
+        // chunk's readers are done (as in k_a2).
+        SB sq[KC / CF::KS];
+#pragma unroll
+        for (int c = 0; c < KC / CF::KS; ++c) {
+            if (c >= nsl) break;
+            const int64_t kk = kb + (int64_t)c * CF::KS;
+            if (TILED) {   // 128-column panels of ldb rows, k-major; the block is columns n0 % 128 ..
+                const double* P = B + (n0 / 128) * ldb * 128 + n0 % 128;
+                if (kk + CF::KS <= ldb) {
+#pragma unroll
+                    for (int e = 0; e < SB::N; ++e) sq[c].load_elem_fast(e, P + kk * 128, 128, boff);
+                } else {
+                    sq[c].load(P, 128, kk, 0, ldb, CF::NT, tid);
+                }
+            } else if (kk + CF::KS <= kbe && n0 + CF::NT <= N && SB::fast_ld(ldb)) {
+#pragma unroll
+                for (int e = 0; e < SB::N; ++e)
+                    sq[c].load_elem_fast(e, TB ? B + n0 * ldb + kk : B + kk * ldb + n0, ldb, boff);
+            } else {
+                sq[c].load(B, ldb, kk, n0, kbe, N, tid);
+            }
         }
         // A slices kRing ahead through a ring of register sets (as the B
         // slices of k_a2)
-        if (total > 0) {
 #pragma unroll
-            for (int u = 0; u < kRing; ++u) load_a(sa[u], u < total ? u : total - 1);
-            sa[0].store(As[0], CF::A_LD, tid);
+        for (int u = 0; u < kRing; ++u) load_a_all(sa[u], u < total ? u : total - 1);
+        __syncthreads();  // previous chunk's readers of As / Bs are done
+#pragma unroll
+        for (int c = 0; c < KC / CF::KS; ++c) {
+            if (c >= nsl) break;
+            sq[c].store(Bs + c * CF::KS * CF::B_LD, CF::B_LD, tid);
         }
+        sa[0].store(As[0], CF::A_LD, tid);
         __syncthreads();
         zero_acc<CF>(acc);
         const double beta_eff = (kb == 0) ? beta : 1.0;
-        const int pf_sl = nsl > kPrefetchC ? nsl - kPrefetchC : 0;
         double cv[CF::BM][CF::BN][4];
+        // the steps of k_a2 with the roles of A and B exchanged
         auto step = [&](int t, auto& reload, auto& ready) {
             const int cur = t & 1;
             const int i = t / nsl, sl = t - i * nsl;
             const int64_t r0 = mbeg + (int64_t)i * CF::MT;
-            load_a(reload, t + kRing < total ? t + kRing : total - 1);
-            if (sl == pf_sl && beta_eff != 0.0) load_c<CF>(cv, C, ldc, r0, n0, mend, N, wm, wn, lane);
-            __builtin_amdgcn_sched_barrier(0);
-            mma_lds_pipe<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs, CF::B_LD, sl * CF::KS, acc, wm, wn, lane);
-            if (t + 1 < total) ready.store(As[cur ^ 1], CF::A_LD, tid);
-            if (sl == nsl - 1) {
-                store_c_loaded<CF>(acc, alpha, beta_eff, cv, C, ldc, r0, n0, mend, N, wm, wn, lane);
+            const bool last = sl == nsl - 1;
+            const int tr = t + kRing < total ? t + kRing : total - 1;
+            const bool cin = r0 + CF::MT <= mend && n0 + CF::NT <= N && sbase_ld(ldc);   // tile inside C
+            double* Cw = C + (r0 + wm * CF::WTM) * ldc + n0 + wn * CF::WTN;
+            if (last) {
+                if (cin) load_c_fast<CF>(cv, Cw, ldc, coff, beta_eff != 0.0);
+                else     load_c<CF>(cv, C, ldc, r0, n0, mend, N, wm, wn, lane, beta_eff != 0.0);
+            }
+            bool rin;
+            const double* rorg;
+            a_plan(tr, rin, rorg);
+            // as in k_a2: one slice entry stored and one refilled per MFMA step
+            mma_lds_pipe<CF, CF::KS / 4>(As[cur], CF::A_LD, 0, Bs, CF::B_LD, sl * CF::KS, acc, wm, wn, lane,
+                                         [&](int kq) {
+#pragma unroll
+                for (int e = kq; e < SA::N; e += CF::KS / 4) {
+                    ready.store_elem(e, As[cur ^ 1], CF::A_LD, tid);
+                    load_a_elem(reload, tr, e, rin, rorg);
+                }
+            });
+            if (last) {
+                if (cin) store_c_fast<CF>(acc, alpha, beta_eff, cv, Cw, ldc, coff);
+                else     store_c_loaded<CF>(acc, alpha, beta_eff, cv, C, ldc, r0, n0, mend, N, wm, wn, lane);
                 zero_acc<CF>(acc);
             }
             __syncthreads();
         };
         static_assert(kRing == 2, "the unrolled steps below assume a ring of two");
+        int t = 0;
 #pragma unroll 1
-        for (int t = 0; t < total; t += 2) {
+        for (; t + 1 < total; t += 2) {
             step(t, sa[0], sa[1]);
-            if (t + 1 < total) step(t + 1, sa[1], sa[0]);
+            step(t + 1, sa[1], sa[0]);
         }
+        if (t < total) step(t, sa[0], sa[1]);
     }
 }
 
