@@ -517,16 +517,71 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha, 
     regc_tile<CF, TA, TB>(M, N, k_begin, k_end, alpha, A, lda, B, ldb, beta, C, ldc, m0, n0, tm, tn, As, Bs);
 }
 
-// Depth of the register ring that streams the other operand's slices
-// through an LDS-resident kernel (a 32-deep slice is about 2 us of MFMAs).
-constexpr int kRing = 2;
+// ---------------------------------------------------------------------------
+// The A-resident kernel k_a2 loads its A block into LDS once per KC chunk and
+// then only reads it, so the workgroup synchronises twice per chunk and never
+// per slice.  B streams from the L2 (through the vector L1) straight into
+// registers, as the Goto loop nest streams its B micro-panels through the L1
+// (Sec. 5.2): each wave loads exactly the MFMA fragments it uses, one 32-deep
+// slice ahead in a ring of two register sets, one MFMA step's fragments per
+// step.  Without a barrier per slice the waves of a workgroup drift apart,
+// and a wave waiting for memory leaves the MFMA unit to the other wave of its
+// SIMD.  Each wave reads its B fragments itself, so every B element is read
+// from the L2 by the two waves that share it.
+
+// Fragments of a streamed operand for one wave and one slice: f[kk][x] is the
+// operand of MFMA step kk for 16-row (A) or 16-column (B) block x.
+template <int KSTEPS, int NX>
+struct Frag {
+    double f[KSTEPS][NX];
+};
+
+// acc += A(:, a_k0 : a_k0 + 4*KSTEPS) * B with A fragments read from LDS
+// (As[m][k], pitch a_ld; the reads of step kk + 1 are issued before the MFMAs
+// of step kk) and B fragments from registers.  between(kk) runs in step kk
+// before its MFMAs (the next slice's loads go there).
+template <class CF, int KSTEPS, class Between>
+__device__ __forceinline__ void mma_a_lds_b_reg(const double* __restrict__ As, int a_ld, int a_k0,
+                                                const double (&bf)[KSTEPS][CF::BN], d4 (&acc)[CF::BM][CF::BN],
+                                                int wm, int lane, Between&& between) {
+    const int li = lane & 15, lk = lane >> 4;
+    const double* ap = As + (wm * CF::WTM + li) * a_ld + a_k0 + lk;
+    double a[2][CF::BM];
+#pragma unroll
+    for (int i = 0; i < CF::BM; ++i) a[0][i] = ap[i * 16 * a_ld];
+#pragma unroll
+    for (int kk = 0; kk < KSTEPS; ++kk) {
+        const int cur = kk & 1;
+        if (kk + 1 < KSTEPS) {
+#pragma unroll
+            for (int i = 0; i < CF::BM; ++i) a[cur ^ 1][i] = ap[i * 16 * a_ld + (kk + 1) * 4];
+        }
+        between(kk);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < CF::BM; ++i)
+#pragma unroll
+            for (int j = 0; j < CF::BN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][i], bf[kk][j], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Where a wave's streamed slice lies: its origin, whether all of it is inside
+// the operand (then each fragment is a scalar base plus the lane offset), and
+// the coordinates of the origin for the predicated form.
+struct SlicePlan {
+    const double* origin;
+    bool interior;
+    int64_t k0, x0;
+};
 
 // ---------------------------------------------------------------------------
 // k_a2: granule = MT rows x (nj * NT) columns.  For each KC chunk of
 // [k_begin, k_end) the A block (MT x KC) is loaded into LDS once and reused for
-// every n-tile of the granule; B slices stream through two LDS buffers.  C is
-// read-modified-written once per chunk: beta applies to the chunk starting at
-// k = 0, later chunks accumulate.  With PACKED, B comes from a packed panel
+// every n-tile of the granule; the B slices stream into registers (above).  C
+// is read-modified-written once per chunk: beta applies to the chunk starting
+// at k = 0, later chunks accumulate.  With PACKED, B comes from a packed panel
 // laid out [n-tile][k][NT] (rows of NT doubles, zero-padded, ldb rows per
 // n-tile), whose origin is (pk0, pn0) in B's coordinates; n-tiles are
 // numbered from pn0.  With TILED, A is tile-major (128 x 16 slabs; MT divides
@@ -541,76 +596,64 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
     static_assert(!TILED || (CF::KS % 16 == 0 && KC % 16 == 0 && 128 % CF::MT == 0),
                   "tile-major slices start on slab boundaries and blocks sit inside 128-row panels");
     constexpr int AB_LD = KC + 1;
+    constexpr int KSTEPS = CF::KS / 4;
     __shared__ double As[CF::MT * AB_LD];
-    __shared__ double Bs[2][CF::KS * CF::B_LD];
     int tm, tn;
     decode_tile(s, blockIdx.x, tm, tn);
     const int64_t m0 = s.m_off + (int64_t)tm * CF::MT;
     const int64_t nbeg = s.n_off + (int64_t)tn * nj * CF::NT;
     const int64_t nend = (nbeg + (int64_t)nj * CF::NT) < s.n_lim ? (nbeg + (int64_t)nj * CF::NT) : s.n_lim;
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: wave-level addresses stay scalar
     const int wm = wave / CF::WN, wn = wave % CF::WN;
     const int ntiles = (int)((nend - nbeg + CF::NT - 1) / CF::NT);
     const uint32_t coff = (uint32_t)(((int64_t)(lane >> 4) * ldc + (lane & 15)) * 8);
-    // Below, every chunk has at least one step (total >= 1), so that no ring
-    // load or store is conditional (see the steps).
+    // every chunk below has at least one step, so no load is conditional
     if (ntiles <= 0) return;
 
-    using SB = Stage<CF::KS, CF::NT, CF::THREADS, PACKED ? false : TB>;
     using SA = Stage<CF::MT, CF::KS, CF::THREADS, TA>;
-    SB sb[kRing];
+    const uint32_t aoff = SA::lane_offset(lda, tid);
+    // B fragment (kk, x) of a wave's slice: k = 4 kk + lk, n = 16 x + li from
+    // the slice origin (column wn * WTN of its n-tile)
+    const int64_t ldbs = PACKED ? CF::NT : ldb;
+    const int64_t bks = TB ? 1 : ldbs, bxs = TB ? ldbs : 1;   // element strides along k and along n
+    const uint32_t blane = (uint32_t)(((int64_t)lk * bks + (int64_t)li * bxs) * 8);
+    Frag<KSTEPS, CF::BN> bq[2];
     d4 acc[CF::BM][CF::BN];
-    const int64_t ldbs = PACKED ? CF::NT : ldb;   // the B slices' leading dimension
-    const uint32_t boff = SB::lane_offset(ldbs, tid), aoff = SA::lane_offset(lda, tid);
 
     for (int64_t kb = k_begin; kb < k_end; kb += KC) {
         const int64_t kbe = (kb + KC) < k_end ? (kb + KC) : k_end;
         const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
         const int total = ntiles * nsl;
-        // element e of B slice t of this chunk (n-tile t / nsl, slice t % nsl)
-        auto load_b = [&](auto& st, int t, int e) {
+        auto b_plan = [&](int t) {
             const int j = t / nsl, sl = t - (t / nsl) * nsl;
+            SlicePlan p;
             if (PACKED) {
-                // panel row (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j);
+                // panel rows from (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j);
                 // ldb is the panel height (KC for a per-chunk pack, the padded
                 // k for a tile-major B); rows past it read as zero
-                const int64_t jt = (nbeg - pn0) / CF::NT + j;
-                const double* P = B + jt * ldb * CF::NT;
-                st.load_elem(e, P, CF::NT, (kb - pk0) + (int64_t)sl * CF::KS, 0, ldb, CF::NT, tid);
-            } else {
-                st.load_elem(e, B, ldb, kb + (int64_t)sl * CF::KS, nbeg + (int64_t)j * CF::NT, kbe, nend, tid);
-            }
-        };
-        // all of B slice t: the interior form when the slice lies inside B
-        // (both forms issue the same loads, so the branch does not disturb
-        // the compiler's count of loads in flight)
-        auto b_plan = [&](int t, bool& interior, const double*& origin) {
-            const int j = t / nsl, sl = t - (t / nsl) * nsl;
-            if (PACKED) {
                 const int64_t row0 = (kb - pk0) + (int64_t)sl * CF::KS;
-                interior = row0 + CF::KS <= ldb;
-                origin = B + ((nbeg - pn0) / CF::NT + j) * ldb * CF::NT + row0 * CF::NT;
+                p.origin = B + ((nbeg - pn0) / CF::NT + j) * ldb * CF::NT + row0 * CF::NT + wn * CF::WTN;
+                p.interior = row0 + CF::KS <= ldb;
+                p.k0 = row0;
+                p.x0 = 0;
             } else {
-                const int64_t row0 = kb + (int64_t)sl * CF::KS, col0 = nbeg + (int64_t)j * CF::NT;
-                interior = row0 + CF::KS <= kbe && col0 + CF::NT <= nend && SB::fast_ld(ldb);
-                origin = TB ? B + col0 * ldb + row0 : B + row0 * ldb + col0;
+                const int64_t k0 = kb + (int64_t)sl * CF::KS, c0 = nbeg + (int64_t)j * CF::NT + wn * CF::WTN;
+                p.origin = TB ? B + c0 * ldb + k0 : B + k0 * ldb + c0;
+                p.interior = k0 + CF::KS <= kbe && c0 + CF::WTN <= nend && sbase_ld(ldb);
+                p.k0 = k0;
+                p.x0 = c0;
             }
+            return p;
         };
-        auto load_b_elem = [&](auto& st, int t, int e, bool interior, const double* origin) {
-            if (interior) st.load_elem_fast(e, origin, ldbs, boff);
-            else          load_b(st, t, e);
+        auto b_load = [&](const SlicePlan& p, int kk, int x) -> double {
+            if (p.interior) return load_sbase(p.origin + (int64_t)(4 * kk) * bks + (int64_t)(16 * x) * bxs, blane);
+            const int64_t kr = 4 * kk + lk, nc = 16 * x + li;
+            const bool ok = PACKED ? p.k0 + kr < ldb : (p.k0 + kr < kbe && p.x0 + nc < nend);
+            return *(ok ? p.origin + kr * bks + nc * bxs : &kZeroEntry);
         };
-        auto load_b_all = [&](auto& st, int t) {
-            bool interior;
-            const double* origin;
-            b_plan(t, interior, origin);
-#pragma unroll
-            for (int e = 0; e < SB::N; ++e) load_b_elem(st, t, e, interior, origin);
-        };
-        // The chunk's A block and its first kRing B slices are all loaded
-        // into registers at once (one memory latency per chunk), then
-        // stored to LDS once the previous chunk's readers are done.
+        // The chunk's A block is loaded into registers at once and stored to
+        // LDS once the previous chunk's readers are done.
         SA sq[KC / CF::KS];
 #pragma unroll
         for (int c = 0; c < KC / CF::KS; ++c) {
@@ -631,79 +674,77 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
                 sq[c].load(A, lda, m0, kk, M, kbe, tid);
             }
         }
-#pragma unroll
-        for (int u = 0; u < kRing; ++u) load_b_all(sb[u], u < total ? u : total - 1);
-        __syncthreads();  // previous chunk's readers of As / Bs are done
+        __syncthreads();  // the previous chunk's readers of As are done
 #pragma unroll
         for (int c = 0; c < KC / CF::KS; ++c) {
             if (c >= nsl) break;
             sq[c].store(As + c * CF::KS, AB_LD, tid);
         }
-        // B slices kRing ahead through a ring of register sets: slice t + u
-        // waits in set (t + u) % kRing (the loop runs kRing steps per
-        // iteration, so every set index is a constant); the prefetch index
-        // is clamped to the last slice rather than skipped, which keeps the
-        // load where it is.  A 32-deep slice is about 2 us of MFMAs.
-        sb[0].store(Bs[0], CF::B_LD, tid);
+        {   // the first B slice, once the A block's registers are free
+            const SlicePlan p0 = b_plan(0);
+#pragma unroll
+            for (int kk = 0; kk < KSTEPS; ++kk)
+#pragma unroll
+                for (int x = 0; x < CF::BN; ++x) bq[0].f[kk][x] = b_load(p0, kk, x);
+        }
         __syncthreads();
         zero_acc<CF>(acc);
         const double beta_eff = (kb == 0) ? beta : 1.0;
         double cv[CF::BM][CF::BN][4];
-        // step t: slice t is in Bs[t & 1] and its register set is free again
-        // (stored in step t - 1).  A tile's last step first loads the tile's
-        // C values (the epilogue's wait for them then leaves the refill in
-        // flight).  Every step refills the free set with slice t + kRing
-        // (clamped to the last slice), computes, and stores slice t + 1 into
-        // the other buffer; on the chunk's last step that is a clamped slice
-        // nobody reads, in a buffer the barrier of step t - 1 released.  No
-        // ring load or store is conditional: the compiler counts the loads in
-        // flight across steps only when every path issues the same ones.
-        auto step = [&](int t, auto& reload, auto& ready, double* cur, double* other) {
+        // Step t computes slice t (n-tile t / nsl, slice t % nsl) from cur
+        // and loads slice t + 1 (clamped to the last) into nxt, spread over
+        // its MFMA steps.  A tile's last step is a copy of its own (LAST):
+        // it first loads the tile's C values and ends with the epilogue.
+        // Every path of a step issues the same loads, so the compiler can
+        // count those in flight and wait only for the fragments an MFMA uses.
+        auto step = [&](auto last_tag, int t, auto& cur, auto& nxt) {
+            constexpr bool LAST = decltype(last_tag)::value;
             const int j = t / nsl, sl = t - j * nsl;
             const int64_t n0 = nbeg + (int64_t)j * CF::NT;
-            const bool last = sl == nsl - 1;
-            const int tr = t + kRing < total ? t + kRing : total - 1;
             const bool cin = m0 + CF::MT <= M && n0 + CF::NT <= nend && sbase_ld(ldc);   // tile inside C
             double* Cw = C + (m0 + wm * CF::WTM) * ldc + n0 + wn * CF::WTN;
-            if (last) {
+            if constexpr (LAST) {
                 if (cin) load_c_fast<CF>(cv, Cw, ldc, coff, beta_eff != 0.0);
                 else     load_c<CF>(cv, C, ldc, m0, n0, M, nend, wm, wn, lane, beta_eff != 0.0);
             }
-            bool rin;
-            const double* rorg;
-            b_plan(tr, rin, rorg);
-            // the slice store and the refill, one entry per MFMA step, so
-            // that the compute unit's memory pipeline works beside the MFMAs
-            mma_lds_pipe<CF, CF::KS / 4>(As, AB_LD, sl * CF::KS, cur, CF::B_LD, 0, acc, wm, wn, lane, [&](int kk) {
+            const SlicePlan p = b_plan(t + 1 < total ? t + 1 : total - 1);
+            mma_a_lds_b_reg<CF, KSTEPS>(As, AB_LD, sl * CF::KS, cur.f, acc, wm, lane, [&](int kk) {
 #pragma unroll
-                for (int e = kk; e < SB::N; e += CF::KS / 4) {
-                    ready.store_elem(e, other, CF::B_LD, tid);
-                    load_b_elem(reload, tr, e, rin, rorg);
-                }
+                for (int x = 0; x < CF::BN; ++x) nxt.f[kk][x] = b_load(p, kk, x);
             });
-            if (last) {
+            if constexpr (LAST) {
                 if (cin) store_c_fast<CF>(acc, alpha, beta_eff, cv, Cw, ldc, coff);
                 else     store_c_loaded<CF>(acc, alpha, beta_eff, cv, C, ldc, m0, n0, M, nend, wm, wn, lane);
                 zero_acc<CF>(acc);
             }
-            __syncthreads();
         };
-        static_assert(kRing == 2, "the unrolled steps below assume a ring of two");
-        // both steps of an iteration always run; an odd last step is peeled
+        auto any_step = [&](int t, auto& cur, auto& nxt) {
+            if (t % nsl == nsl - 1) step(std::true_type{}, t, cur, nxt);
+            else                    step(std::false_type{}, t, cur, nxt);
+        };
+        // two steps per iteration (the ring's register sets stay fixed); an
+        // odd last step is peeled
         int t = 0;
 #pragma unroll 1
         for (; t + 1 < total; t += 2) {
-            step(t, sb[0], sb[1], Bs[0], Bs[1]);
-            step(t + 1, sb[1], sb[0], Bs[1], Bs[0]);
+            any_step(t, bq[0], bq[1]);
+            any_step(t + 1, bq[1], bq[0]);
         }
-        if (t < total) step(t, sb[0], sb[1], Bs[0], Bs[1]);
+        if (t < total) any_step(t, bq[0], bq[1]);
     }
 }
 
+// Depth of the register ring that streams k_b2's A slices (a 32-deep slice
+// is about 2 us of MFMAs).
+constexpr int kRing = 2;
+
 // ---------------------------------------------------------------------------
 // k_b2: mirror of k_a2.  Granule = (mi * MT) rows x NT columns; for each KC
-// chunk the B block (KC x NT) is resident in LDS and reused for every m-tile;
-// A slices stream through two LDS buffers.  With TILED, A is tile-major
+// chunk the B block (KC x NT) is resident in LDS and reused for every m-tile.
+// Unlike k_a2, the A slices stream through two LDS buffers (a register ring
+// of two sets, one slice entry stored and one refilled per MFMA step): each
+// wave reading its own A fragments from memory would read 16 rows of 32
+// bytes per load, which measured slower.  With TILED, A is tile-major
 // (128 x 16 slabs, lda = slabs per row panel) and B comes from tile-major
 // 128-column panels (ldb = the padded k; NT divides 128), both zero beyond
 // the matrix.
