@@ -752,13 +752,16 @@ __device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^
 // the register set since the previous step) into the other buffer (last
 // read in step t - 1, before the previous barrier), issue the loads of step
 // t + 2 into the freed registers, run window 1, synchronise.  The stores
-// overlap window 1's MFMAs; each load has a whole step to land.
+// overlap window 1's MFMAs; each load has a whole step to land.  On the last
+// step the store writes a repeat of it that nobody reads: kept
+// unconditional, so that the compiler sees the same loads and stores on
+// every path and waits only for the loads each store needs.
 #define MOMMS_I8_STEP(t_, buf_) MOMMS_I8_STEP_G(t_, buf_, MOMMS_I8_GLOAD)
 #define MOMMS_I8_STEP_G(t_, buf_, GLOAD_)                                                        \
     do {                                                                                         \
         MOMMS_I8_WINDOW(buf_, 0);                                                                \
         __builtin_amdgcn_sched_barrier(0);                                                       \
-        if ((t_) + 1 < total) MOMMS_I8_LSTORE((buf_) ^ 1, g);                                    \
+        MOMMS_I8_LSTORE((buf_) ^ 1, g);                                                          \
         __builtin_amdgcn_sched_barrier(0);                                                       \
         GLOAD_(g, (t_) + 2 < last ? (t_) + 2 : last);                                            \
         __builtin_amdgcn_sched_barrier(0);                                                       \
@@ -901,27 +904,46 @@ struct CrtOut {
     float ipf[kMaxModuli];
 };
 
+// *(base + off bytes) as 16 bytes for a wave-uniform base and a 32-bit lane
+// offset: a global load with a scalar base address and a vector offset, no
+// per-lane 64-bit address arithmetic (both operands opaque, or the compiler
+// folds the offset in once and steps 64-bit vector addresses).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
+typedef __attribute__((address_space(1))) const uint8_t gbyte_c;
+__device__ __forceinline__ uint4 load16_sbase(const int8_t* base, uint32_t off) {
+    gbyte_c* b = (gbyte_c*)reinterpret_cast<const uint8_t*>(base);
+    asm volatile("" : "+s"(b), "+v"(off));
+    const u32x4 v = *reinterpret_cast<gu32x4*>(b + off);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// The loads of the next step to fetch (item f_it, k-step f_s), then the
+// fetch state advances unless it is at the last step (the kernel fetches
+// steps 0, 1, 2, ... in order and repeats the last).  An item's bases and k
+// stagger are computed once per item (f_item), not per step.
 #define MOMMS_CRT_GLOAD(R, t_)                                                                   \
     do {                                                                                         \
-        const int it_ = (t_) / nks;                                                              \
-        const int s_ = (t_) - it_ * nks;                                                         \
-        const int j_ = (int)blockIdx.x + it_ * G;                                                \
-        const int l_ = j_ / tiles;                                                               \
-        int tm_, tn_;                                                                            \
-        decode_tile(sc, j_ - l_ * tiles, tm_, tn_);                                              \
-        int kq = s_ + ((tm_ + tn_) & 7) % nks;                                                   \
+        int kq = f_s + f_shift;                                                                  \
         if (kq >= nks) kq -= nks;                                                                \
-        const int64_t kk = (int64_t)kq * kI8KS + gcol;                                           \
-        const int8_t* pa = SA + (int64_t)l_ * sa_stride + (sc.m_off + (int64_t)tm_ * kI8MT + grow) * kp + kk; \
-        const int8_t* pb = SB + (int64_t)l_ * sb_stride + (sc.n_off + (int64_t)tn_ * kI8NT + grow) * kp + kk; \
-        R##0 = *reinterpret_cast<const uint4*>(pa);                                              \
-        R##1 = *reinterpret_cast<const uint4*>(pa + 64 * kp);                                    \
-        R##2 = *reinterpret_cast<const uint4*>(pa + 128 * kp);                                   \
-        R##3 = *reinterpret_cast<const uint4*>(pa + 192 * kp);                                   \
-        R##4 = *reinterpret_cast<const uint4*>(pb);                                              \
-        R##5 = *reinterpret_cast<const uint4*>(pb + 64 * kp);                                    \
-        R##6 = *reinterpret_cast<const uint4*>(pb + 128 * kp);                                   \
-        R##7 = *reinterpret_cast<const uint4*>(pb + 192 * kp);                                   \
+        const int8_t* pa = f_pa + (int64_t)kq * kI8KS;                                           \
+        const int8_t* pb = f_pb + (int64_t)kq * kI8KS;                                           \
+        R##0 = load16_sbase(pa, goff);                                                           \
+        R##1 = load16_sbase(pa + 64 * kp, goff);                                                 \
+        R##2 = load16_sbase(pa + 128 * kp, goff);                                                \
+        R##3 = load16_sbase(pa + 192 * kp, goff);                                                \
+        R##4 = load16_sbase(pb, goff);                                                           \
+        R##5 = load16_sbase(pb + 64 * kp, goff);                                                 \
+        R##6 = load16_sbase(pb + 128 * kp, goff);                                                \
+        R##7 = load16_sbase(pb + 192 * kp, goff);                                                \
+        if (f_n < last) {                                                                        \
+            ++f_n;                                                                               \
+            if (++f_s == nks) {                                                                  \
+                f_s = 0;                                                                         \
+                ++f_it;                                                                          \
+                f_item();                                                                        \
+            }                                                                                    \
+        }                                                                                        \
     } while (0)
 
 __device__ __forceinline__ uint32_t residue_u8(int a, int p, int c16, float ipf) {
@@ -955,6 +977,21 @@ __global__ __launch_bounds__(512) void k_crt_gemm(int64_t M, int64_t N, int64_t 
     const int total = n_it * nks;
     const int last = total - 1;
     uint4 g0, g1, g2, g3, g4, g5, g6, g7;
+    // fetch state (see MOMMS_CRT_GLOAD): this thread's 16-byte chunk of row
+    // grow at a 32-bit offset from the item's scalar bases
+    const uint32_t goff = (uint32_t)((int64_t)grow * kp + gcol);
+    int f_it = 0, f_s = 0, f_n = 0, f_shift = 0;
+    const int8_t *f_pa = SA, *f_pb = SB;
+    auto f_item = [&]() {
+        const int j_ = (int)blockIdx.x + f_it * G;
+        const int l_ = j_ / tiles;
+        int tm_, tn_;
+        decode_tile(sc, j_ - l_ * tiles, tm_, tn_);
+        f_shift = ((tm_ + tn_) & 7) % nks;
+        f_pa = SA + (int64_t)l_ * sa_stride + (sc.m_off + (int64_t)tm_ * kI8MT) * kp;
+        f_pb = SB + (int64_t)l_ * sb_stride + (sc.n_off + (int64_t)tn_ * kI8NT) * kp;
+    };
+    f_item();
 
     MOMMS_CRT_GLOAD(g, 0);
     MOMMS_I8_LSTORE(0, g);
