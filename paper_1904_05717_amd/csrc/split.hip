@@ -729,7 +729,9 @@ __device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^
     } while (0)
 
 // One 64-deep window of the current stage: 4 B fragments stay, the 8 A
-// fragments stream through in pairs (fewer live registers), 32 MFMAs.
+// fragments stream through in pairs, 32 MFMAs.  The next pair is read from
+// LDS before the current pair's MFMAs are issued, so a pair's read latency
+// is covered by the MFMAs of the pair before it.
 #define MOMMS_I8_WINDOW(buf_, w_)                                                                \
     do {                                                                                         \
         const int8_t* la = As + (buf_) * i8::kStageA + (w_) * i8::kWinA;                         \
@@ -737,13 +739,20 @@ __device__ __forceinline__ int lds_off(int r, int q) { return r * 64 + 16 * (q ^
         i4 bf[4];                                                                                \
         _Pragma("unroll") for (int j = 0; j < 4; ++j)                                            \
             bf[j] = *reinterpret_cast<const i4*>(lb + fb_off[j]);                                \
+        i4 ap[2][2];                                                                             \
+        ap[0][0] = *reinterpret_cast<const i4*>(la + fa_off[0]);                                 \
+        ap[0][1] = *reinterpret_cast<const i4*>(la + fa_off[1]);                                 \
         _Pragma("unroll") for (int i2 = 0; i2 < 8; i2 += 2) {                                    \
-            const i4 a0 = *reinterpret_cast<const i4*>(la + fa_off[i2]);                         \
-            const i4 a1 = *reinterpret_cast<const i4*>(la + fa_off[i2 + 1]);                     \
+            const int c_ = (i2 >> 1) & 1;                                                        \
+            if (i2 + 2 < 8) {                                                                    \
+                ap[c_ ^ 1][0] = *reinterpret_cast<const i4*>(la + fa_off[i2 + 2]);               \
+                ap[c_ ^ 1][1] = *reinterpret_cast<const i4*>(la + fa_off[i2 + 3]);               \
+            }                                                                                    \
+            __builtin_amdgcn_sched_barrier(0);                                                   \
             _Pragma("unroll") for (int j = 0; j < 4; ++j)                                        \
-                acc[i2][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, bf[j], acc[i2][j], 0, 0, 0); \
+                acc[i2][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[c_][0], bf[j], acc[i2][j], 0, 0, 0); \
             _Pragma("unroll") for (int j = 0; j < 4; ++j)                                        \
-                acc[i2 + 1][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, bf[j], acc[i2 + 1][j], 0, 0, 0); \
+                acc[i2 + 1][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[c_][1], bf[j], acc[i2 + 1][j], 0, 0, 0); \
             __builtin_amdgcn_sched_barrier(0);                                                   \
         }                                                                                        \
     } while (0)
