@@ -251,8 +251,9 @@ __global__ __launch_bounds__(256) void k_residues(const double* __restrict__ P, 
                                                   int8_t* __restrict__ out, int64_t Rp, int64_t Cp) {
     // 32 x 128 tiles: each row of a plane gets whole 128-byte lines.  A
     // stored row (TRANSPOSED = false) is already contiguous along c, so a
-    // thread reads its 16 values directly; the transposed side goes through
-    // LDS.
+    // thread reads its 16 values directly (staging them through LDS with
+    // lane-contiguous loads measured 13% slower); the transposed side goes
+    // through LDS.
     __shared__ double tile[TRANSPOSED ? 32 : 1][129];
     const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 128;
     const int tid = threadIdx.x;
@@ -368,9 +369,17 @@ __global__ __launch_bounds__(256) void k_crt_combine(int64_t M, int64_t N, const
 #pragma unroll
             for (int c = 0; c < 7; ++c) acc[r][c] = 0u;
         }
-#pragma unroll 4
-        for (int l = 0; l < cp.n; ++l) {
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(Rs + l * plane + (q4 * ldr + j) * 4);
+        // every plane's word in flight at once (planes past cp.n re-read the
+        // last one and are not used)
+        uint32_t wl[kMaxModuli];
+        const uint8_t* rp = Rs + (q4 * ldr + j) * 4;
+#pragma unroll
+        for (int l = 0; l < kMaxModuli; ++l)
+            wl[l] = *reinterpret_cast<const uint32_t*>(rp + (int64_t)(l < cp.n ? l : cp.n - 1) * plane);
+#pragma unroll
+        for (int l = 0; l < kMaxModuli; ++l) {
+            if (l >= cp.n) break;
+            const uint32_t w = wl[l];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint32_t x = (w >> (8 * r)) & 0xffu;
