@@ -223,8 +223,9 @@ int momms_balanced_block(double M, double beta_b, double beta_c, double *mc, dou
 /* The planner's level-2 (LDS) block solver (Sec. 2.4 balance within the
  * Sec. 4.1 capacity): for a fast memory of lds_bytes holding the resident
  * block (row pitch kc + 1 doubles) plus two streamed k-slices of
- * slice x (tile_other + 2) doubles, the block (rows a multiple of 64, kc a
- * multiple of 64) with the most flops per unit of streamed cost, the streamed
+ * slice x (tile_other + 2) doubles (none when tile_other is 0: the streamed
+ * panel goes straight to registers), the block (rows a multiple of 64, kc a
+ * multiple of slice) with the most flops per unit of streamed cost, the streamed
  * panel costing beta_stream and C beta_c per element; ties go to the block
  * nearer the continuous optimum (momms_balanced_block), then to fewer rows.
  * The LDS-resident kernels are built for its answer on gfx950.  Returns 0,

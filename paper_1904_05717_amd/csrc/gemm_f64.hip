@@ -93,7 +93,7 @@ static void launch_regc(const Args& a, int64_t k0, int64_t k1, double beta, cons
 template <bool TA, bool TB, bool PK>
 static void launch_a2_t(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, const double* Bsrc,
                         int64_t ldb, int64_t pk0, int64_t pn0) {
-    hipLaunchKernelGGL((k_a2<CfgA, kKC, TA, TB, PK>), dim3(grid_of(s)), dim3(CfgA::THREADS), 0, a.st, a.M, a.N, k0,
+    hipLaunchKernelGGL((k_a2<CfgA, kKCa, TA, TB, PK>), dim3(grid_of(s)), dim3(CfgA::THREADS), 0, a.st, a.M, a.N, k0,
                        k1, a.alpha, a.A, a.lda, Bsrc, ldb, a.beta, a.C, a.ldc, s, nj, pk0, pn0);
 }
 
@@ -102,8 +102,8 @@ static void launch_a2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int
                       int64_t pk0, int64_t pn0) {
     if (grid_of(s) <= 0) return;
     if (packed) {
-        if (!a.ta) launch_a2_t<false, false, true>(a, k0, k1, s, nj, packed, kKC, pk0, pn0);
-        else launch_a2_t<true, false, true>(a, k0, k1, s, nj, packed, kKC, pk0, pn0);
+        if (!a.ta) launch_a2_t<false, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0);
+        else launch_a2_t<true, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0);
         return;
     }
     if (!a.ta && !a.tb) launch_a2_t<false, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
@@ -128,15 +128,15 @@ static void launch_b2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int
 
 static void launch_pack_b(const Args& a, int64_t pk0, int64_t pn0, int64_t ncw, double* P) {
     const int ntiles = (int)cdiv(ncw, CfgA::NT);
-    const int64_t total = (int64_t)ntiles * kKC * CfgA::NT;
+    const int64_t total = (int64_t)ntiles * kKCa * CfgA::NT;
     int grid = (int)cdiv(total, 256);
     if (grid > 4 * kCUs * 8) grid = 4 * kCUs * 8;
     if (a.tb)
         hipLaunchKernelGGL((k_pack_b<CfgA::NT, true>), dim3(grid), dim3(256), 0, a.st, a.B, a.ldb, a.K, a.N, pk0, pn0,
-                           (int)kKC, ntiles, P);
+                           (int)kKCa, ntiles, P);
     else
         hipLaunchKernelGGL((k_pack_b<CfgA::NT, false>), dim3(grid), dim3(256), 0, a.st, a.B, a.ldb, a.K, a.N, pk0,
-                           pn0, (int)kKC, ntiles, P);
+                           pn0, (int)kKCa, ntiles, P);
 }
 
 // Runs the loop nest of plan p.  Returns 0 or a hipError_t.
@@ -274,7 +274,7 @@ static int check_args(int transA, int transB, int64_t m, int64_t n, int64_t k, d
 // device memory: its device address is taken once per device with that device
 // current, and only that address is passed to kernels.
 constexpr size_t kStaticScratchBytes = (size_t)4 << 20;   // 4 MiB
-static_assert((size_t)kKC * kGotoNc * sizeof(double) <= kStaticScratchBytes, "Goto's panel fits the scratch");
+static_assert((size_t)kKCa * kGotoNc * sizeof(double) <= kStaticScratchBytes, "Goto's panel fits the scratch");
 static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
 constexpr int kMaxDevices = 64;
 static std::mutex g_scratch_mu;

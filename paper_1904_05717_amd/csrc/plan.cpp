@@ -9,9 +9,11 @@
 //            (512 KiB/CU) is larger than the LDS (160 KiB/CU).
 //   level 2: LDS.  The resident block is sized by lds_block(): the Sec. 2.4
 //            balance between the streamed panel (from the L2) and C (from
-//            HBM, read and written), within the Sec. 4.1 capacity (block plus
-//            two 32-deep streamed slices in 160 KiB), on the MFMA wave grid:
-//            a 64 x 160 A block (or 160 x 64 B block), 80 KiB.
+//            HBM, read and written), within the Sec. 4.1 capacity, on the
+//            MFMA wave grid.  The A-resident kernel streams B through
+//            registers, so its block has the 160 KiB alone: 64 x 288 (144
+//            KiB).  The B-resident kernel keeps two 32-deep A slices beside
+//            its block: 160 x 64 (80 KiB).
 //   level 3: one XCD's 4 MiB L2.  A 512 x 512 resident block (2 MiB) leaves
 //            half the L2 for the guest and streamed panels (Sec. 4.1).
 //   level 4: the 256 MiB MALL.  A 4096 x 4096 C block (128 MiB) leaves half.
@@ -43,7 +45,10 @@ static inline int regc_tile(int64_t m, int64_t n) {
 // sqrt(beta_c / beta_stream M) (momms_balanced_block).  The kernels need rows
 // a multiple of 64 (two rows of 32-row waves) and kc a multiple of the slice
 // depth; the block plus two streamed k-slices of slice x (tile_other + 2)
-// must fit lds_doubles with the block's row pitch kc + 1.  The slice depth
+// must fit lds_doubles with the block's row pitch kc + 1.  tile_other = 0
+// means the streamed panel does not pass through LDS at all (the A-resident
+// kernel reads its B fragments straight into registers), so the block has
+// the whole of it.  The slice depth
 // is the kernels' choice (32: enough MFMAs between two barriers), made before
 // the block is sized.  Among those blocks the one
 // with the most flops per unit cost wins; ties go to the one nearer the
@@ -51,7 +56,7 @@ static inline int regc_tile(int64_t m, int64_t n) {
 // kernel is the mirror (rows = block columns).
 void lds_block(double lds_doubles, int slice, int tile_other, double beta_stream, double beta_c, int* rows,
                int* kc) {
-    const double stream = 2.0 * slice * (tile_other + 2);
+    const double stream = tile_other > 0 ? 2.0 * slice * (tile_other + 2) : 0.0;
     const double M = lds_doubles - stream;
     const double ratio_opt = beta_c / beta_stream;   // kc / rows at the optimum
     int best_r = 0, best_k = 0;
@@ -84,9 +89,9 @@ constexpr double kBetaStream = 1.0, kBetaC = 2.0 * 39.3 / 8.0;
 static bool lds_blocks_match() {
     static const bool ok = [] {
         int ra = 0, ka = 0, rb = 0, kb = 0;
-        lds_block(kLdsDoubles, kKSlds, kNTa, kBetaStream, kBetaC, &ra, &ka);   // A block, B slices of kNTa
+        lds_block(kLdsDoubles, kKSlds, 0, kBetaStream, kBetaC, &ra, &ka);      // A block alone in LDS
         lds_block(kLdsDoubles, kKSlds, kMTb, kBetaStream, kBetaC, &rb, &kb);   // B block, A slices of kMTb
-        return ra == kMCa && ka == kKC && rb == kNCb && kb == kKC;
+        return ra == kMCa && ka == kKCa && rb == kNCb && kb == kKC;
     }();
     return ok;
 }
@@ -166,7 +171,7 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             p->mt = kMCa;
             p->nt = kNTa;
             p->ks = kKSlds;
-            p->kc = kKC;
+            p->kc = kKCa;
             p->nc = kGotoNc;
             p->nj = tiles_per_wg(cdiv(m, p->mt), cdiv(n < p->nc ? n : p->nc, p->nt));
             p->k_range = p->kc < k ? p->kc : k;
@@ -180,13 +185,13 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
         case MOMMS_B3A2C0: {
             // n by nc3 -> k by kc3 (B block in one XCD's L2) -> m by 64 (A
             // block in LDS) -> k by kc -> n by 128.  nc3 = nj tiles (at most
-            // 512: a 480 x 512 B block is about half the L2).
+            // 512: a 288 x 512 B block is 1.2 MiB of the 4 MiB L2).
             p->kernel = 1;
             p->mt = kMCa;
             p->nt = kNTa;
             p->ks = kKSlds;
-            p->kc = kKC;
-            p->kc3 = 3 * kKC;   // whole LDS blocks: a ragged last kc would cost a C pass of its own
+            p->kc = kKCa;
+            p->kc3 = kKCa;      // one A block per B block: three (864 x 512) would not fit half the L2
             p->nj = tiles_per_wg(cdiv(m, p->mt), cdiv(n, p->nt));
             p->nc3 = (int64_t)p->nj * p->nt;
             p->xcd_aware = 1;
@@ -205,7 +210,7 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             p->nt = kNCb;
             p->ks = kKSlds;
             p->kc = kKC;
-            p->kc3 = 3 * kKC;   // whole LDS blocks, as in B3A2C0
+            p->kc3 = 3 * kKC;   // whole LDS blocks: a ragged last kc would cost a C pass of its own
             p->mi = tiles_per_wg(cdiv(n, p->nt), cdiv(m, p->mt));
             p->mc3 = (int64_t)p->mi * p->mt;
             p->xcd_aware = 1;
@@ -226,7 +231,7 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             p->mt = kMCa;
             p->nt = kNTa;
             p->ks = kKSlds;
-            p->kc = kKC;
+            p->kc = kKCa;
             p->nj = 1;
             p->xcd_aware = 1;
             p->group_m = (int)(cdiv(m, p->mt) < 4 ? cdiv(m, p->mt) : 4);
@@ -243,7 +248,7 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             p->mt = kMCa;
             p->nt = kNTa;
             p->ks = kKSlds;
-            p->kc = kKC;
+            p->kc = kKCa;
             p->mc4 = p->nc4 = 4096;
             p->nj = tiles_per_wg(cdiv(m < p->mc4 ? m : p->mc4, p->mt), cdiv(n < p->nc4 ? n : p->nc4, p->nt));
             p->k_range = p->kc < k ? p->kc : k;
@@ -265,7 +270,7 @@ size_t workspace_bytes(int member, int64_t m, int64_t n, int64_t k) {
     (void)k;
     if (member != MOMMS_A2C0) return 0;
     const int64_t nc = n < kGotoNc ? n : kGotoNc;
-    return (size_t)(kKC * cdiv(nc, kNTa) * kNTa) * sizeof(double);
+    return (size_t)(kKCa * cdiv(nc, kNTa) * kNTa) * sizeof(double);
 }
 
 // Measured table: shape buckets (rounded log2 of m, n, k) whose best member
@@ -385,7 +390,7 @@ int momms_lds_block(double lds_bytes, int slice, int tile_other, double beta_str
                     int* kc) {
     if (!(lds_bytes > 0) || !std::isfinite(lds_bytes)) return -1;
     if (slice < 1) return -2;
-    if (tile_other < 1) return -3;
+    if (tile_other < 0) return -3;
     if (!(beta_stream > 0) || !std::isfinite(beta_stream)) return -4;
     if (!(beta_c > 0) || !std::isfinite(beta_c)) return -5;
     if (!rows) return -6;

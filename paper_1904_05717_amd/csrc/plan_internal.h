@@ -9,15 +9,18 @@ namespace momms {
 
 constexpr int kCUs = 256;              // MI355X: 8 XCDs x 32 CUs
 constexpr double kXcdsH = 8.0;         // XCD count as a double for the model
-// LDS-resident blocks (level 2): A block kMCa x kKC for the A-resident
+// LDS-resident blocks (level 2): A block kMCa x kKCa for the A-resident
 // kernel, B block kKC x kNCb for the B-resident kernel; the C tiles they
 // update are kMCa x kNTa and kMTb x kNCb.  lds_block() derives these from the
-// Sec. 2.4 balance and the Sec. 4.1 capacity.
+// Sec. 2.4 balance and the Sec. 4.1 capacity: the A-resident kernel streams
+// its B slices through registers, so its block has the LDS to itself; the
+// B-resident kernel keeps two A slices beside its block.
 constexpr int kKSlds = 32;             // k depth of a streamed slice of the LDS-resident kernels
-constexpr int64_t kKC = 160;           // k depth of an LDS-resident block
+constexpr int64_t kKCa = 288;          // k depth of the A-resident block
+constexpr int64_t kKC = 160;           // k depth of the B-resident block
 constexpr int kMCa = 64, kNTa = 128;   // A-resident kernel: block rows, C tile columns
 constexpr int kMTb = 128, kNCb = 64;   // B-resident kernel: C tile rows, block columns
-constexpr int64_t kGotoNc = 2048;      // Goto's n_c: its packed k_c x n_c panel is 2.5 MiB
+constexpr int64_t kGotoNc = 1024;      // Goto's n_c: its packed k_c x n_c panel is 2.25 MiB, about half an XCD's L2
 constexpr int kWGsPerXcd128 = 64;      // 128x128 register tile: 2 workgroups per CU
 constexpr int kWGsPerXcd64 = 128;      // 64x64 register tile: 4 workgroups per CU (LDS-bound)
 constexpr int kWGsPerXcdLds = 32;      // LDS-resident kernels: 1 workgroup per CU

@@ -216,7 +216,7 @@ static void launch(const TArgs& a, int tile, int64_t s0, int64_t s1, double beta
 static void launch_a2(const TArgs& a, int64_t k0, int64_t k1, const Sched& s, int nj, int64_t slabs) {
     const int grid = s.tiles_m * s.tiles_n;
     if (grid <= 0) return;
-    hipLaunchKernelGGL((k_a2<CfgA, kKC, false, false, true, true>), dim3(grid), dim3(CfgA::THREADS), 0, a.st, a.M,
+    hipLaunchKernelGGL((k_a2<CfgA, kKCa, false, false, true, true>), dim3(grid), dim3(CfgA::THREADS), 0, a.st, a.M,
                        a.N, k0, k1, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc, s, nj, (int64_t)0,
                        (int64_t)0);
 }

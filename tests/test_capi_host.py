@@ -94,7 +94,8 @@ def test_static_argument_errors_and_quick_returns_before_any_device_call():
     assert f(0, 0, 4, 4, 4, 0.0, NULL, 4, NULL, 4, 1.0, BIG, 4, goto, None) == 0
     # the largest panel any shape asks of Goto (k_c x n_c) fits the static array
     biggest = _lib.momms_workspace_size(64, 1 << 20, 64, goto)
-    assert biggest == 8 * mm.member_plan("A2C0", 64, 1 << 20, 64)["kc"] * 2048 and biggest <= 4 << 20
+    gp = mm.member_plan("A2C0", 64, 1 << 20, 64)
+    assert biggest == 8 * gp["kc"] * gp["nc"] and biggest <= 4 << 20
     assert _lib.momms_status_string(1005) != _lib.momms_status_string(1004)
 
 

@@ -123,12 +123,18 @@ def test_lds_block_solver():
     # panel comes from the L2 (39 TB/s) and C is read and written in HBM
     # (8 TB/s), so a C element costs 2 * 39.3 / 8 streamed elements.
     lds, bc = 160 * 1024, 2 * 39.3 / 8
+    # a block beside two 32-deep slices of a 128-wide streamed panel (the
+    # B-resident kernel keeps its A slices in LDS) ...
     assert mm.lds_block(lds, 32, 128, 1.0, bc) == (64, 160)
-    # the plans of the LDS-resident members use exactly that block, with
+    # ... and a block alone (the A-resident kernel streams B through
+    # registers): 64 x 288, since 64 x 319 is the most that fits and k_c
+    # steps by the slice
+    assert mm.lds_block(lds, 32, 0, 1.0, bc) == (64, 288)
+    # the plans of the LDS-resident members use exactly those blocks, with
     # 32-deep streamed slices
     for name in ("A2C0", "B3A2C0", "C3A2C0", "C4A2C0"):
         p = mm.member_plan(name, 8192, 8192, 8192)
-        assert (p["mt"], p["kc"], p["ks"]) == (64, 160, 32), name
+        assert (p["mt"], p["kc"], p["ks"]) == (64, 288, 32), name
     p = mm.member_plan("A3B2C0", 8192, 8192, 8192)
     assert (p["nt"], p["kc"], p["ks"]) == (64, 160, 32)
     # equal costs and thin slices: the block comes out nearly square
@@ -141,12 +147,19 @@ def test_lds_block_solver():
             if r:
                 assert r % 64 == 0 and k % 8 == 0
                 assert 8 * (r * (k + 1) + 2 * 8 * 130) <= b
+            r0, k0 = mm.lds_block(b, 8, 0, 1.0, ratio)
+            if r0:
+                assert r0 % 64 == 0 and k0 % 8 == 0 and 8 * r0 * (k0 + 1) <= b
+                # with the slices gone the block can only grow
+                assert 2.0 * r0 * k0 / (k0 + ratio * r0) >= 2.0 * r * k / (k + ratio * r) - 1e-9 if r else True
     # C dearer -> the block deepens (kc / rows grows), never the reverse
     ratios = [mm.lds_block(1 << 20, 8, 128, 1.0, c) for c in (0.5, 1.0, 4.0, 16.0)]
     depth = [k / r for r, k in ratios]
     assert depth == sorted(depth)
     with pytest.raises(Exception):
         mm.lds_block(-1, 8, 128, 1.0, 1.0)
+    with pytest.raises(Exception):
+        mm.lds_block(1 << 20, 8, -1, 1.0, 1.0)
 
 
 L2_HALF = 0.5 * 4 * 1024 * 1024   # bytes: the Sec. 4.1 share of one XCD's L2 a block may take
