@@ -92,24 +92,25 @@ static void launch_regc(const Args& a, int64_t k0, int64_t k1, double beta, cons
 
 template <bool TA, bool TB, bool PK>
 static void launch_a2_t(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, const double* Bsrc,
-                        int64_t ldb, int64_t pk0, int64_t pn0) {
+                        int64_t ldb, int64_t pk0, int64_t pn0, int kc) {
     hipLaunchKernelGGL((k_a2<CfgA, kKCa, TA, TB, PK>), dim3(grid_of(s)), dim3(CfgA::THREADS), 0, a.st, a.M, a.N, k0,
-                       k1, a.alpha, a.A, a.lda, Bsrc, ldb, a.beta, a.C, a.ldc, s, nj, pk0, pn0);
+                       k1, a.alpha, a.A, a.lda, Bsrc, ldb, a.beta, a.C, a.ldc, s, nj, pk0, pn0, kc);
 }
 
-// beta is applied by the kernel to the pass whose k chunk starts at 0.
-static void launch_a2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, const double* packed,
+// beta is applied by the kernel to the pass whose k chunk starts at 0; the
+// kernel walks [k0, k1) in chunks of kc (the plan's, checked by run()).
+static void launch_a2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, int kc, const double* packed,
                       int64_t pk0, int64_t pn0) {
     if (grid_of(s) <= 0) return;
     if (packed) {
-        if (!a.ta) launch_a2_t<false, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0);
-        else launch_a2_t<true, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0);
+        if (!a.ta) launch_a2_t<false, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0, kc);
+        else launch_a2_t<true, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0, kc);
         return;
     }
-    if (!a.ta && !a.tb) launch_a2_t<false, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
-    else if (!a.ta && a.tb) launch_a2_t<false, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
-    else if (a.ta && !a.tb) launch_a2_t<true, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
-    else launch_a2_t<true, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0);
+    if (!a.ta && !a.tb) launch_a2_t<false, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
+    else if (!a.ta && a.tb) launch_a2_t<false, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
+    else if (a.ta && !a.tb) launch_a2_t<true, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
+    else launch_a2_t<true, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
 }
 
 template <bool TA, bool TB>
@@ -142,6 +143,7 @@ static void launch_pack_b(const Args& a, int64_t pk0, int64_t pn0, int64_t ncw, 
 // Runs the loop nest of plan p.  Returns 0 or a hipError_t.
 static int run_member(const momms_plan& p, const Args& a, void* ws) {
     const int64_t M = a.M, N = a.N, K = a.K;
+    if (p.kernel == 1 && !a2_chunk_ok(p.kc)) return MOMMS_ERR_INTERNAL;
     switch (p.member) {
         case MOMMS_C0: {
             const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, 1, false);
@@ -186,9 +188,9 @@ static int run_member(const momms_plan& p, const Args& a, void* ws) {
                     if (ws) {
                         double* P = static_cast<double*>(ws);
                         launch_pack_b(a, pc, jc, je - jc, P);
-                        launch_a2(a, pc, pe, s, p.nj, P, pc, jc);
+                        launch_a2(a, pc, pe, s, p.nj, (int)p.kc, P, pc, jc);
                     } else {
-                        launch_a2(a, pc, pe, s, p.nj, nullptr, 0, 0);
+                        launch_a2(a, pc, pe, s, p.nj, (int)p.kc, nullptr, 0, 0);
                     }
                 }
             }
@@ -201,7 +203,7 @@ static int run_member(const momms_plan& p, const Args& a, void* ws) {
             const Sched s = make_sched(0, 0, M, N, p.mt, p.nc3, p.group_m, true);
             for (int64_t kb = 0; kb < K; kb += p.kc3) {
                 const int64_t ke = kb + p.kc3 < K ? kb + p.kc3 : K;
-                launch_a2(a, kb, ke, s, p.nj, nullptr, 0, 0);
+                launch_a2(a, kb, ke, s, p.nj, (int)p.kc, nullptr, 0, 0);
             }
             break;
         }
@@ -215,7 +217,7 @@ static int run_member(const momms_plan& p, const Args& a, void* ws) {
         }
         case MOMMS_C3A2C0: {
             const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, p.group_m, true);
-            launch_a2(a, 0, K, s, 1, nullptr, 0, 0);
+            launch_a2(a, 0, K, s, 1, (int)p.kc, nullptr, 0, 0);
             break;
         }
         case MOMMS_C4A2C0: {
@@ -227,7 +229,7 @@ static int run_member(const momms_plan& p, const Args& a, void* ws) {
                     const Sched s = make_sched(ib, jb, ie, je, p.mt, (int64_t)p.nj * p.nt, 1, false);
                     for (int64_t pc = 0; pc < K; pc += p.kc) {
                         const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
-                        launch_a2(a, pc, pe, s, p.nj, nullptr, 0, 0);
+                        launch_a2(a, pc, pe, s, p.nj, (int)p.kc, nullptr, 0, 0);
                     }
                 }
             }

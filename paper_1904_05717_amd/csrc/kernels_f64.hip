@@ -577,8 +577,9 @@ struct SlicePlan {
 };
 
 // ---------------------------------------------------------------------------
-// k_a2: granule = MT rows x (nj * NT) columns.  For each KC chunk of
-// [k_begin, k_end) the A block (MT x KC) is loaded into LDS once and reused for
+// k_a2: granule = MT rows x (nj * NT) columns.  For each kc chunk of
+// [k_begin, k_end) (kc a multiple of KS, at most KC, the depth the LDS block
+// is laid out for) the A block (MT x kc) is loaded into LDS once and reused for
 // every n-tile of the granule; the B slices stream into registers (above).  C
 // is read-modified-written once per chunk: beta applies to the chunk starting
 // at k = 0, later chunks accumulate.  With PACKED, B comes from a packed panel
@@ -591,7 +592,7 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
                                                     double alpha, const double* __restrict__ A, int64_t lda,
                                                     const double* __restrict__ B, int64_t ldb, double beta,
                                                     double* __restrict__ C, int64_t ldc, Sched s, int nj,
-                                                    int64_t pk0, int64_t pn0) {
+                                                    int64_t pk0, int64_t pn0, int kc) {
     static_assert(KC % CF::KS == 0, "KC must be a multiple of the slice depth");
     static_assert(!TILED || (CF::KS % 16 == 0 && KC % 16 == 0 && 128 % CF::MT == 0),
                   "tile-major slices start on slab boundaries and blocks sit inside 128-row panels");
@@ -621,8 +622,8 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
     Frag<KSTEPS, CF::BN> bq[2];
     d4 acc[CF::BM][CF::BN];
 
-    for (int64_t kb = k_begin; kb < k_end; kb += KC) {
-        const int64_t kbe = (kb + KC) < k_end ? (kb + KC) : k_end;
+    for (int64_t kb = k_begin; kb < k_end; kb += kc) {
+        const int64_t kbe = (kb + kc) < k_end ? (kb + kc) : k_end;
         const int nsl = (int)((kbe - kb + CF::KS - 1) / CF::KS);
         const int total = ntiles * nsl;
         auto b_plan = [&](int t) {
@@ -630,7 +631,7 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
             SlicePlan p;
             if (PACKED) {
                 // panel rows from (kb - pk0 + sl*KS) of n-tile ((nbeg - pn0)/NT + j);
-                // ldb is the panel height (KC for a per-chunk pack, the padded
+                // ldb is the panel height (kc for a per-chunk pack, the padded
                 // k for a tile-major B); rows past it read as zero
                 const int64_t row0 = (kb - pk0) + (int64_t)sl * CF::KS;
                 p.origin = B + ((nbeg - pn0) / CF::NT + j) * ldb * CF::NT + row0 * CF::NT + wn * CF::WTN;

@@ -223,20 +223,39 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
         case MOMMS_C3A2C0: {
             // n, m by a C block per XCD -> k by kc -> m by 64 (A block in
             // LDS) -> n by 128; one launch, every workgroup walks all of k.
-            // The C block is the tiles one XCD runs at once (32 workgroups,
-            // one per CU): 4 x 8 tiles of 64 x 128 = 256 x 1024 = 2 MiB,
-            // half the L2 (Sec. 4.1: the other half holds the A blocks and
-            // B slices streaming through it).
+            // Sec. 4.1 at level 3: the C block is the tiles one XCD runs at
+            // once (32 workgroups, one per CU: 32 tiles of 64 x 128, 2 MiB,
+            // half the L2).  Between two visits of a C tile the XCD also
+            // reads one chunk's guests, the A rows (rows x kc) and B columns
+            // (kc x cols) of the block, and they must fit the other half.
+            // The block's shape (group_m tile rows, swept column by column)
+            // minimises rows + cols; kc is then the deepest whole number of
+            // slices, up to the LDS block's depth, whose guests fit (8192^2:
+            // 8 x 4 tiles = 512 x 512, kc = 256).
             p->kernel = 1;
             p->mt = kMCa;
             p->nt = kNTa;
             p->ks = kKSlds;
-            p->kc = kKCa;
             p->nj = 1;
             p->xcd_aware = 1;
-            p->group_m = (int)(cdiv(m, p->mt) < 4 ? cdiv(m, p->mt) : 4);
-            p->mc3 = (int64_t)p->group_m * p->mt;
-            p->nc3 = (int64_t)(kWGsPerXcdLds / 4) * p->nt;
+            const int64_t tm = cdiv(m, p->mt), tn = cdiv(n, p->nt);
+            double best = -1.0;
+            for (int g = 1; g <= kWGsPerXcdLds; g *= 2) {
+                const int gm = (int)(g < tm ? g : (tm > 0 ? tm : 1));
+                const double cols = std::fmin((double)tn, std::ceil((double)kWGsPerXcdLds / gm));
+                const double rows = std::fmin((double)tm, std::ceil((double)kWGsPerXcdLds / cols));
+                const double edge = rows * p->mt + cols * p->nt;
+                if (best < 0.0 || edge < best) {
+                    best = edge;
+                    p->group_m = gm;
+                    p->mc3 = (int64_t)rows * p->mt;
+                    p->nc3 = (int64_t)cols * p->nt;
+                }
+            }
+            const int64_t kfit = (int64_t)(0.5 * kL2Bytes / (8.0 * (best > 0.0 ? best : 1.0)));
+            p->kc = kfit / kKSlds * kKSlds;
+            if (p->kc > kKCa) p->kc = kKCa;
+            if (p->kc < kKSlds) p->kc = kKSlds;
             p->k_range = p->kc < k ? p->kc : k;
             p->workgroups = cdiv(m, p->mt) * cdiv(n, p->nt);
             break;

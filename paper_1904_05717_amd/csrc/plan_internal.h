@@ -24,6 +24,11 @@ constexpr int64_t kGotoNc = 1024;      // Goto's n_c: its packed k_c x n_c panel
 constexpr int kWGsPerXcd128 = 64;      // 128x128 register tile: 2 workgroups per CU
 constexpr int kWGsPerXcd64 = 128;      // 64x64 register tile: 4 workgroups per CU (LDS-bound)
 constexpr int kWGsPerXcdLds = 32;      // LDS-resident kernels: 1 workgroup per CU
+constexpr double kL2Bytes = 4.0 * 1024 * 1024;   // one XCD's L2
+
+// A chunk depth the A-resident kernel can run: a whole number of streamed
+// slices within the depth its LDS block is laid out for.
+inline bool a2_chunk_ok(int64_t kc) { return kc >= kKSlds && kc <= kKCa && kc % kKSlds == 0; }
 
 int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p);
 void lds_block(double lds_doubles, int slice, int tile_other, double beta_stream, double beta_c, int* rows,

@@ -213,12 +213,12 @@ static void launch(const TArgs& a, int tile, int64_t s0, int64_t s1, double beta
 // The LDS-resident A-block kernel on tile-major operands: A from its 128 x 16
 // slabs, B k-slices straight from the tile-major column panels (the panel
 // height is the padded k).  s covers granules of kMCa rows x nj column tiles.
-static void launch_a2(const TArgs& a, int64_t k0, int64_t k1, const Sched& s, int nj, int64_t slabs) {
+static void launch_a2(const TArgs& a, int64_t k0, int64_t k1, const Sched& s, int nj, int kc, int64_t slabs) {
     const int grid = s.tiles_m * s.tiles_n;
     if (grid <= 0) return;
     hipLaunchKernelGGL((k_a2<CfgA, kKCa, false, false, true, true>), dim3(grid), dim3(CfgA::THREADS), 0, a.st, a.M,
                        a.N, k0, k1, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc, s, nj, (int64_t)0,
-                       (int64_t)0);
+                       (int64_t)0, kc);
 }
 
 // Granules of kMCa rows x nj column tiles (kNTa wide) over [m_off, m_lim) x
@@ -232,6 +232,7 @@ static Sched granules(int64_t m_off, int64_t n_off, int64_t m_lim, int64_t n_lim
 
 // The loop nests of the members, as in the row-major path.
 static int run(const momms_plan& p, const TArgs& a, int64_t K) {
+    if (p.kernel == 1 && !a2_chunk_ok(p.kc)) return MOMMS_ERR_INTERNAL;
     const int64_t M = a.M, N = a.N, slabs = cdiv(K, kSlab);
     const int t = p.mt;
     switch (p.member) {
@@ -266,7 +267,7 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
                 const Sched s = granules(0, jc, M, je, p.nj, 1, false);
                 for (int64_t pc = 0; pc < K; pc += p.kc) {
                     const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
-                    launch_a2(a, pc, pe, s, p.nj, slabs);
+                    launch_a2(a, pc, pe, s, p.nj, (int)p.kc, slabs);
                 }
             }
             break;
@@ -276,7 +277,7 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
             const Sched s = granules(0, 0, M, N, p.nj, p.group_m, true);
             for (int64_t kb = 0; kb < K; kb += p.kc3) {
                 const int64_t ke = kb + p.kc3 < K ? kb + p.kc3 : K;
-                launch_a2(a, kb, ke, s, p.nj, slabs);
+                launch_a2(a, kb, ke, s, p.nj, (int)p.kc, slabs);
             }
             break;
         }
@@ -297,7 +298,7 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
         }
         case MOMMS_C3A2C0:
             // XCD-grouped C tiles, each walking all of k with its A block in LDS
-            launch_a2(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true), 1, slabs);
+            launch_a2(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true), 1, (int)p.kc, slabs);
             break;
         case MOMMS_C4A2C0:
             // m, n by the MALL-resident C block -> k by kc -> the kernel
@@ -308,7 +309,7 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
                     const Sched s = granules(ib, jb, ie, je, p.nj, 1, false);
                     for (int64_t pc = 0; pc < K; pc += p.kc) {
                         const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
-                        launch_a2(a, pc, pe, s, p.nj, slabs);
+                        launch_a2(a, pc, pe, s, p.nj, (int)p.kc, slabs);
                     }
                 }
             }

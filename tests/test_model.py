@@ -132,7 +132,7 @@ def test_lds_block_solver():
     assert mm.lds_block(lds, 32, 0, 1.0, bc) == (64, 288)
     # the plans of the LDS-resident members use exactly those blocks, with
     # 32-deep streamed slices
-    for name in ("A2C0", "B3A2C0", "C3A2C0", "C4A2C0"):
+    for name in ("A2C0", "B3A2C0", "C4A2C0"):
         p = mm.member_plan(name, 8192, 8192, 8192)
         assert (p["mt"], p["kc"], p["ks"]) == (64, 288, 32), name
     p = mm.member_plan("A3B2C0", 8192, 8192, 8192)
@@ -237,3 +237,31 @@ def test_every_member_model_is_its_resident_counts(name, shape):
     want = member_counts(name, shape)
     for x in ("a_reads", "b_reads", "c_reads", "c_writes"):
         assert got[x] == pytest.approx(8 * want[x], rel=1e-12), (name, x, got[x], 8 * want[x])
+
+
+def test_c3a2c0_block_fits_l2():
+    """Sec. 4.1 at level 3 for C3A2C0: the C block is the 32 tiles of 64 x 128
+    one XCD runs at once (2 MiB, half of its 4 MiB L2), and the chunk's guests
+    beside it, the block's A rows (rows x kc) and B columns (kc x cols), take
+    at most the other half, with kc as deep as that allows (in 32-deep
+    slices, at most the 288 of the LDS block)."""
+    half = 2 * 1024 * 1024
+    # hand-derived: a 512 x 512 block leaves 2 MiB / (8 B * 1024) = 256 of
+    # depth; a 1024 x 256 block (two tile columns) 2 MiB / (8 * 1280) = 204.8
+    p = mm.member_plan("C3A2C0", 8192, 8192, 8192)
+    assert (p["mc3"], p["nc3"], p["kc"], p["k_range"]) == (512, 512, 256, 256)
+    p = mm.member_plan("C3A2C0", 16384, 256, 16384)
+    assert (p["mc3"], p["nc3"], p["kc"]) == (1024, 256, 192)
+    for shape in [(8192, 8192, 8192), (16384, 16384, 256), (16384, 256, 16384), (1024, 1024, 1024),
+                  (100, 3000, 500), (3000, 100, 500), (64, 128, 4096), (4096, 8192, 2048)]:
+        p = mm.member_plan("C3A2C0", *shape)
+        m, n, k = shape
+        edge = p["mc3"] + p["nc3"]
+        assert p["kc"] % 32 == 0 and 32 <= p["kc"] <= 288
+        assert 8 * p["kc"] * edge <= half, shape
+        assert p["kc"] == 288 or 8 * (p["kc"] + 32) * edge > half, shape
+        # the block is the tiles one XCD holds at once, clipped to the matrix
+        assert p["mc3"] % 64 == 0 and p["nc3"] % 128 == 0
+        assert (p["mc3"] // 64) * (p["nc3"] // 128) <= 32
+        assert p["mc3"] <= max(64, -(-m // 64) * 64) and p["nc3"] <= max(128, -(-n // 128) * 128)
+        assert p["k_range"] == min(p["kc"], k)
