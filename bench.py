@@ -785,13 +785,16 @@ SWEEP_SHAPES = [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (819
 def bench_sweep(args):
     """The FP64 sweep: square sizes 1024 .. 16384, the rank-k update
     16384 x 16384 x 256 and the panel-panel product 16384 x 256 x 16384
-    (U[-1,1], beta = 1).  Every member after a warm-up, the fastest of up to
-    five calls (fewer when a call is long); the member AUTO picks; measured L2 traffic against the model where a stored traffic
+    (U[-1,1], beta = 1).  Every member timed as the member tuner times it
+    (the fastest of three batch means, batches of back-to-back calls at least
+    2 ms long, the rounds visiting the members in turn); the member AUTO
+    picks; measured L2 traffic against the model where a stored traffic
     profile of the same shape and kernels exists."""
     import torch
 
     import paper_1904_05717_amd as mm
     import workloads
+    from paper_1904_05717_amd import tuner
 
     out = []
     for (m, n, k) in SWEEP_SHAPES:
@@ -807,25 +810,10 @@ def bench_sweep(args):
         except (OSError, ValueError, KeyError):
             pass
         members = {}
-        for member in mm.FAMILY:
-            wsb = mm.workspace_size(m, n, k, member)
-            ws = torch.empty(wsb, dtype=torch.uint8, device="cuda:0") if wsb else None
-            mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
-            torch.cuda.synchronize()
-            times = []
-            while len(times) < 5 and sum(times) < 200.0:   # the fastest of up to 5 calls within ~0.2 s
-                e0, e1 = events()
-                e0.record()
-                mm.gemm(Ad, Bd, Cd, 1.0, 1.0, member=member, workspace=ws)
-                e1.record()
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1))
-            ms = min(times)
-            members[member] = {"ms": round(ms, 3), "tflops": round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 2),
-                               "calls": len(times)}
+        for member, ms in tuner.time_members(mm, Ad, Bd, Cd, mm.FAMILY).items():
+            members[member] = {"ms": round(ms, 4), "tflops": round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 2)}
             if member in traffic:
                 members[member]["traffic_vs_model"] = traffic[member]
-            del ws
         best = max(members, key=lambda x: members[x]["tflops"])
         out.append({"m": m, "n": n, "k": k, "auto": mm.select_member(m, n, k), "best": best,
                     "best_tflops": members[best]["tflops"], "members": members})

@@ -63,6 +63,42 @@ def time_member(mm, A, B, C, member, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
+def time_members(mm, A, B, C, members, min_ms=2.0, rounds=3):
+    """Milliseconds per call of each member: the fastest of `rounds` batch
+    means, a batch being enough back-to-back calls to last about min_ms (one
+    call when a call is longer).  The rounds visit the members in turn, so a
+    drift of the clock or of the other load on the device touches every
+    member alike, and short calls are timed over many launches."""
+    import torch
+    m, k = A.shape
+    n = B.shape[1]
+    ws, reps, best = {}, {}, {}
+    for mem in members:
+        wsb = mm.workspace_size(m, n, k, mem)
+        ws[mem] = torch.empty(wsb, dtype=torch.uint8, device=A.device) if wsb else None
+        mm.gemm(A, B, C, 1.0, 1.0, member=mem, workspace=ws[mem])   # warm-up
+        torch.cuda.synchronize()
+        one = _batch(mm, A, B, C, mem, ws[mem], 1)
+        reps[mem] = max(1, min(200, int(math.ceil(min_ms / max(one, 1e-3)))))
+        best[mem] = float("inf")
+    for _ in range(rounds):
+        for mem in members:
+            best[mem] = min(best[mem], _batch(mm, A, B, C, mem, ws[mem], reps[mem]))
+    return best
+
+
+def _batch(mm, A, B, C, member, ws, reps):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        mm.gemm(A, B, C, 1.0, 1.0, member=member, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 TIE = 0.01
 
 
@@ -108,7 +144,7 @@ def sweep(shapes=SWEEP_SHAPES, members=None):
         A, B, C = workloads.gemm_operands(m, n, k)
         Ad, Bd, Cd = (torch.from_numpy(x).to("cuda:0") for x in (A, B, C))
         del A, B, C
-        times = {mem: time_member(mm, Ad, Bd, Cd, mem) for mem in members}
+        times = time_members(mm, Ad, Bd, Cd, members)
         best = pick(mm, m, n, k, times)
         entries.append({"shape": [m, n, k], "bucket": list(bucket(m, n, k)), "best": best,
                         "ms": {k2: round(v, 4) for k2, v in times.items()},
