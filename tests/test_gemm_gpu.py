@@ -60,6 +60,29 @@ def test_config1_integer_bit_exact(member):
     np.testing.assert_array_equal(run(A, B, C, 1.0, 1.0, member), want)
 
 
+@pytest.mark.parametrize("shape", [(100, 3000, 500), (1000, 256, 1000)])
+@pytest.mark.parametrize("trans", [(False, False), (True, True)])
+def test_c3a2c0_shallow_chunks(shape, trans):
+    # C3A2C0's chunk depth comes from its level-3 block (the chunk's A rows
+    # and B columns must fit half an L2 beside the C block), so on these
+    # shapes the A-resident kernel runs chunks shallower than its LDS block,
+    # several of them, with a ragged last one
+    m, n, k = shape
+    p = mm.member_plan("C3A2C0", m, n, k)
+    assert p["kc"] < 288 and k > 2 * p["kc"] and k % p["kc"] != 0, p
+    ta, tb = trans
+    A, B, C = workloads.gemm_operands(m, n, k)
+    Ai, Bi, _ = workloads.gemm_operands(m, n, k, kind="int")
+    for X, Y, Z, exact in ((A, B, C, False), (Ai, Bi, np.zeros((m, n)), True)):
+        want = oracle.gemm(X, Y, Z, 1.5 if not exact else 1.0, -0.5 if not exact else 1.0)
+        got = run(X.T.copy() if ta else X, Y.T.copy() if tb else Y, Z, 1.5 if not exact else 1.0,
+                  -0.5 if not exact else 1.0, "C3A2C0", transA=ta, transB=tb)
+        if exact:
+            np.testing.assert_array_equal(got, want)
+        else:
+            assert_within_bound(got, want, X, Y, Z, 1.5, -0.5, f"C3A2C0 {shape} {trans}")
+
+
 @pytest.mark.parametrize("member", FAMILY)
 @pytest.mark.parametrize("shape", [(300, 280, 260), (129, 257, 131)])
 def test_ragged_alpha_beta(member, shape):
