@@ -7,8 +7,9 @@
 //   k_regc : C tile resident in registers (level 0) while the workgroup runs
 //            over a k range; A and B k-slices are streamed through a
 //            double-buffered LDS stage (LDS holds no resident block).
-//   k_a2   : an A block (MT x KC) resident in LDS (level 2), reused across
-//            NJ n-tiles; B slices streamed; C updated once per KC.
+//   k_a2   : an A block (MT x kc, kc <= KC) resident in LDS (level 2),
+//            reused across NJ n-tiles; B slices streamed; C updated once
+//            per chunk of kc.
 //   k_b2   : a B block (KC x NT) resident in LDS, reused across MI m-tiles;
 //            A slices streamed; C updated once per KC.
 //
@@ -518,7 +519,7 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha, 
 }
 
 // ---------------------------------------------------------------------------
-// The A-resident kernel k_a2 loads its A block into LDS once per KC chunk and
+// The A-resident kernel k_a2 loads its A block into LDS once per k chunk and
 // then only reads it, so the workgroup synchronises twice per chunk and never
 // per slice.  B streams from the L2 (through the vector L1) straight into
 // registers, as the Goto loop nest streams its B micro-panels through the L1
