@@ -7,9 +7,8 @@
 //   k_regc : C tile resident in registers (level 0) while the workgroup runs
 //            over a k range; A and B k-slices are streamed through a
 //            double-buffered LDS stage (LDS holds no resident block).
-//   k_a2   : an A block (MT x kc, kc <= KC) resident in LDS (level 2),
-//            reused across NJ n-tiles; B slices streamed; C updated once
-//            per chunk of kc.
+//   k_a2   : an A block (MT x kc, kc <= KC) resident in LDS (level 2), reused
+//            across NJ n-tiles; B slices streamed; C updated once per kc.
 //   k_b2   : a B block (KC x NT) resident in LDS, reused across MI m-tiles;
 //            A slices streamed; C updated once per KC.
 //

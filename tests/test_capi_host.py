@@ -155,6 +155,23 @@ def test_member_table_is_ignored_when_measured_on_other_sources(tmp_path):
         tuner.install()
 
 
+def test_committed_measurements_belong_to_the_committed_sources():
+    # The member table and the traffic profiles carry a hash of the kernel
+    # and planner sources (comments stripped) they were measured on; AUTO and
+    # the bench line use them only while it matches.  A source change that is
+    # not re-measured shows here rather than as a silent fallback.
+    import json
+    import os
+    from paper_1904_05717_amd import tuner
+    import bench
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    table = json.load(open(os.path.join(root, "paper_1904_05717_amd", "tuned_members.json")))
+    assert table["source_sha"] == tuner.source_sha()
+    for shape in ("8192", "16384x16384x256", "16384x256x16384"):
+        prof = json.load(open(os.path.join(root, "profiles", f"traffic_f64_{shape}.json")))
+        assert prof["kernel_source_sha"] == bench.kernel_source_sha(), shape
+
+
 def test_int8_and_fp8_exactness_limits():
     # slices * k (k rounded up to 128) must stay <= 2^17 so every INT32 sum
     # is exact; beyond it the call is refused before any launch.
