@@ -141,9 +141,11 @@ def test_block_edges(m):
 
 
 @pytest.mark.parametrize("uplo,trans,diag", COMBOS)
-@pytest.mark.parametrize("m", [65, 100, 128])
-def test_two_block_solve_every_combination(m, uplo, trans, diag):
-    """Solves just past one diagonal block: two blocks and the product between them."""
+@pytest.mark.parametrize("m", [65, 100, 128, 150, 192, 193])
+def test_multi_block_solve_every_combination(m, uplo, trans, diag):
+    """Solves past one diagonal block: two and three 64-row blocks with the
+    products between them (ragged last blocks, and uneven splits at 150 and
+    193), on a ragged number of columns."""
     n = 70
     A = well_conditioned(m, 11)
     B = np.random.Generator(np.random.PCG64(12)).uniform(-1, 1, (m, n))
