@@ -653,16 +653,49 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
             const bool ok = PACKED ? p.k0 + kr < ldb : (p.k0 + kr < kbe && p.x0 + nc < nend);
             return *(ok ? p.origin + kr * bks + nc * bxs : &kZeroEntry);
         };
-        // The chunk's A block goes to LDS in rounds of kRound slices through
-        // two register sets: a round's loads are in flight while the round
-        // before it is stored.  The first round is loaded before the barrier
-        // that waits for the previous chunk's readers of As.
-        constexpr int NSL = KC / CF::KS, kRound = 2;
-        auto load_round = [&](SA (&set)[kRound], int c0) {
+        // The chunk's A block goes to LDS in rounds of slices through two
+        // register sets: a round's loads are in flight while the round before
+        // it is stored.  The first round is loaded before the barrier that
+        // waits for the previous chunk's readers of As.  A chunk whose block
+        // lies wholly inside A takes the unchecked loads for every slice, in
+        // one round (all of the block's loads in flight at once); an edge
+        // chunk takes the checked ones, two slices a round.  Deciding once
+        // per chunk keeps the checked path's per-entry addresses out of the
+        // fast path's registers.
+        constexpr int NSL = KC / CF::KS;
+        const bool fast = !TILED && m0 + CF::MT <= M && kbe - kb == (int64_t)nsl * CF::KS && SA::fast_ld(lda);
+        auto rounds = [&](auto kround_tag, auto load_slice) {
+            constexpr int KR = decltype(kround_tag)::value;
+            auto load_round = [&](SA (&set)[KR], int c0) {
 #pragma unroll
-            for (int u = 0; u < kRound; ++u) {
-                const int c = c0 + u;
-                if (c >= nsl) break;
+                for (int u = 0; u < KR; ++u)
+                    if (c0 + u < nsl) load_slice(set[u], c0 + u);
+            };
+            auto store_round = [&](const SA (&set)[KR], int c0) {
+#pragma unroll
+                for (int u = 0; u < KR; ++u)
+                    if (c0 + u < nsl) set[u].store(As + (c0 + u) * CF::KS, AB_LD, tid);
+            };
+            SA sq[2][KR];
+            load_round(sq[0], 0);
+            __syncthreads();  // the previous chunk's readers of As are done
+#pragma unroll
+            for (int c0 = 0; c0 < NSL; c0 += 2 * KR) {
+                if (c0 + KR < NSL) load_round(sq[1], c0 + KR);
+                store_round(sq[0], c0);
+                if (c0 + 2 * KR < NSL) load_round(sq[0], c0 + 2 * KR);
+                if (c0 + KR < NSL) store_round(sq[1], c0 + KR);
+            }
+        };
+        if (fast) {
+            rounds(std::integral_constant<int, NSL>{}, [&](SA& st, int c) {
+                const int64_t kk = kb + (int64_t)c * CF::KS;
+#pragma unroll
+                for (int e = 0; e < SA::N; ++e)
+                    st.load_elem_fast(e, TA ? A + kk * lda + m0 : A + m0 * lda + kk, lda, aoff);
+            });
+        } else {
+            rounds(std::integral_constant<int, 2>{}, [&](SA& st, int c) {
                 const int64_t kk = kb + (int64_t)c * CF::KS;
                 if constexpr (TILED) {
                     // tile-major A: 128 x 16 slabs, lda = slabs per row panel,
@@ -670,33 +703,11 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
                     // divides 128: the block is rows m0 % 128 .. of its
                     // slabs; a slice starts on a slab boundary)
                     const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + (m0 % 128) * 16;
-                    set[u].load_slabs(P, 2048, lda * 16 - kk, tid);
-                } else if (m0 + CF::MT <= M && kk + CF::KS <= kbe && SA::fast_ld(lda)) {
-#pragma unroll
-                    for (int e = 0; e < SA::N; ++e)
-                        set[u].load_elem_fast(e, TA ? A + kk * lda + m0 : A + m0 * lda + kk, lda, aoff);
+                    st.load_slabs(P, 2048, lda * 16 - kk, tid);
                 } else {
-                    set[u].load(A, lda, m0, kk, M, kbe, tid);
+                    st.load(A, lda, m0, kk, M, kbe, tid);
                 }
-            }
-        };
-        auto store_round = [&](const SA (&set)[kRound], int c0) {
-#pragma unroll
-            for (int u = 0; u < kRound; ++u) {
-                const int c = c0 + u;
-                if (c >= nsl) break;
-                set[u].store(As + c * CF::KS, AB_LD, tid);
-            }
-        };
-        SA sq[2][kRound];
-        load_round(sq[0], 0);
-        __syncthreads();  // the previous chunk's readers of As are done
-#pragma unroll
-        for (int c0 = 0; c0 < NSL; c0 += 2 * kRound) {
-            if (c0 + kRound < NSL) load_round(sq[1], c0 + kRound);
-            store_round(sq[0], c0);
-            if (c0 + 2 * kRound < NSL) load_round(sq[0], c0 + 2 * kRound);
-            if (c0 + kRound < NSL) store_round(sq[1], c0 + kRound);
+            });
         }
         {   // the first B slice, once the A block's registers are free
             const SlicePlan p0 = b_plan(0);
