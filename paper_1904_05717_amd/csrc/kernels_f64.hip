@@ -614,6 +614,9 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
 
     using SA = Stage<CF::MT, CF::KS, CF::THREADS, TA>;
     const uint32_t aoff = SA::lane_offset(lda, tid);
+    // tile-major A: this thread's entry of a 32-deep slice within its two
+    // 128 x 16 slabs (element (r, s) of the block at slab s / 16, row r)
+    const uint32_t aoff_slab = (uint32_t)((((tid % CF::KS) / 16) * 2048 + (tid / CF::KS) * 16 + tid % 16) * 8);
     // B fragment (kk, x) of a wave's slice: k = 4 kk + lk, n = 16 x + li from
     // the slice origin (column wn * WTN of its n-tile)
     const int64_t ldbs = PACKED ? CF::NT : ldb;
@@ -661,9 +664,10 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
         // one round (all of the block's loads in flight at once); an edge
         // chunk takes the checked ones, two slices a round.  Deciding once
         // per chunk keeps the checked path's per-entry addresses out of the
-        // fast path's registers.
+        // fast path's registers.  Tile-major A is zero-padded to whole row
+        // panels and slabs, so there every chunk of full slices is interior.
         constexpr int NSL = KC / CF::KS;
-        const bool fast = !TILED && m0 + CF::MT <= M && kbe - kb == (int64_t)nsl * CF::KS && SA::fast_ld(lda);
+        const bool fast = kbe - kb == (int64_t)nsl * CF::KS && (TILED || (m0 + CF::MT <= M && SA::fast_ld(lda)));
         auto rounds = [&](auto kround_tag, auto load_slice) {
             constexpr int KR = decltype(kround_tag)::value;
             auto load_round = [&](SA (&set)[KR], int c0) {
@@ -690,9 +694,17 @@ __global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_
         if (fast) {
             rounds(std::integral_constant<int, NSL>{}, [&](SA& st, int c) {
                 const int64_t kk = kb + (int64_t)c * CF::KS;
+                if constexpr (TILED) {
+                    // entry e of this thread: slab row (tid / KS) + e * RPP
+                    // of the slabs at kk, column tid % KS (aoff_slab)
+                    const double* P = A + ((m0 / 128) * lda + kk / 16) * 2048 + (m0 % 128) * 16;
 #pragma unroll
-                for (int e = 0; e < SA::N; ++e)
-                    st.load_elem_fast(e, TA ? A + kk * lda + m0 : A + m0 * lda + kk, lda, aoff);
+                    for (int e = 0; e < SA::N; ++e) st.v[e] = load_sbase(P + (int64_t)e * SA::RPP * 16, aoff_slab);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < SA::N; ++e)
+                        st.load_elem_fast(e, TA ? A + kk * lda + m0 : A + m0 * lda + kk, lda, aoff);
+                }
             });
         } else {
             rounds(std::integral_constant<int, 2>{}, [&](SA& st, int c) {
