@@ -158,7 +158,7 @@ int momms_gemm_ex(int transA, int transB, int64_t m, int64_t n, int64_t k,
  * to momms_gemm_ex with a workspace; other members use no scratch.  If the
  * member would need more than the array holds the call returns
  * MOMMS_ERR_SCRATCH before any HIP call (no member does at present: Goto's
- * panel is at most 128 x 4096 doubles).  Each GPU has its own array, kept
+ * panel is at most 288 x 1024 doubles).  Each GPU has its own array, kept
  * until the process ends and shared by every call on that GPU: calls that
  * overlap in time on one GPU (different streams, or different host threads)
  * race on it and must be serialized by the caller.  Nothing is allocated,
