@@ -49,6 +49,8 @@ def parse():
                     help="split-precision configurations to time, as type:slices[,type:slices...]")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--full-json", metavar="PATH", default=None,
+                    help="also write every section's full results to PATH as one JSON object")
     ap.add_argument("--profile", action="store_true", help="few steps, FP64 product only (for rocprofv3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (3 times): the reference for HBM byte counters")
@@ -972,8 +974,8 @@ def _split_summary(sp):
 
 def compact_line(out):
     """The final stdout line: the headline and a short summary of every
-    section (the full sections are printed on earlier lines and written to
-    gpurun_out/bench_full.json)."""
+    section (the full sections are printed on earlier lines, and written to
+    --full-json when given)."""
     keep = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
             "vs_baseline", "dtype", "data", "config", "roofline", "max_err_over_bound_260_entries",
             "measured_vs_model", "cpu_baseline"]
@@ -1056,12 +1058,9 @@ def main():
             print(json.dumps({"section": name, "result": out[name]}), flush=True)
     if not args.no_cpu and not args.profile:
         out["cpu_baseline"] = cpu_baseline(args.size, args.size, args.size, args.cpu_seconds)
-    try:
-        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-        with open(os.path.join(ROOT, "gpurun_out", "bench_full.json"), "w") as fh:
+    if args.full_json:
+        with open(args.full_json, "w") as fh:
             json.dump(out, fh)
-    except OSError:
-        pass
     print(json.dumps(compact_line(out)), flush=True)
 
 
