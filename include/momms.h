@@ -221,18 +221,20 @@ int momms_model_resident(int resident, int64_t m, int64_t n, int64_t k, int64_t 
  * mc = sqrt(beta_b/beta_c M), kc = sqrt(beta_c/beta_b M).  Host-only. */
 int momms_balanced_block(double M, double beta_b, double beta_c, double *mc, double *kc);
 /* The planner's level-2 (LDS) block solver (Sec. 2.4 balance within the
- * Sec. 4.1 capacity): for a fast memory of lds_bytes holding the resident
- * block (row pitch kc + 1 doubles) plus two streamed k-slices of
- * slice x (tile_other + 2) doubles (none when tile_other is 0: the streamed
- * panel goes straight to registers), the block (rows a multiple of 64, kc a
- * multiple of slice) with the most flops per unit of streamed cost, the streamed
- * panel costing beta_stream and C beta_c per element; ties go to the block
- * nearer the continuous optimum (momms_balanced_block), then to fewer rows.
- * The LDS-resident kernels are built for its answer on gfx950.  Returns 0,
- * or -i for a bad argument i (rows and kc are 0 when nothing fits).
- * Host-only. */
-int momms_lds_block(double lds_bytes, int slice, int tile_other, double beta_stream, double beta_c, int *rows,
-                    int *kc);
+ * Sec. 4.1 capacity): for a fast memory of lds_bytes (one workgroup's share
+ * of a CU's LDS) holding the resident block (row pitch kc + 1 doubles) plus
+ * two streamed k-slices of slice x (tile_other + 2) doubles (none when
+ * tile_other is 0: the streamed panel goes straight to registers), the block
+ * (rows a multiple of row_step, which is a positive multiple of 16, and kc a
+ * multiple of slice) with the most flops per unit of streamed cost, the
+ * streamed panel costing beta_stream and C beta_c per element; ties go to the
+ * block nearer the continuous optimum (momms_balanced_block), then to fewer
+ * rows.  The LDS-resident kernels are built for its answer on gfx950: the
+ * A-resident block for 80 KiB (two workgroups per CU) with row_step 32, the
+ * B-resident block for 160 KiB with row_step 64.  Returns 0, or -i for a bad
+ * argument i (rows and kc are 0 when nothing fits).  Host-only. */
+int momms_lds_block(double lds_bytes, int slice, int tile_other, int row_step, double beta_stream, double beta_c,
+                    int *rows, int *kc);
 
 /* ---------------------------------------------------------------------
  * Split-precision FP64-accurate product (Ozaki-style error-free splitting;

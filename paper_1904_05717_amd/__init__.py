@@ -436,12 +436,13 @@ def balanced_block(M, beta_b, beta_c):
     return mc.value, kc.value
 
 
-def lds_block(lds_bytes, slice_depth, tile_other, beta_stream, beta_c):
+def lds_block(lds_bytes, slice_depth, tile_other, row_step, beta_stream, beta_c):
     """The planner's level-2 block solver: (rows, kc) of the resident block."""
     import ctypes
     rows, kc = ctypes.c_int(), ctypes.c_int()
-    check_status(_lib.momms_lds_block(float(lds_bytes), int(slice_depth), int(tile_other), float(beta_stream),
-                                      float(beta_c), ctypes.byref(rows), ctypes.byref(kc)), "momms_lds_block")
+    check_status(_lib.momms_lds_block(float(lds_bytes), int(slice_depth), int(tile_other), int(row_step),
+                                      float(beta_stream), float(beta_c), ctypes.byref(rows), ctypes.byref(kc)),
+                 "momms_lds_block")
     return rows.value, kc.value
 
 

@@ -82,7 +82,7 @@ momms_batch_set_rates = _fn("momms_batch_set_rates", i32, [dbl, dbl, dbl])
 
 momms_model_resident = _fn("momms_model_resident", i32, [i32, i64, i64, i64, i64, i64, dbl, _pdbl])
 momms_balanced_block = _fn("momms_balanced_block", i32, [dbl, dbl, dbl, _pdbl, _pdbl])
-momms_lds_block = _fn("momms_lds_block", i32, [dbl, i32, i32, dbl, dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)])
+momms_lds_block = _fn("momms_lds_block", i32, [dbl, i32, i32, i32, dbl, dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)])
 
 momms_set_member_table = _fn("momms_set_member_table", i32, [i32, _pi32, _pi32, _pi32, _pi32])
 momms_select_member_prior = _fn("momms_select_member_prior", i32, [i64, i64, i64])

@@ -32,12 +32,15 @@ __global__ __launch_bounds__(256) void k_scale_c(int64_t M, int64_t N, double be
 
 using CfgL = TileCfg<128, 128, 16, 2, 2>;  // register-resident C, large problems
 using CfgS = TileCfg<64, 64, 16, 2, 2>;    // register-resident C, small problems
-// LDS-resident blocks: eight waves of 32 x 32, two per SIMD, 32-deep streamed
-// slices.  A block kMCa x kKC (C tiles kMCa x kNTa); B block kKC x kNCb (C
-// tiles kMTb x kNCb).
+// LDS-resident blocks: waves of 32 x 32, two per SIMD, 32-deep streamed
+// slices.  A block kMCa x kKCa (C tiles kMCa x kNTa), four waves, two
+// workgroups per CU; for C3A2C0 kMCa1 x kKCa, eight waves, one per CU; B
+// block kKC x kNCb (C tiles kMTb x kNCb), eight waves.
 using CfgA = TileCfg<kMCa, kNTa, kKSlds, kMCa / 32, kNTa / 32>;
+using CfgA1 = TileCfg<kMCa1, kNTa, kKSlds, kMCa1 / 32, kNTa / 32>;
 using CfgB = TileCfg<kMTb, kNCb, kKSlds, kMTb / 32, kNCb / 32>;
-static_assert(CfgA::THREADS == 512 && CfgB::THREADS == 512, "eight waves per LDS-resident workgroup");
+static_assert(CfgA::THREADS * kWGsPerCuA == 512 && CfgA1::THREADS == 512 && CfgB::THREADS == 512,
+              "eight waves per CU");
 
 static hipStream_t g_stream = nullptr;
 
@@ -90,27 +93,29 @@ static void launch_regc(const Args& a, int64_t k0, int64_t k1, double beta, cons
     else launch_regc_t<CF, true, true>(a, k0, k1, beta, s);
 }
 
-template <bool TA, bool TB, bool PK>
+template <class Cfg, bool TA, bool TB, bool PK>
 static void launch_a2_t(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, const double* Bsrc,
                         int64_t ldb, int64_t pk0, int64_t pn0, int kc) {
-    hipLaunchKernelGGL((k_a2<CfgA, kKCa, TA, TB, PK>), dim3(grid_of(s)), dim3(CfgA::THREADS), 0, a.st, a.M, a.N, k0,
+    hipLaunchKernelGGL((k_a2<Cfg, kKCa, TA, TB, PK>), dim3(grid_of(s)), dim3(Cfg::THREADS), 0, a.st, a.M, a.N, k0,
                        k1, a.alpha, a.A, a.lda, Bsrc, ldb, a.beta, a.C, a.ldc, s, nj, pk0, pn0, kc);
 }
 
 // beta is applied by the kernel to the pass whose k chunk starts at 0; the
-// kernel walks [k0, k1) in chunks of kc (the plan's, checked by run()).
+// kernel walks [k0, k1) in chunks of kc (the plan's, checked by run()).  Cfg
+// is CfgA1 for C3A2C0 (never packed), CfgA for the other members.
+template <class Cfg = CfgA>
 static void launch_a2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, int kc, const double* packed,
                       int64_t pk0, int64_t pn0) {
     if (grid_of(s) <= 0) return;
     if (packed) {
-        if (!a.ta) launch_a2_t<false, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0, kc);
-        else launch_a2_t<true, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0, kc);
+        if (!a.ta) launch_a2_t<CfgA, false, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0, kc);
+        else launch_a2_t<CfgA, true, false, true>(a, k0, k1, s, nj, packed, kKCa, pk0, pn0, kc);
         return;
     }
-    if (!a.ta && !a.tb) launch_a2_t<false, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
-    else if (!a.ta && a.tb) launch_a2_t<false, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
-    else if (a.ta && !a.tb) launch_a2_t<true, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
-    else launch_a2_t<true, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
+    if (!a.ta && !a.tb) launch_a2_t<Cfg, false, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
+    else if (!a.ta && a.tb) launch_a2_t<Cfg, false, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
+    else if (a.ta && !a.tb) launch_a2_t<Cfg, true, false, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
+    else launch_a2_t<Cfg, true, true, false>(a, k0, k1, s, nj, a.B, a.ldb, 0, 0, kc);
 }
 
 template <bool TA, bool TB>
@@ -143,7 +148,8 @@ static void launch_pack_b(const Args& a, int64_t pk0, int64_t pn0, int64_t ncw, 
 // Runs the loop nest of plan p.  Returns 0 or a hipError_t.
 static int run_member(const momms_plan& p, const Args& a, void* ws) {
     const int64_t M = a.M, N = a.N, K = a.K;
-    if (p.kernel == 1 && !a2_chunk_ok(p.kc)) return MOMMS_ERR_INTERNAL;
+    if (p.kernel == 1 && (!a2_chunk_ok(p.kc) || p.mt != (p.member == MOMMS_C3A2C0 ? CfgA1::MT : CfgA::MT)))
+        return MOMMS_ERR_INTERNAL;
     switch (p.member) {
         case MOMMS_C0: {
             const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, 1, false);
@@ -217,7 +223,7 @@ static int run_member(const momms_plan& p, const Args& a, void* ws) {
         }
         case MOMMS_C3A2C0: {
             const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, p.group_m, true);
-            launch_a2(a, 0, K, s, 1, (int)p.kc, nullptr, 0, 0);
+            launch_a2<CfgA1>(a, 0, K, s, 1, (int)p.kc, nullptr, 0, 0);
             break;
         }
         case MOMMS_C4A2C0: {

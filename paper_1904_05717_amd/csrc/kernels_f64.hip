@@ -524,10 +524,10 @@ void k_regc(int64_t M, int64_t N, int64_t k_begin, int64_t k_end, double alpha, 
 // registers, as the Goto loop nest streams its B micro-panels through the L1
 // (Sec. 5.2): each wave loads exactly the MFMA fragments it uses, one 32-deep
 // slice ahead in a ring of two register sets, one MFMA step's fragments per
-// step.  Without a barrier per slice the waves of a workgroup drift apart,
-// and a wave waiting for memory leaves the MFMA unit to the other wave of its
-// SIMD.  Each wave reads its B fragments itself, so every B element is read
-// from the L2 by the two waves that share it.
+// step.  Without a barrier per slice the waves of a workgroup drift apart.
+// Two workgroups of one row of four waves share a CU and its SIMDs: a wave
+// waiting for memory, or its workgroup refilling its A block at a chunk
+// start, leaves the MFMA unit to the other workgroup's waves.
 
 // Fragments of a streamed operand for one wave and one slice: f[kk][x] is the
 // operand of MFMA step kk for 16-row (A) or 16-column (B) block x.
@@ -586,9 +586,10 @@ struct SlicePlan {
 // laid out [n-tile][k][NT] (rows of NT doubles, zero-padded, ldb rows per
 // n-tile), whose origin is (pk0, pn0) in B's coordinates; n-tiles are
 // numbered from pn0.  With TILED, A is tile-major (128 x 16 slabs; MT divides
-// 128).
+// 128).  Registers are capped for two waves per SIMD, so that two four-wave
+// workgroups fit a CU.
 template <class CF, int KC, bool TA, bool TB, bool PACKED, bool TILED = false>
-__global__ __launch_bounds__(CF::THREADS) void k_a2(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
+__global__ __launch_bounds__(CF::THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_a2(int64_t M, int64_t N, int64_t k_begin, int64_t k_end,
                                                     double alpha, const double* __restrict__ A, int64_t lda,
                                                     const double* __restrict__ B, int64_t ldb, double beta,
                                                     double* __restrict__ C, int64_t ldc, Sched s, int nj,

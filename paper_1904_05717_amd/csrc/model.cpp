@@ -161,15 +161,16 @@ int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int pa
             break;
         }
         case MOMMS_C3A2C0: {
-            // One XCD round is 32 workgroups in the grouped order (group_m
-            // tile rows swept column by column): a C block of cols = min(tn,
-            // 32 / group_m) tile columns and 32 / cols tile rows, which is
+            // One XCD round is 32 workgroups (one per CU) in the grouped
+            // order (group_m tile rows swept column by column): a C block of
+            // cols = min(tn, 32 / group_m) tile columns and 32 / cols tile
+            // rows, which is
             // Resident C for A and B.  Its lines stay in the L2 for reads (C
             // read once), but the L2 writes the updated lines back after
             // every kc pass (measured: the write traffic is C once per pass),
             // so C is written once per pass.
-            const double cols = std::fmin(tn, std::ceil((double)kWGsPerXcdLds / (double)p.group_m));
-            const double rows = std::fmin(tm, std::ceil((double)kWGsPerXcdLds / cols));
+            const double cols = std::fmin(tn, std::ceil((double)kWGsPerXcdA1 / (double)p.group_m));
+            const double rows = std::fmin(tm, std::ceil((double)kWGsPerXcdA1 / cols));
             double cnt[4];
             resident_counts('C', m, n, k, (int64_t)rows * p.mt, (int64_t)cols * p.nt, beta, cnt);
             a = cnt[0];

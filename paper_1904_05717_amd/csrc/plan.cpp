@@ -11,9 +11,11 @@
 //            balance between the streamed panel (from the L2) and C (from
 //            HBM, read and written), within the Sec. 4.1 capacity, on the
 //            MFMA wave grid.  The A-resident kernel streams B through
-//            registers, so its block has the 160 KiB alone: 64 x 288 (144
-//            KiB).  The B-resident kernel keeps two 32-deep A slices beside
-//            its block: 160 x 64 (80 KiB).
+//            registers, so its block has LDS to itself; two of its
+//            workgroups share a CU (one computes while the other refills its
+//            block), so each has half: 32 x 288 (72 KiB).  The B-resident
+//            kernel keeps two 32-deep A slices beside its block: 160 x 64
+//            (80 KiB).
 //   level 3: one XCD's 4 MiB L2.  A 512 x 512 resident block (2 MiB) leaves
 //            half the L2 for the guest and streamed panels (Sec. 4.1).
 //   level 4: the 256 MiB MALL.  A 4096 x 4096 C block (128 MiB) leaves half.
@@ -43,7 +45,8 @@ static inline int regc_tile(int64_t m, int64_t n) {
 // of B for beta_stream kc + beta_c rows of cost; the continuous optimum at a
 // capacity of M elements is rows = sqrt(beta_stream / beta_c M), kc =
 // sqrt(beta_c / beta_stream M) (momms_balanced_block).  The kernels need rows
-// a multiple of 64 (two rows of 32-row waves) and kc a multiple of the slice
+// a multiple of row_step (32 per row of 32-row waves: the A-resident kernel
+// has one, the B-resident kernel two columns) and kc a multiple of the slice
 // depth; the block plus two streamed k-slices of slice x (tile_other + 2)
 // must fit lds_doubles with the block's row pitch kc + 1.  tile_other = 0
 // means the streamed panel does not pass through LDS at all (the A-resident
@@ -54,14 +57,14 @@ static inline int regc_tile(int64_t m, int64_t n) {
 // with the most flops per unit cost wins; ties go to the one nearer the
 // continuous optimum (in kc / rows), then to fewer rows.  The B-resident
 // kernel is the mirror (rows = block columns).
-void lds_block(double lds_doubles, int slice, int tile_other, double beta_stream, double beta_c, int* rows,
-               int* kc) {
+void lds_block(double lds_doubles, int slice, int tile_other, int row_step, double beta_stream, double beta_c,
+               int* rows, int* kc) {
     const double stream = tile_other > 0 ? 2.0 * slice * (tile_other + 2) : 0.0;
     const double M = lds_doubles - stream;
     const double ratio_opt = beta_c / beta_stream;   // kc / rows at the optimum
     int best_r = 0, best_k = 0;
     double best_e = -1.0, best_d = 0.0;
-    for (int r = 64; r <= 512; r += 64) {
+    for (int r = row_step; r <= 512; r += row_step) {
         const int kmax = (int)std::floor(M / r) - 1;   // r (kc + 1) <= M
         const int kcand = (kmax / slice) * slice;
         if (kcand < slice) continue;
@@ -89,15 +92,20 @@ constexpr double kBetaStream = 1.0, kBetaC = 2.0 * 39.3 / 8.0;
 static bool lds_blocks_match() {
     static const bool ok = [] {
         int ra = 0, ka = 0, rb = 0, kb = 0;
-        lds_block(kLdsDoubles, kKSlds, 0, kBetaStream, kBetaC, &ra, &ka);      // A block alone in LDS
-        lds_block(kLdsDoubles, kKSlds, kMTb, kBetaStream, kBetaC, &rb, &kb);   // B block, A slices of kMTb
-        return ra == kMCa && ka == kKCa && rb == kNCb && kb == kKC;
+        // A block alone in its workgroup's share of LDS; B block beside A
+        // slices of kMTb, one workgroup per CU
+        int r1 = 0, k1 = 0;
+        lds_block(kLdsDoubles / kWGsPerCuA, kKSlds, 0, 32, kBetaStream, kBetaC, &ra, &ka);
+        lds_block(kLdsDoubles, kKSlds, 0, 64, kBetaStream, kBetaC, &r1, &k1);   // a CU to itself
+        lds_block(kLdsDoubles, kKSlds, kMTb, 64, kBetaStream, kBetaC, &rb, &kb);
+        return ra == kMCa && ka == kKCa && r1 == kMCa1 && k1 == kKCa && rb == kNCb && kb == kKC;
     }();
     return ok;
 }
 
 // Column tiles per workgroup (the inner loop over the resident block): the
-// largest of 4, 2, 1 that still gives two rounds of workgroups on the chip.
+// largest of 4, 2, 1 that still gives 512 workgroups (two rounds on the chip
+// of the B-resident kernel, one of the A-resident kernel).
 static int tiles_per_wg(int64_t blocks, int64_t tiles_other) {
     for (int j = 4; j > 1; j /= 2)
         if (blocks * cdiv(tiles_other, j) >= 2 * kCUs) return j;
@@ -165,7 +173,7 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             break;
         }
         case MOMMS_A2C0: {
-            // Goto: n by nc -> k by kc (pack B panel) -> m by 64 (A block
+            // Goto: n by nc -> k by kc (pack B panel) -> m by 32 (A block
             // in LDS) -> n by 128 across workgroups (the parallel 2nd loop).
             p->kernel = 1;
             p->mt = kMCa;
@@ -183,7 +191,7 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             break;
         }
         case MOMMS_B3A2C0: {
-            // n by nc3 -> k by kc3 (B block in one XCD's L2) -> m by 64 (A
+            // n by nc3 -> k by kc3 (B block in one XCD's L2) -> m by 32 (A
             // block in LDS) -> k by kc -> n by 128.  nc3 = nj tiles (at most
             // 512: a 288 x 512 B block is 1.2 MiB of the 4 MiB L2).
             p->kernel = 1;
@@ -224,8 +232,8 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             // n, m by a C block per XCD -> k by kc -> m by 64 (A block in
             // LDS) -> n by 128; one launch, every workgroup walks all of k.
             // Sec. 4.1 at level 3: the C block is the tiles one XCD runs at
-            // once (32 workgroups, one per CU: 32 tiles of 64 x 128, 2 MiB,
-            // half the L2).  Between two visits of a C tile the XCD also
+            // once (32 workgroups, one per CU, so that they stay in step
+            // through k: 32 tiles of 64 x 128, 2 MiB, half the L2).  Between two visits of a C tile the XCD also
             // reads one chunk's guests, the A rows (rows x kc) and B columns
             // (kc x cols) of the block, and they must fit the other half.
             // The block's shape (group_m tile rows, swept column by column)
@@ -233,17 +241,17 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             // slices, up to the LDS block's depth, whose guests fit (8192^2:
             // 8 x 4 tiles = 512 x 512, kc = 256).
             p->kernel = 1;
-            p->mt = kMCa;
+            p->mt = kMCa1;
             p->nt = kNTa;
             p->ks = kKSlds;
             p->nj = 1;
             p->xcd_aware = 1;
             const int64_t tm = cdiv(m, p->mt), tn = cdiv(n, p->nt);
             double best = -1.0;
-            for (int g = 1; g <= kWGsPerXcdLds; g *= 2) {
+            for (int g = 1; g <= kWGsPerXcdA1; g *= 2) {
                 const int gm = (int)(g < tm ? g : (tm > 0 ? tm : 1));
-                const double cols = std::fmin((double)tn, std::ceil((double)kWGsPerXcdLds / gm));
-                const double rows = std::fmin((double)tm, std::ceil((double)kWGsPerXcdLds / cols));
+                const double cols = std::fmin((double)tn, std::ceil((double)kWGsPerXcdA1 / gm));
+                const double rows = std::fmin((double)tm, std::ceil((double)kWGsPerXcdA1 / cols));
                 const double edge = rows * p->mt + cols * p->nt;
                 if (best < 0.0 || edge < best) {
                     best = edge;
@@ -261,7 +269,7 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             break;
         }
         case MOMMS_C4A2C0: {
-            // m, n by a 4096 x 4096 C block (MALL) -> k by kc -> m by 64 (A
+            // m, n by a 4096 x 4096 C block (MALL) -> k by kc -> m by 32 (A
             // block in LDS) -> n by 128 across workgroups.
             p->kernel = 1;
             p->mt = kMCa;
@@ -405,16 +413,17 @@ size_t momms_workspace_size(int64_t m, int64_t n, int64_t k, int member) {
 }
 
 
-int momms_lds_block(double lds_bytes, int slice, int tile_other, double beta_stream, double beta_c, int* rows,
-                    int* kc) {
+int momms_lds_block(double lds_bytes, int slice, int tile_other, int row_step, double beta_stream, double beta_c,
+                    int* rows, int* kc) {
     if (!(lds_bytes > 0) || !std::isfinite(lds_bytes)) return -1;
     if (slice < 1) return -2;
     if (tile_other < 0) return -3;
-    if (!(beta_stream > 0) || !std::isfinite(beta_stream)) return -4;
-    if (!(beta_c > 0) || !std::isfinite(beta_c)) return -5;
-    if (!rows) return -6;
-    if (!kc) return -7;
-    momms::lds_block(lds_bytes / 8.0, slice, tile_other, beta_stream, beta_c, rows, kc);
+    if (row_step < 16 || row_step % 16 != 0) return -4;
+    if (!(beta_stream > 0) || !std::isfinite(beta_stream)) return -5;
+    if (!(beta_c > 0) || !std::isfinite(beta_c)) return -6;
+    if (!rows) return -7;
+    if (!kc) return -8;
+    momms::lds_block(lds_bytes / 8.0, slice, tile_other, row_step, beta_stream, beta_c, rows, kc);
     return 0;
 }
 

@@ -39,6 +39,7 @@ constexpr int kSlabElems = kT * kSlab;
 typedef TileCfg<128, 128, 16, 2, 2> Cfg128;
 typedef TileCfg<64, 64, 16, 2, 2> Cfg64;
 typedef TileCfg<kMCa, kNTa, kKSlds, kMCa / 32, kNTa / 32> CfgA;   // the LDS-resident A-block kernel
+typedef TileCfg<kMCa1, kNTa, kKSlds, kMCa1 / 32, kNTa / 32> CfgA1;   // the same, one per CU (C3A2C0)
 typedef TileCfg<kMTb, kNCb, kKSlds, kMTb / 32, kNCb / 32> CfgB;   // the LDS-resident B-block kernel
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -212,27 +213,30 @@ static void launch(const TArgs& a, int tile, int64_t s0, int64_t s1, double beta
 
 // The LDS-resident A-block kernel on tile-major operands: A from its 128 x 16
 // slabs, B k-slices straight from the tile-major column panels (the panel
-// height is the padded k).  s covers granules of kMCa rows x nj column tiles.
+// height is the padded k).  s covers granules of Cfg::MT rows x nj column
+// tiles.
+template <class Cfg = CfgA>
 static void launch_a2(const TArgs& a, int64_t k0, int64_t k1, const Sched& s, int nj, int kc, int64_t slabs) {
     const int grid = s.tiles_m * s.tiles_n;
     if (grid <= 0) return;
-    hipLaunchKernelGGL((k_a2<CfgA, kKCa, false, false, true, true>), dim3(grid), dim3(CfgA::THREADS), 0, a.st, a.M,
+    hipLaunchKernelGGL((k_a2<Cfg, kKCa, false, false, true, true>), dim3(grid), dim3(Cfg::THREADS), 0, a.st, a.M,
                        a.N, k0, k1, a.alpha, a.At, slabs, a.Bt, a.kp, a.beta, a.C, a.ldc, s, nj, (int64_t)0,
                        (int64_t)0, kc);
 }
 
-// Granules of kMCa rows x nj column tiles (kNTa wide) over [m_off, m_lim) x
+// Granules of rows x nj column tiles (kNTa wide) over [m_off, m_lim) x
 // [n_off, n_lim).
 static Sched granules(int64_t m_off, int64_t n_off, int64_t m_lim, int64_t n_lim, int nj, int64_t group_m,
-                      bool xcd) {
-    Sched s = sched_of(m_off, n_off, m_lim, n_lim, kMCa, group_m, xcd);
+                      bool xcd, int64_t rows = kMCa) {
+    Sched s = sched_of(m_off, n_off, m_lim, n_lim, rows, group_m, xcd);
     s.tiles_n = (int)cdiv(n_lim - n_off, (int64_t)nj * kNTa);
     return s;
 }
 
 // The loop nests of the members, as in the row-major path.
 static int run(const momms_plan& p, const TArgs& a, int64_t K) {
-    if (p.kernel == 1 && !a2_chunk_ok(p.kc)) return MOMMS_ERR_INTERNAL;
+    if (p.kernel == 1 && (!a2_chunk_ok(p.kc) || p.mt != (p.member == MOMMS_C3A2C0 ? CfgA1::MT : CfgA::MT)))
+        return MOMMS_ERR_INTERNAL;
     const int64_t M = a.M, N = a.N, slabs = cdiv(K, kSlab);
     const int t = p.mt;
     switch (p.member) {
@@ -298,7 +302,7 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
         }
         case MOMMS_C3A2C0:
             // XCD-grouped C tiles, each walking all of k with its A block in LDS
-            launch_a2(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true), 1, (int)p.kc, slabs);
+            launch_a2<CfgA1>(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true, kMCa1), 1, (int)p.kc, slabs);
             break;
         case MOMMS_C4A2C0:
             // m, n by the MALL-resident C block -> k by kc -> the kernel

@@ -111,7 +111,7 @@ def test_plans_are_consistent():
     for name in mm.FAMILY:
         p = mm.member_plan(name, 8192, 8192, 8192)
         assert p["member"] == mm.MEMBERS[name]
-        assert p["mt"] in (64, 128) and p["nt"] in (64, 128)
+        assert p["mt"] in (32, 64, 128) and p["nt"] in (64, 128)
         assert p["launches"] >= 1 and p["workgroups"] >= 1
         assert 1 <= p["k_range"] <= 8192
     assert mm.member_plan("AUTO", 8192, 8192, 8192)["member"] == mm.MEMBERS[mm.select_member(8192, 8192, 8192)]

@@ -124,42 +124,56 @@ def test_lds_block_solver():
     # (8 TB/s), so a C element costs 2 * 39.3 / 8 streamed elements.
     lds, bc = 160 * 1024, 2 * 39.3 / 8
     # a block beside two 32-deep slices of a 128-wide streamed panel (the
-    # B-resident kernel keeps its A slices in LDS) ...
-    assert mm.lds_block(lds, 32, 128, 1.0, bc) == (64, 160)
+    # B-resident kernel keeps its A slices in LDS, one workgroup per CU, two
+    # columns of waves) ...
+    assert mm.lds_block(lds, 32, 128, 64, 1.0, bc) == (64, 160)
     # ... and a block alone (the A-resident kernel streams B through
-    # registers): 64 x 288, since 64 x 319 is the most that fits and k_c
-    # steps by the slice
-    assert mm.lds_block(lds, 32, 0, 1.0, bc) == (64, 288)
+    # registers) in half of it (two workgroups per CU, one row of waves):
+    # 32 x 288, since 32 x 319 is the most that fits and k_c steps by the
+    # slice; the continuous optimum there has 32.3 rows
+    assert mm.lds_block(lds / 2, 32, 0, 32, 1.0, bc) == (32, 288)
+    mc, kc = mm.balanced_block(lds / 2 / 8, 1.0, bc)
+    assert round(mc) == 32
+    # with a CU to itself (C3A2C0, whose XCD's workgroups must stay in step
+    # for its C block to stay in the L2) the same block has 64 rows
+    assert mm.lds_block(lds, 32, 0, 64, 1.0, bc) == (64, 288)
     # the plans of the LDS-resident members use exactly those blocks, with
-    # 32-deep streamed slices
+    # 32-deep streamed slices (C3A2C0 takes a shallower chunk of its block)
     for name in ("A2C0", "B3A2C0", "C4A2C0"):
         p = mm.member_plan(name, 8192, 8192, 8192)
-        assert (p["mt"], p["kc"], p["ks"]) == (64, 288, 32), name
+        assert (p["mt"], p["kc"], p["ks"]) == (32, 288, 32), name
+    p = mm.member_plan("C3A2C0", 8192, 8192, 8192)
+    assert (p["mt"], p["kc"], p["ks"]) == (64, 256, 32)
     p = mm.member_plan("A3B2C0", 8192, 8192, 8192)
     assert (p["nt"], p["kc"], p["ks"]) == (64, 160, 32)
     # equal costs and thin slices: the block comes out nearly square
-    # (Sec. 2.4), 128 x 136 within capacity
-    assert mm.lds_block(lds, 8, 128, 1.0, 1.0) == (128, 136)
+    # (Sec. 2.4), 128 x 136 within capacity, on either row grid
+    assert mm.lds_block(lds, 8, 128, 64, 1.0, 1.0) == (128, 136)
+    assert mm.lds_block(lds, 8, 128, 32, 1.0, 1.0) == (128, 136)
     # every answer fits: block (pitch kc + 1) plus two streamed slices
-    for b in (8 * 1024, 64 * 1024, 160 * 1024, 1 << 20):
-        for ratio in (0.25, 1.0, 2.0, 10.0):
-            r, k = mm.lds_block(b, 8, 128, 1.0, ratio)
-            if r:
-                assert r % 64 == 0 and k % 8 == 0
-                assert 8 * (r * (k + 1) + 2 * 8 * 130) <= b
-            r0, k0 = mm.lds_block(b, 8, 0, 1.0, ratio)
-            if r0:
-                assert r0 % 64 == 0 and k0 % 8 == 0 and 8 * r0 * (k0 + 1) <= b
-                # with the slices gone the block can only grow
-                assert 2.0 * r0 * k0 / (k0 + ratio * r0) >= 2.0 * r * k / (k + ratio * r) - 1e-9 if r else True
+    for step in (32, 64):
+        for b in (8 * 1024, 64 * 1024, 160 * 1024, 1 << 20):
+            for ratio in (0.25, 1.0, 2.0, 10.0):
+                r, k = mm.lds_block(b, 8, 128, step, 1.0, ratio)
+                if r:
+                    assert r % step == 0 and k % 8 == 0
+                    assert 8 * (r * (k + 1) + 2 * 8 * 130) <= b
+                r0, k0 = mm.lds_block(b, 8, 0, step, 1.0, ratio)
+                if r0:
+                    assert r0 % step == 0 and k0 % 8 == 0 and 8 * r0 * (k0 + 1) <= b
+                    # with the slices gone the block can only grow
+                    assert 2.0 * r0 * k0 / (k0 + ratio * r0) >= 2.0 * r * k / (k + ratio * r) - 1e-9 if r else True
     # C dearer -> the block deepens (kc / rows grows), never the reverse
-    ratios = [mm.lds_block(1 << 20, 8, 128, 1.0, c) for c in (0.5, 1.0, 4.0, 16.0)]
+    ratios = [mm.lds_block(1 << 20, 8, 128, 64, 1.0, c) for c in (0.5, 1.0, 4.0, 16.0)]
     depth = [k / r for r, k in ratios]
     assert depth == sorted(depth)
     with pytest.raises(Exception):
-        mm.lds_block(-1, 8, 128, 1.0, 1.0)
+        mm.lds_block(-1, 8, 128, 64, 1.0, 1.0)
     with pytest.raises(Exception):
-        mm.lds_block(1 << 20, 8, -1, 1.0, 1.0)
+        mm.lds_block(1 << 20, 8, -1, 64, 1.0, 1.0)
+    for bad_step in (0, 8, 40):
+        with pytest.raises(Exception):
+            mm.lds_block(1 << 20, 8, 0, bad_step, 1.0, 1.0)
 
 
 L2_HALF = 0.5 * 4 * 1024 * 1024   # bytes: the Sec. 4.1 share of one XCD's L2 a block may take
@@ -212,9 +226,9 @@ def member_counts(name, shape):
         ic3 = cdiv(m, p["mc3"])
         ab = {"a_reads": r["a_reads"], "b_reads": r["b_reads"] if 8 * p["kc3"] * n > L2_HALF else k * n * min(ic3, 8)}
     elif name == "C3A2C0":
-        # the C block of one XCD round (group_m x 32 / group_m tiles) is
-        # Resident C; its lines stay for reads (C read once) but are written
-        # back after every pass
+        # the C block of one XCD round (32 workgroups, one per CU: group_m x
+        # 32 / group_m tiles) is Resident C; its lines stay for reads (C read
+        # once) but are written back after every pass
         cols = min(tn, cdiv(32, p["group_m"]))
         rows = min(tm, cdiv(32, cols))
         ab = resident("C", shape, rows * p["mt"], cols * p["nt"])
@@ -241,7 +255,7 @@ def test_every_member_model_is_its_resident_counts(name, shape):
 
 def test_c3a2c0_block_fits_l2():
     """Sec. 4.1 at level 3 for C3A2C0: the C block is the 32 tiles of 64 x 128
-    one XCD runs at once (2 MiB, half of its 4 MiB L2), and the chunk's guests
+    one XCD runs at once (one per CU; 2 MiB, half of its 4 MiB L2), and the chunk's guests
     beside it, the block's A rows (rows x kc) and B columns (kc x cols), take
     at most the other half, with kc as deep as that allows (in 32-deep
     slices, at most the 288 of the LDS block)."""
@@ -261,6 +275,7 @@ def test_c3a2c0_block_fits_l2():
         assert 8 * p["kc"] * edge <= half, shape
         assert p["kc"] == 288 or 8 * (p["kc"] + 32) * edge > half, shape
         # the block is the tiles one XCD holds at once, clipped to the matrix
+        assert p["mt"] == 64
         assert p["mc3"] % 64 == 0 and p["nc3"] % 128 == 0
         assert (p["mc3"] // 64) * (p["nc3"] // 128) <= 32
         assert p["mc3"] <= max(64, -(-m // 64) * 64) and p["nc3"] <= max(128, -(-n // 128) * 128)
