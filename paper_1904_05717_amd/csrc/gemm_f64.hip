@@ -102,7 +102,8 @@ static void launch_a2_t(const Args& a, int64_t k0, int64_t k1, const Sched& s, i
 
 // beta is applied by the kernel to the pass whose k chunk starts at 0; the
 // kernel walks [k0, k1) in chunks of kc (the plan's, checked by run()).  Cfg
-// is CfgA1 for C3A2C0 (never packed), CfgA for the other members.
+// is CfgA1 for C3A2C0 on problems that fill the chip (never packed), CfgA
+// otherwise.
 template <class Cfg = CfgA>
 static void launch_a2(const Args& a, int64_t k0, int64_t k1, const Sched& s, int nj, int kc, const double* packed,
                       int64_t pk0, int64_t pn0) {
@@ -148,7 +149,7 @@ static void launch_pack_b(const Args& a, int64_t pk0, int64_t pn0, int64_t ncw, 
 // Runs the loop nest of plan p.  Returns 0 or a hipError_t.
 static int run_member(const momms_plan& p, const Args& a, void* ws) {
     const int64_t M = a.M, N = a.N, K = a.K;
-    if (p.kernel == 1 && (!a2_chunk_ok(p.kc) || p.mt != (p.member == MOMMS_C3A2C0 ? CfgA1::MT : CfgA::MT)))
+    if (p.kernel == 1 && (!a2_chunk_ok(p.kc) || !(p.mt == CfgA::MT || (p.member == MOMMS_C3A2C0 && p.mt == CfgA1::MT))))
         return MOMMS_ERR_INTERNAL;
     switch (p.member) {
         case MOMMS_C0: {
@@ -223,7 +224,8 @@ static int run_member(const momms_plan& p, const Args& a, void* ws) {
         }
         case MOMMS_C3A2C0: {
             const Sched s = make_sched(0, 0, M, N, p.mt, p.nt, p.group_m, true);
-            launch_a2<CfgA1>(a, 0, K, s, 1, (int)p.kc, nullptr, 0, 0);
+            if (p.mt == CfgA1::MT) launch_a2<CfgA1>(a, 0, K, s, 1, (int)p.kc, nullptr, 0, 0);
+            else launch_a2<CfgA>(a, 0, K, s, 1, (int)p.kc, nullptr, 0, 0);
             break;
         }
         case MOMMS_C4A2C0: {

@@ -161,16 +161,18 @@ int model_bytes(int member, int64_t m, int64_t n, int64_t k, double beta, int pa
             break;
         }
         case MOMMS_C3A2C0: {
-            // One XCD round is 32 workgroups (one per CU) in the grouped
-            // order (group_m tile rows swept column by column): a C block of
-            // cols = min(tn, 32 / group_m) tile columns and 32 / cols tile
+            // One XCD round is 32 workgroups (one per CU; 64 for the
+            // two-per-CU block of small problems) in the grouped order
+            // (group_m tile rows swept column by column): a C block of cols =
+            // min(tn, per_xcd / group_m) tile columns and per_xcd / cols tile
             // rows, which is
             // Resident C for A and B.  Its lines stay in the L2 for reads (C
             // read once), but the L2 writes the updated lines back after
             // every kc pass (measured: the write traffic is C once per pass),
             // so C is written once per pass.
-            const double cols = std::fmin(tn, std::ceil((double)kWGsPerXcdA1 / (double)p.group_m));
-            const double rows = std::fmin(tm, std::ceil((double)kWGsPerXcdA1 / cols));
+            const double per_xcd = p.mt == kMCa1 ? kWGsPerXcdA1 : 32.0 * kWGsPerCuA;
+            const double cols = std::fmin(tn, std::ceil(per_xcd / (double)p.group_m));
+            const double rows = std::fmin(tm, std::ceil(per_xcd / cols));
             double cnt[4];
             resident_counts('C', m, n, k, (int64_t)rows * p.mt, (int64_t)cols * p.nt, beta, cnt);
             a = cnt[0];

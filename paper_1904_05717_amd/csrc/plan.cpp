@@ -239,19 +239,25 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             // The block's shape (group_m tile rows, swept column by column)
             // minimises rows + cols; kc is then the deepest whole number of
             // slices, up to the LDS block's depth, whose guests fit (8192^2:
-            // 8 x 4 tiles = 512 x 512, kc = 256).
+            // 8 x 4 tiles = 512 x 512, kc = 256).  When tiles of 64 rows
+            // would not give every CU one, the two-per-CU block of 32 rows
+            // runs instead: the launch then fits the chip at once, so every
+            // workgroup is resident from its start to its end and none can
+            // fall behind a round.
             p->kernel = 1;
-            p->mt = kMCa1;
+            const bool fill = cdiv(m, kMCa1) * cdiv(n, kNTa) >= kCUs;
+            p->mt = fill ? kMCa1 : kMCa;
             p->nt = kNTa;
             p->ks = kKSlds;
             p->nj = 1;
             p->xcd_aware = 1;
+            const int per_xcd = fill ? kWGsPerXcdA1 : 32 * kWGsPerCuA;
             const int64_t tm = cdiv(m, p->mt), tn = cdiv(n, p->nt);
             double best = -1.0;
-            for (int g = 1; g <= kWGsPerXcdA1; g *= 2) {
+            for (int g = 1; g <= per_xcd; g *= 2) {
                 const int gm = (int)(g < tm ? g : (tm > 0 ? tm : 1));
-                const double cols = std::fmin((double)tn, std::ceil((double)kWGsPerXcdA1 / gm));
-                const double rows = std::fmin((double)tm, std::ceil((double)kWGsPerXcdA1 / cols));
+                const double cols = std::fmin((double)tn, std::ceil((double)per_xcd / gm));
+                const double rows = std::fmin((double)tm, std::ceil((double)per_xcd / cols));
                 const double edge = rows * p->mt + cols * p->nt;
                 if (best < 0.0 || edge < best) {
                     best = edge;

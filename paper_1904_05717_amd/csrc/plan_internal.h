@@ -20,7 +20,9 @@ constexpr double kXcdsH = 8.0;         // XCD count as a double for the model
 // A-resident kernel with a CU to itself (block kMCa1 x kKCa): its C block is
 // the tiles an XCD runs at once, which stay in the L2 only while those
 // workgroups move through k together, and two workgroups on one CU drift
-// apart (the older one's instructions issue first).
+// apart (the older one's instructions issue first).  On problems too small
+// to give every CU a 64-row tile it runs the two-per-CU block, and the whole
+// launch is resident at once.
 constexpr int kKSlds = 32;             // k depth of a streamed slice of the LDS-resident kernels
 constexpr int64_t kKCa = 288;          // k depth of the A-resident block
 constexpr int64_t kKC = 160;           // k depth of the B-resident block
@@ -31,7 +33,7 @@ constexpr int kMTb = 128, kNCb = 64;   // B-resident kernel: C tile rows, block 
 constexpr int64_t kGotoNc = 1024;      // Goto's n_c: its packed k_c x n_c panel is 2.25 MiB, about half an XCD's L2
 constexpr int kWGsPerXcd128 = 64;      // 128x128 register tile: 2 workgroups per CU
 constexpr int kWGsPerXcd64 = 128;      // 64x64 register tile: 4 workgroups per CU (LDS-bound)
-constexpr int kWGsPerXcdA1 = 32;      // C3A2C0: workgroups one XCD runs at once (one per CU)
+constexpr int kWGsPerXcdA1 = 32;      // C3A2C0 with a CU each: workgroups one XCD runs at once
 constexpr double kL2Bytes = 4.0 * 1024 * 1024;   // one XCD's L2
 
 // A chunk depth the A-resident kernel can run: a whole number of streamed

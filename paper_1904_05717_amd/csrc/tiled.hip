@@ -235,7 +235,7 @@ static Sched granules(int64_t m_off, int64_t n_off, int64_t m_lim, int64_t n_lim
 
 // The loop nests of the members, as in the row-major path.
 static int run(const momms_plan& p, const TArgs& a, int64_t K) {
-    if (p.kernel == 1 && (!a2_chunk_ok(p.kc) || p.mt != (p.member == MOMMS_C3A2C0 ? CfgA1::MT : CfgA::MT)))
+    if (p.kernel == 1 && (!a2_chunk_ok(p.kc) || !(p.mt == CfgA::MT || (p.member == MOMMS_C3A2C0 && p.mt == CfgA1::MT))))
         return MOMMS_ERR_INTERNAL;
     const int64_t M = a.M, N = a.N, slabs = cdiv(K, kSlab);
     const int t = p.mt;
@@ -302,7 +302,10 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
         }
         case MOMMS_C3A2C0:
             // XCD-grouped C tiles, each walking all of k with its A block in LDS
-            launch_a2<CfgA1>(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true, kMCa1), 1, (int)p.kc, slabs);
+            if (p.mt == CfgA1::MT)
+                launch_a2<CfgA1>(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true, kMCa1), 1, (int)p.kc, slabs);
+            else
+                launch_a2<CfgA>(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true), 1, (int)p.kc, slabs);
             break;
         case MOMMS_C4A2C0:
             // m, n by the MALL-resident C block -> k by kc -> the kernel

@@ -83,6 +83,28 @@ def test_c3a2c0_shallow_chunks(shape, trans):
             assert_within_bound(got, want, X, Y, Z, 1.5, -0.5, f"C3A2C0 {shape} {trans}")
 
 
+@pytest.mark.parametrize("trans", [(False, False), (True, True)])
+def test_c3a2c0_one_workgroup_per_cu_block(trans):
+    # C3A2C0 runs the 64-row, one-workgroup-per-CU form of the A-resident
+    # kernel once its tiles fill the chip (the smaller shapes above run the
+    # 32-row, two-per-CU form); here 2000 x 1100 gives 32 x 9 such tiles,
+    # ragged in both directions, and k = 300 one full chunk and a ragged one
+    m, n, k = 2000, 1100, 300
+    p = mm.member_plan("C3A2C0", m, n, k)
+    assert p["mt"] == 64 and p["workgroups"] >= 256 and k % p["kc"] != 0, p
+    ta, tb = trans
+    A, B, C = workloads.gemm_operands(m, n, k)
+    Ai, Bi, _ = workloads.gemm_operands(m, n, k, kind="int")
+    for X, Y, Z, exact in ((A, B, C, False), (Ai, Bi, np.zeros((m, n)), True)):
+        alpha, beta = (1.0, 1.0) if exact else (1.5, -0.5)
+        want = oracle.gemm(X, Y, Z, alpha, beta)
+        got = run(X.T.copy() if ta else X, Y.T.copy() if tb else Y, Z, alpha, beta, "C3A2C0", transA=ta, transB=tb)
+        if exact:
+            np.testing.assert_array_equal(got, want)
+        else:
+            assert_within_bound(got, want, X, Y, Z, alpha, beta, f"C3A2C0 64-row {trans}")
+
+
 @pytest.mark.parametrize("member", FAMILY)
 @pytest.mark.parametrize("shape", [(300, 280, 260), (129, 257, 131)])
 def test_ragged_alpha_beta(member, shape):

@@ -226,11 +226,13 @@ def member_counts(name, shape):
         ic3 = cdiv(m, p["mc3"])
         ab = {"a_reads": r["a_reads"], "b_reads": r["b_reads"] if 8 * p["kc3"] * n > L2_HALF else k * n * min(ic3, 8)}
     elif name == "C3A2C0":
-        # the C block of one XCD round (32 workgroups, one per CU: group_m x
-        # 32 / group_m tiles) is Resident C; its lines stay for reads (C read
-        # once) but are written back after every pass
-        cols = min(tn, cdiv(32, p["group_m"]))
-        rows = min(tm, cdiv(32, cols))
+        # the C block of one XCD round (32 workgroups, one per CU, or 64 of
+        # the 32-row block on problems that leave CUs without a 64-row tile:
+        # group_m x per_xcd / group_m tiles) is Resident C; its lines stay
+        # for reads (C read once) but are written back after every pass
+        per_xcd = 32 if p["mt"] == 64 else 64
+        cols = min(tn, cdiv(per_xcd, p["group_m"]))
+        rows = min(tm, cdiv(per_xcd, cols))
         ab = resident("C", shape, rows * p["mt"], cols * p["nt"])
         c = {"c_reads": m * n, "c_writes": m * n * passes}
     elif name == "C4A2C0":
@@ -266,6 +268,10 @@ def test_c3a2c0_block_fits_l2():
     assert (p["mc3"], p["nc3"], p["kc"], p["k_range"]) == (512, 512, 256, 256)
     p = mm.member_plan("C3A2C0", 16384, 256, 16384)
     assert (p["mc3"], p["nc3"], p["kc"]) == (1024, 256, 192)
+    # 1024^3: 128 tiles of 64 rows would leave half the CUs idle, so 256 of
+    # 32 rows, two per CU; an XCD round of 64 is a 16 x 4 block, 512 x 512
+    p = mm.member_plan("C3A2C0", 1024, 1024, 1024)
+    assert (p["mt"], p["mc3"], p["nc3"], p["kc"], p["workgroups"]) == (32, 512, 512, 256, 256)
     for shape in [(8192, 8192, 8192), (16384, 16384, 256), (16384, 256, 16384), (1024, 1024, 1024),
                   (100, 3000, 500), (3000, 100, 500), (64, 128, 4096), (4096, 8192, 2048)]:
         p = mm.member_plan("C3A2C0", *shape)
@@ -275,8 +281,12 @@ def test_c3a2c0_block_fits_l2():
         assert 8 * p["kc"] * edge <= half, shape
         assert p["kc"] == 288 or 8 * (p["kc"] + 32) * edge > half, shape
         # the block is the tiles one XCD holds at once, clipped to the matrix
-        assert p["mt"] == 64
-        assert p["mc3"] % 64 == 0 and p["nc3"] % 128 == 0
-        assert (p["mc3"] // 64) * (p["nc3"] // 128) <= 32
-        assert p["mc3"] <= max(64, -(-m // 64) * 64) and p["nc3"] <= max(128, -(-n // 128) * 128)
+        # one 64-row workgroup per CU, or, where those tiles would leave CUs
+        # idle, two 32-row ones per CU
+        fill = -(-m // 64) * -(-n // 128) >= 256
+        t, per_xcd = (64, 32) if fill else (32, 64)
+        assert p["mt"] == t, shape
+        assert p["mc3"] % t == 0 and p["nc3"] % 128 == 0
+        assert (p["mc3"] // t) * (p["nc3"] // 128) <= per_xcd
+        assert p["mc3"] <= max(t, -(-m // t) * t) and p["nc3"] <= max(128, -(-n // 128) * 128)
         assert p["k_range"] == min(p["kc"], k)

@@ -52,7 +52,7 @@ def test_layout_positions_and_padding():
 
 @pytest.mark.parametrize("member", MEMBERS)
 @pytest.mark.parametrize("shape", [(256, 256, 256), (300, 290, 700), (129, 65, 33), (1, 1, 1), (640, 1100, 1500),
-                                   (1000, 256, 1000)])
+                                   (1000, 256, 1000), (2000, 1100, 300)])
 def test_equals_row_major_and_within_bound(member, shape):
     m, n, k = shape
     A, B, C = workloads.gemm_operands(m, n, k)
