@@ -229,14 +229,15 @@ static int run_member(const momms_plan& p, const Args& a, void* ws) {
             break;
         }
         case MOMMS_C4A2C0: {
-            // m, n by the MALL-resident C block -> k by kc (host) -> kernel.
+            // m, n by the MALL-resident C block -> k by kc3 (host) -> kernel
+            // (k by kc inside).
             for (int64_t ib = 0; ib < M; ib += p.mc4) {
                 const int64_t ie = ib + p.mc4 < M ? ib + p.mc4 : M;
                 for (int64_t jb = 0; jb < N; jb += p.nc4) {
                     const int64_t je = jb + p.nc4 < N ? jb + p.nc4 : N;
                     const Sched s = make_sched(ib, jb, ie, je, p.mt, (int64_t)p.nj * p.nt, 1, false);
-                    for (int64_t pc = 0; pc < K; pc += p.kc) {
-                        const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
+                    for (int64_t pc = 0; pc < K; pc += p.kc3) {
+                        const int64_t pe = pc + p.kc3 < K ? pc + p.kc3 : K;
                         launch_a2(a, pc, pe, s, p.nj, (int)p.kc, nullptr, 0, 0);
                     }
                 }

@@ -276,17 +276,22 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
         }
         case MOMMS_C4A2C0: {
             // m, n by a 4096 x 4096 C block (MALL) -> k by kc -> m by 32 (A
-            // block in LDS) -> n by 128 across workgroups.
+            // block in LDS) -> n by 128 across workgroups.  One launch walks
+            // four chunks (kc3 = 4 kc) on its granules: with one chunk, a
+            // launch of a block holds two rounds of workgroups and its tail
+            // leaves the chip idle between launches; the data each chunk
+            // moves is the same.
             p->kernel = 1;
             p->mt = kMCa;
             p->nt = kNTa;
             p->ks = kKSlds;
             p->kc = kKCa;
+            p->kc3 = 4 * kKCa;
             p->mc4 = p->nc4 = 4096;
             p->nj = tiles_per_wg(cdiv(m < p->mc4 ? m : p->mc4, p->mt), cdiv(n < p->nc4 ? n : p->nc4, p->nt));
             p->k_range = p->kc < k ? p->kc : k;
             const int64_t blocks = cdiv(m, p->mc4) * cdiv(n, p->nc4);
-            const int64_t pcs = k > 0 ? cdiv(k, p->kc) : 1;
+            const int64_t pcs = k > 0 ? cdiv(k, p->kc3) : 1;
             p->launches = blocks * pcs;
             const int64_t mw = m < p->mc4 ? m : p->mc4, nw = n < p->nc4 ? n : p->nc4;
             p->workgroups = p->launches * cdiv(mw, p->mt) * cdiv(nw, (int64_t)p->nj * p->nt);

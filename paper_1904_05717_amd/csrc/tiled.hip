@@ -308,14 +308,14 @@ static int run(const momms_plan& p, const TArgs& a, int64_t K) {
                 launch_a2<CfgA>(a, 0, K, granules(0, 0, M, N, 1, p.group_m, true), 1, (int)p.kc, slabs);
             break;
         case MOMMS_C4A2C0:
-            // m, n by the MALL-resident C block -> k by kc -> the kernel
+            // m, n by the MALL-resident C block -> k by kc3 -> the kernel
             for (int64_t ib = 0; ib < M; ib += p.mc4) {
                 const int64_t ie = ib + p.mc4 < M ? ib + p.mc4 : M;
                 for (int64_t jb = 0; jb < N; jb += p.nc4) {
                     const int64_t je = jb + p.nc4 < N ? jb + p.nc4 : N;
                     const Sched s = granules(ib, jb, ie, je, p.nj, 1, false);
-                    for (int64_t pc = 0; pc < K; pc += p.kc) {
-                        const int64_t pe = pc + p.kc < K ? pc + p.kc : K;
+                    for (int64_t pc = 0; pc < K; pc += p.kc3) {
+                        const int64_t pe = pc + p.kc3 < K ? pc + p.kc3 : K;
                         launch_a2(a, pc, pe, s, p.nj, (int)p.kc, slabs);
                     }
                 }

@@ -105,6 +105,21 @@ def test_c3a2c0_one_workgroup_per_cu_block(trans):
             assert_within_bound(got, want, X, Y, Z, alpha, beta, f"C3A2C0 64-row {trans}")
 
 
+def test_c4a2c0_chunks_per_launch():
+    # C4A2C0's host loop steps k by kc3 (several chunks per launch) and the
+    # kernel by kc inside: k = 2600 is two whole launches and a ragged third
+    # (one whole chunk and an 8-deep one)
+    m, n, k = 300, 700, 2600
+    p = mm.member_plan("C4A2C0", m, n, k)
+    assert p["kc3"] > p["kc"] and k % p["kc3"] > p["kc"] and k % p["kc3"] % p["kc"] != 0, p
+    A, B, C = workloads.gemm_operands(m, n, k)
+    Ai, Bi, _ = workloads.gemm_operands(m, n, k, kind="int")
+    assert_within_bound(run(A, B, C, 1.5, -0.5, "C4A2C0"), oracle.gemm(A, B, C, 1.5, -0.5), A, B, C, 1.5, -0.5,
+                        "C4A2C0")
+    Z = np.zeros((m, n))
+    np.testing.assert_array_equal(run(Ai, Bi, Z, 1.0, 1.0, "C4A2C0"), oracle.gemm(Ai, Bi, Z, 1.0, 1.0))
+
+
 @pytest.mark.parametrize("member", FAMILY)
 @pytest.mark.parametrize("shape", [(300, 280, 260), (129, 257, 131)])
 def test_ragged_alpha_beta(member, shape):
