@@ -275,12 +275,12 @@ int plan_member(int member, int64_t m, int64_t n, int64_t k, momms_plan* p) {
             break;
         }
         case MOMMS_C4A2C0: {
-            // m, n by a 4096 x 4096 C block (MALL) -> k by kc -> m by 32 (A
-            // block in LDS) -> n by 128 across workgroups.  One launch walks
-            // four chunks (kc3 = 4 kc) on its granules: with one chunk, a
-            // launch of a block holds two rounds of workgroups and its tail
-            // leaves the chip idle between launches; the data each chunk
-            // moves is the same.
+            // m, n by a 4096 x 4096 C block (MALL) -> k by kc3 = 4 kc -> k by
+            // kc -> m by 32 (A block in LDS) -> n by 128.  One launch walks
+            // four chunks: with one, a launch holds two rounds of workgroups
+            // and its tail idles the chip; with eight, its A and B panels (72
+            // MiB each) and the 128 MiB C block would overflow the 256 MiB
+            // MALL (four: 36 MiB each).  Each chunk moves the same data.
             p->kernel = 1;
             p->mt = kMCa;
             p->nt = kNTa;
