@@ -90,7 +90,10 @@ typedef struct momms_plan {
     int member;          /* enum momms_member, never MOMMS_AUTO here        */
     int kernel;          /* 0: register-resident C over a k range;
                             1: A block resident in LDS; 2: B block in LDS   */
-    int mt, nt, ks;      /* workgroup register tile and LDS k-slice         */
+    int mt, nt, ks;      /* workgroup C tile and LDS k-slice (kernel 1: mt
+                            is the A block's rows, 32 with two workgroups
+                            per CU, 64 with one for C3A2C0 on problems
+                            whose 64-row tiles fill the chip)               */
     int nj, mi;          /* n-tiles per LDS-resident A block (kernel 1);
                             m-tiles per LDS-resident B block (kernel 2)     */
     int group_m;         /* height (in tiles) of a grouped tile order       */
@@ -98,7 +101,9 @@ typedef struct momms_plan {
                             contiguous in the tile order                    */
     int pack;            /* streamed panel packed into the workspace        */
     int64_t kc;          /* k extent of the LDS-resident block              */
-    int64_t mc3, nc3, kc3;   /* level-3 (XCD L2) block                      */
+    int64_t mc3, nc3, kc3;   /* level-3 (XCD L2) block; for C4A2C0, kc3 is
+                                the host's k step (four kc chunks per
+                                launch)                                    */
     int64_t mc4, nc4;        /* level-4 (MALL) block                        */
     int64_t nc;              /* outermost n blocksize (Goto's n_c)          */
     int64_t k_range;     /* k extent one workgroup accumulates before it
