@@ -272,6 +272,13 @@ def test_c3a2c0_block_fits_l2():
     # 32 rows, two per CU; an XCD round of 64 is a 16 x 4 block, 512 x 512
     p = mm.member_plan("C3A2C0", 1024, 1024, 1024)
     assert (p["mt"], p["mc3"], p["nc3"], p["kc"], p["workgroups"]) == (32, 512, 512, 256, 256)
+    # at the switch: 16 x 16 tiles of 64 rows fill the 256 CUs; 16 x 15 do
+    # not, and their 32-row launch (at most twice the tiles) still fits the
+    # chip at once, two workgroups per CU
+    assert mm.member_plan("C3A2C0", 1024, 2048, 512)["mt"] == 64
+    for m, n in [(1024, 1920), (1000, 1920), (993, 1917), (64, 128 * 255)]:
+        p = mm.member_plan("C3A2C0", m, n, 512)
+        assert p["mt"] == 32 and p["workgroups"] <= 2 * 256, (m, n, p)
     for shape in [(8192, 8192, 8192), (16384, 16384, 256), (16384, 256, 16384), (1024, 1024, 1024),
                   (100, 3000, 500), (3000, 100, 500), (64, 128, 4096), (4096, 8192, 2048)]:
         p = mm.member_plan("C3A2C0", *shape)
